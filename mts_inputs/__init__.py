@@ -1,0 +1,215 @@
+"""Seeded synthetic problem instances for the multi-time-step PD/FE fracture solver.
+
+This module is shared by the oracle (test infrastructure) and the HIP library's
+callers.  It holds no arithmetic of the method itself: it only lays out node
+positions on a lattice, draws the seeded perturbation, and records the plain
+problem parameters (geometry, material, loads, step ratio, step count).  Every
+quantity the method derives from these (horizon, micromodulus, critical stretch,
+Arlequin weights, masses, neighbour lists, multipliers) is computed separately
+by each side.
+
+Instances stand in for the paper's plate workloads (Sec. 3.3 efficiency study and
+Sec. 4.1 crack branching: a 100 x 40 mm plate with an edge notch, PD placed
+around the crack, Q4 elements elsewhere, step ratios 2..20).  The paper uses no
+public dataset; all inputs here are synthetic.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Iterator, List, Optional
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+SEED_BASE = 240303605
+SERVING_SEED = 240303700
+
+
+# ---------------------------------------------------------------------------
+# SplitMix64 (Vigna, "Further scramblings of Marsaglia's xorshift generators",
+# the seeding generator of xoroshiro).  Written from its published definition.
+# ---------------------------------------------------------------------------
+class SplitMix64:
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Uniform double in [0, 1) with 53 random bits."""
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+
+def splitmix64_uniforms(seed: int, count: int) -> np.ndarray:
+    """`count` consecutive SplitMix64 uniforms, vectorised (same stream as the class)."""
+    golden = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        k = np.arange(1, count + 1, dtype=np.uint64)
+        z = np.uint64(seed & MASK64) + k * golden
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def lattice_positions(n, lo, dx: float, perturb: float = 0.0, seed: int = SEED_BASE) -> np.ndarray:
+    """Cell-centred lattice of n[0] x n[1] (x n[2]) nodes starting at `lo`.
+
+    Node id = (iz * ny + iy) * nx + ix.  Each coordinate gets (2u - 1) * perturb * dx
+    with u drawn from SplitMix64(seed) in node-id order, x then y (then z).
+    Returns an (N, dim) float64 array.
+    """
+    dim = len(n)
+    axes = [lo[a] + (np.arange(n[a], dtype=np.float64) + 0.5) * dx for a in range(dim)]
+    if dim == 2:
+        yy, xx = np.meshgrid(axes[1], axes[0], indexing="ij")
+        pos = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    else:
+        zz, yy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+        pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    pos = np.ascontiguousarray(pos)
+    if perturb > 0.0:
+        u = splitmix64_uniforms(seed, pos.size).reshape(pos.shape)
+        pos = pos + (2.0 * u - 1.0) * (perturb * dx)
+    return pos
+
+
+# ---------------------------------------------------------------------------
+# Instances
+# ---------------------------------------------------------------------------
+GLASS = dict(E=72e9, rho=2440.0, G0=3.8)
+
+
+def plate2d(nx: int, m: int, n_pd_steps: int, dt_pd: float, *, perturb: float = 0.0,
+            seed: int = SEED_BASE, precision: str = "fp64", traction: float = 1e6,
+            notch: Optional[float] = None, crack_y: Optional[float] = None,
+            mode: str = "coupled", breaking: bool = True, weight: str = "cubic",
+            kernel: str = "pmb", name: str = "plate2d") -> Dict:
+    """2D plane-stress plate 0.1 x 0.04 m with an edge notch along y = crack_y.
+
+    PD lattice nx x (0.4 nx) nodes of spacing dx = 0.05 / nx covering the strip
+    x in [a - 0.01, a + 0.04], y in [0.01, 0.03] (for the default notch a = 0.05),
+    Q4 elements of size 4 dx over the whole plate, overlap 3 dx, traction on the
+    edges y = 0 and y = 0.04.
+    """
+    assert nx % 2 == 0 and (2 * nx) % 5 == 0
+    ny = (2 * nx) // 5
+    dx = 0.05 / nx
+    L, Hh = 0.1, 0.04
+    a = 0.05 if notch is None else notch
+    yc = 0.02 if crack_y is None else crack_y
+    x0 = a - 0.2 * 0.05
+    y0 = yc - 0.5 * ny * dx
+    fe_h = 4.0 * dx
+    pd_lo = (x0, y0)
+    pd_hi = (x0 + nx * dx, y0 + ny * dx)
+    inst = dict(
+        name=name, dim=2, mode=mode, precision=precision, breaking=breaking,
+        pd_n=(nx, ny, 1), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.015,
+        perturb=perturb, seed=seed,
+        dom_lo=(0.0, 0.0), dom_hi=(L, Hh),
+        fe_n=(int(round(L / fe_h)), int(round(Hh / fe_h)), 1), fe_h=fe_h,
+        overlap=3.0 * dx, weight=weight,
+        cracks=[(yc, 0.0, a)],
+        thickness=1.0, kernel=kernel, l_over_delta=0.1,
+        traction=traction, vel_bc=0.0,
+        m=m, dt_pd=dt_pd, n_macro=n_pd_steps // m, **GLASS,
+    )
+    if mode == "pure_pd":
+        inst.update(dom_lo=pd_lo, dom_hi=pd_hi, fe_n=(0, 0, 0))
+    inst["pos"] = lattice_positions((nx, ny), pd_lo, dx, perturb, seed)
+    return inst
+
+
+def block3d(nx: int, ny: int, nz: int, m: int, n_pd_steps: int, dt_pd: float, *,
+            perturb: float = 0.0, seed: int = SEED_BASE, precision: str = "fp64",
+            vel_bc: float = 20.0, mode: str = "coupled", breaking: bool = True,
+            name: str = "block3d") -> Dict:
+    """3D PD block nx x ny x nz (dx = 1 mm scale: dx = 0.02 / nz) spanning the full
+    width and thickness of a hex8 bar 2 nx dx long, centred along x; prescribed
+    velocity vel_bc on the bar face x = 0."""
+    dx = 0.02 / nz
+    Lx, Ly, Lz = 2.0 * nx * dx, ny * dx, nz * dx
+    pd_lo = (0.5 * nx * dx, 0.0, 0.0)
+    pd_hi = (1.5 * nx * dx, Ly, Lz)
+    fe_h = 2.0 * dx
+    inst = dict(
+        name=name, dim=3, mode=mode, precision=precision, breaking=breaking,
+        pd_n=(nx, ny, nz), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.015,
+        perturb=perturb, seed=seed,
+        dom_lo=(0.0, 0.0, 0.0), dom_hi=(Lx, Ly, Lz),
+        fe_n=(int(round(Lx / fe_h)), int(round(Ly / fe_h)), int(round(Lz / fe_h))), fe_h=fe_h,
+        overlap=3.0 * dx, weight="cubic", cracks=[],
+        thickness=1.0, kernel="pmb", l_over_delta=1.0 / 16.0,
+        traction=0.0, vel_bc=vel_bc,
+        m=m, dt_pd=dt_pd, n_macro=n_pd_steps // m, **GLASS,
+    )
+    if mode == "pure_pd":
+        inst.update(dom_lo=pd_lo, dom_hi=pd_hi, fe_n=(0, 0, 0))
+    inst["pos"] = lattice_positions((nx, ny, nz), pd_lo, dx, perturb, seed)
+    return inst
+
+
+# Step sizes (s): at most 0.8 of the smaller of the PD stability bound and the
+# explicit-FE bound divided by m, and below the Gershgorin FE bound / m.  The
+# bounds scale with dx for these layouts; the test suite re-derives them.
+DT = {
+    "C1": 1.0e-7,
+    "C2": 6.0e-9,
+    "C3": 2.4e-9,
+    "C4": 2.5e-8,
+}
+
+
+def config(k: int, **over) -> Dict:
+    """The five workloads: 0 small 2D, 1 plain FP64 2D, 2 mixed 2D, 3 mixed 3D."""
+    if k == 0:
+        kw = dict(nx=50, m=4, n_pd_steps=200, dt_pd=DT["C1"], perturb=0.0, seed=SEED_BASE,
+                  precision="fp64", name="C1 plate 50x20 m=4 fp64")
+        kw.update(over)
+        return plate2d(**kw)
+    if k == 1:
+        kw = dict(nx=400, m=10, n_pd_steps=4000, dt_pd=DT["C2"], perturb=1e-6,
+                  seed=SEED_BASE + 1, precision="fp64", name="C2 plate 400x160 m=10 fp64")
+        kw.update(over)
+        return plate2d(**kw)
+    if k == 2:
+        kw = dict(nx=1000, m=10, n_pd_steps=5000, dt_pd=DT["C3"], perturb=1e-6,
+                  seed=SEED_BASE + 2, precision="mixed", name="C3 plate 1000x400 m=10 mixed")
+        kw.update(over)
+        return plate2d(**kw)
+    if k == 3:
+        kw = dict(nx=100, ny=100, nz=20, m=8, n_pd_steps=2000, dt_pd=DT["C4"], perturb=1e-6,
+                  seed=SEED_BASE + 3, precision="mixed", name="C4 block 100x100x20 m=8 mixed")
+        kw.update(over)
+        return block3d(**kw)
+    raise ValueError(k)
+
+
+def serving_stream(n_requests: int = 256, rate: float = 20.0, seed: int = SERVING_SEED,
+                   t_end: float = 1e-5, nx_choices=None) -> List[Dict]:
+    """Request stream: Poisson arrivals, plate sizes 100x40 .. 800x320, notch length
+    and position in [0.2, 0.6] of the plate's width/height, traction 0.5..2 MPa,
+    step ratio in {4, 8, 10}.  Draw order per request: inter-arrival, nx, notch
+    length, notch height, traction, m, perturbation seed."""
+    rng = SplitMix64(seed)
+    if nx_choices is None:
+        nx_choices = list(range(100, 801, 20))
+    t = 0.0
+    out = []
+    for r in range(n_requests):
+        t += -math.log(1.0 - rng.uniform()) / rate
+        nx = nx_choices[min(int(rng.uniform() * len(nx_choices)), len(nx_choices) - 1)]
+        a = (0.2 + 0.4 * rng.uniform()) * 0.1
+        yc = (0.2 + 0.4 * rng.uniform()) * 0.04
+        T = (0.5 + 1.5 * rng.uniform()) * 1e6
+        m = (4, 8, 10)[min(int(rng.uniform() * 3), 2)]
+        pseed = rng.next_u64()
+        out.append(dict(arrival=t, nx=nx, notch=a, crack_y=yc, traction=T, m=m, seed=pseed,
+                        t_end=t_end))
+    return out

@@ -1,0 +1,630 @@
+"""Pins of the oracle against what the paper and the mathematics fix (CPU only).
+
+Each test checks the oracle against something other than itself: a closed form,
+an invariant, an independent algorithm, or a special case that reduces to a
+textbook result.  None of them calls the HIP library.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import mts_inputs as mi
+from oracle import Oracle, exp_moment, neighbors_brute, neighbors_grid
+import oracle.oracle as O
+
+PI = math.pi
+
+
+# ---------------------------------------------------------------------------
+# Input generator
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_value():
+    # First output of SplitMix64 seeded with 0, as published with the generator.
+    assert mi.SplitMix64(0).next_u64() == 0xE220A8397B1DCDAF
+    g = mi.SplitMix64(12345)
+    ref = np.array([g.uniform() for _ in range(1000)])
+    assert np.array_equal(ref, mi.splitmix64_uniforms(12345, 1000))
+
+
+def test_perturbation_bounds():
+    p0 = mi.lattice_positions((40, 16), (0.0, 0.0), 1e-3)
+    p1 = mi.lattice_positions((40, 16), (0.0, 0.0), 1e-3, perturb=1e-6, seed=7)
+    d = np.abs(p1 - p0).max()
+    assert 0 < d <= 1e-9 * 1.0000001
+
+
+# ---------------------------------------------------------------------------
+# Neighbourhoods (Sec. 2.1: |x' - x| <= delta)
+# ---------------------------------------------------------------------------
+def _stencil(dim, hf):
+    r = int(math.floor(hf))
+    offs = []
+    rng = range(-r, r + 1)
+    if dim == 2:
+        for b in rng:
+            for a in rng:
+                if (a, b) != (0, 0) and a * a + b * b <= hf * hf:
+                    offs.append((a, b, 0))
+    else:
+        for c in rng:
+            for b in rng:
+                for a in rng:
+                    if (a, b, c) != (0, 0, 0) and a * a + b * b + c * c <= hf * hf:
+                        offs.append((a, b, c))
+    return offs
+
+
+def lattice_bond_count(n, hf):
+    """Directed bonds of a rectangular lattice: sum over offsets of the number of
+    node pairs at that offset -- a closed form independent of any search."""
+    dim = len(n)
+    tot = 0
+    for o in _stencil(dim, hf):
+        t = 1
+        for a in range(dim):
+            t *= max(n[a] - abs(o[a]), 0)
+        tot += t
+    return tot
+
+
+def test_interior_family_sizes():
+    assert len(_stencil(2, 3.015)) == 28
+    assert len(_stencil(3, 3.015)) == 122
+
+
+@pytest.mark.parametrize("n,total", [((50, 20), 25516), ((400, 160), 1771876),
+                                     ((1000, 400), 11149636), ((100, 100, 20), 22472408)])
+def test_lattice_bond_totals(n, total):
+    assert lattice_bond_count(n, 3.015) == total
+
+
+@pytest.mark.parametrize("dim,npts,seed", [(2, 600, 1), (3, 700, 2)])
+def test_neighbors_grid_equals_bruteforce_random(dim, npts, seed):
+    rng = np.random.default_rng(seed)
+    pos = rng.random((npts, dim))
+    delta = 0.11 if dim == 2 else 0.2
+    rp1, c1 = neighbors_brute(pos, delta)
+    rp2, c2 = neighbors_grid(pos, delta)
+    assert np.array_equal(rp1, rp2) and np.array_equal(c1, c2)
+    # direct definition, pair by pair
+    d2 = ((pos[:, None, :] - pos[None, :, :]) ** 2).sum(-1)
+    for i in range(0, npts, 37):
+        want = [k for k in range(npts) if k != i and d2[i, k] <= delta * delta * (1 - 1e-12)]
+        got = list(c1[rp1[i]:rp1[i + 1]])
+        assert set(want) <= set(got)
+
+
+@pytest.mark.parametrize("n", [(40, 16), (12, 12, 12)])
+def test_neighbors_perturbed_lattice(n):
+    dx = 1e-3
+    pos = mi.lattice_positions(n, (0.0,) * len(n), dx, perturb=1e-6, seed=99)
+    rp1, c1 = neighbors_brute(pos, 3.015 * dx)
+    rp2, c2 = neighbors_grid(pos, 3.015 * dx)
+    assert np.array_equal(rp1, rp2) and np.array_equal(c1, c2)
+    assert c1.size == lattice_bond_count(n, 3.015)
+    for i in range(len(pos)):
+        row = c1[rp1[i]:rp1[i + 1]]
+        assert np.all(np.diff(row) > 0)
+
+
+def test_config_bond_counts(oracle_mod):
+    o = Oracle(mi.config(0))
+    assert o.info()["nnz"] == 25516
+
+
+# ---------------------------------------------------------------------------
+# Calibration (reading R2; Sec. 3.2 and Sec. 3.3 micromodulus formulas)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,l", [(5, 0.1), (6, 1 / 16), (7, 0.3), (5, 2.0)])
+def test_exp_moment_closed_form(n, l):
+    delta = 1.7
+    ref, _ = integrate.quad(lambda r: r ** n * math.exp(-r / l), 0.0, delta, epsabs=0, epsrel=1e-13)
+    assert exp_moment(n, delta, l) == pytest.approx(ref, rel=1e-11)
+
+
+def _small(kernel="pmb", dim=2, **kw):
+    if dim == 2:
+        inst = mi.plate2d(20, 2, 4, 1e-8, kernel=kernel, mode="pure_pd", **kw)
+        inst["cracks"] = []
+    else:
+        inst = mi.block3d(8, 8, 8, 2, 4, 1e-8, mode="pure_pd", **kw)
+        inst["kernel"] = kernel
+    return inst
+
+
+@pytest.mark.parametrize("kernel", ["pmb", "exp"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_micromodulus_calibration(kernel, dim):
+    inst = _small(kernel, dim)
+    o = Oracle(inst)
+    info = o.info()
+    d = info["delta"]
+    c0 = info["c0"]
+    l = d * inst["l_over_delta"]
+    c = (lambda r: c0 / r ** 3) if kernel == "pmb" else (lambda r: c0 * math.exp(-r / l))
+    E = inst["E"]
+    if dim == 2:
+        val, _ = integrate.quad(lambda r: c(r) * r ** 5, 0.0, d, epsrel=1e-13)
+        assert inst["thickness"] * val == pytest.approx(3 * E / PI, rel=1e-10)
+    else:
+        val, _ = integrate.quad(lambda r: c(r) * r ** 6, 0.0, d, epsrel=1e-13)
+        assert val == pytest.approx(3 * E / PI, rel=1e-10)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_critical_stretch_from_fracture_energy(dim):
+    """G0 = energy of all bonds crossing a unit crack area at stretch s_crit,
+    integrated in its original (unsimplified) form."""
+    inst = _small("pmb", dim)
+    o = Oracle(inst)
+    info = o.info()
+    d, c0, s = info["delta"], info["c0"], info["s_crit"]
+    w = lambda r: 0.5 * (c0 / r ** 3) * (s * r * r) ** 2      # pair energy at pure stretch s
+    if dim == 2:
+        inner = lambda z: integrate.quad(lambda r: 2.0 * math.acos(z / r) * w(r) * r, z, d, epsrel=1e-12)[0]
+        G, _ = integrate.quad(inner, 0.0, d, epsrel=1e-11)
+        G *= inst["thickness"]
+    else:
+        inner = lambda z: integrate.quad(lambda r: 2.0 * PI * (1.0 - z / r) * w(r) * r * r, z, d, epsrel=1e-12)[0]
+        G, _ = integrate.quad(inner, 0.0, d, epsrel=1e-11)
+    assert G == pytest.approx(inst["G0"], rel=1e-8)
+    if dim == 2:   # closed form for the PMB-equivalent kernel
+        assert s == pytest.approx(math.sqrt(4 * PI * inst["G0"] / (9 * inst["E"] * d)), rel=1e-13)
+
+
+def test_config_critical_stretch_values():
+    # closed-form values for the 2D plates (dx = 1, 0.125, 0.05 mm)
+    for k, want in [(0, 1.5634e-4)]:
+        assert Oracle(mi.config(k)).info()["s_crit"] == pytest.approx(want, rel=1e-4)
+    E, G0 = 72e9, 3.8
+    for dx, want in [(0.125e-3, 4.4219e-4), (0.05e-3, 6.9917e-4)]:
+        assert math.sqrt(4 * PI * G0 / (9 * E * 3.015 * dx)) == pytest.approx(want, rel=1e-4)
+
+
+def _uniform_strain_energy_closed_form(n, dx, hf, c, eps, V):
+    tot = 0.0
+    for o in _stencil(len(n), hf):
+        mult = 1
+        for a in range(len(n)):
+            mult *= max(n[a] - abs(o[a]), 0)
+        xi = np.array(o[:len(n)], float) * dx
+        r = math.sqrt((xi ** 2).sum())
+        tot += mult * 0.25 * c(r) * (eps * xi[0] * xi[0]) ** 2 * V * V
+    return tot
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pd_energy_uniform_strain_lattice_sum(dim):
+    inst = _small("pmb", dim)
+    o = Oracle(inst)
+    info = o.info()
+    eps = 1e-4
+    pos = inst["pos"]
+    u = np.zeros_like(pos)
+    u[:, 0] = eps * pos[:, 0]
+    c0 = info["c0"]
+    n = inst["pd_n"][:dim]
+    ref = _uniform_strain_energy_closed_form(n, inst["dx"], 3.015, lambda r: c0 / r ** 3, eps, info["volume"])
+    assert o.pd_energy(u) == pytest.approx(ref, rel=1e-11)
+
+
+def test_lattice_energy_ratio():
+    """Interior energy density under uniaxial strain vs the continuum value
+    (9/16) E eps^2 (plane stress, nu = 1/3): the discrete modulus is 3.7 % stiff at
+    delta = 3.015 dx and tends to 1 as delta/dx grows."""
+    def ratio(hf):
+        dx, E, h = 1.0, 1.0, 1.0
+        d = hf * dx
+        c0 = 9 * E / (PI * h * d ** 3)
+        W = sum(0.25 * c0 / (math.hypot(a, b) * dx) ** 3 * (a * a * dx * dx) ** 2 * dx * dx * h
+                for (a, b, _) in _stencil(2, hf))
+        return W / (9.0 / 16.0 * E)
+    assert ratio(3.015) == pytest.approx(1.0371335599, rel=1e-9)
+    assert abs(ratio(20.015) - 1) < abs(ratio(3.015) - 1) / 5
+
+
+# ---------------------------------------------------------------------------
+# Force invariants (Eq. 2)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def plate_small():
+    inst = mi.plate2d(30, 2, 4, 1e-8, perturb=1e-6, seed=5, name="small")
+    return inst, Oracle(inst)
+
+
+def test_force_sum_zero_and_translation(plate_small):
+    inst, o = plate_small
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(inst["pos"].shape) * 1e-6
+    f = o.pd_force(u)
+    scale = np.abs(f).max() * f.shape[0]
+    assert np.abs(f.sum(0)).max() <= 1e-13 * scale
+    ut = np.zeros_like(u)
+    ut[:, 0] = 3e-5
+    ut[:, 1] = -1e-5
+    assert np.all(o.pd_force(ut) == 0.0)
+
+
+def test_force_infinitesimal_rotation(plate_small):
+    inst, o = plate_small
+    th = 1e-7
+    pos = inst["pos"]
+    u = np.stack([-th * pos[:, 1], th * pos[:, 0]], 1)
+    f_rot = np.abs(o.pd_force(u)).max()
+    rng = np.random.default_rng(1)
+    f_rand = np.abs(o.pd_force(rng.standard_normal(u.shape) * np.abs(u).max())).max()
+    assert f_rot <= 1e-9 * f_rand
+
+
+def test_force_uniform_strain_interior_zero():
+    inst = mi.plate2d(30, 2, 4, 1e-8, mode="pure_pd")
+    inst["cracks"] = []
+    o = Oracle(inst)
+    pos = inst["pos"]
+    u = np.stack([1e-4 * pos[:, 0], -3e-5 * pos[:, 1]], 1)
+    f = o.pd_force(u)
+    lo, hi, d = np.array(inst["pd_lo"]), np.array(inst["pd_hi"]), 3.1 * inst["dx"]
+    inner = np.all((pos > lo + d) & (pos < hi - d), axis=1)
+    fb = np.abs(f[~inner]).max()
+    assert inner.sum() > 50
+    assert np.abs(f[inner]).max() <= 1e-10 * fb
+
+
+def test_precrack_cuts_and_symmetry():
+    inst = mi.config(0)
+    o = Oracle(inst)
+    rp, col, mu = o.bonds()
+    n = len(rp) - 1
+    pos = inst["pos"]
+    yc, x0, x1 = inst["cracks"][0]
+    lookup = {}
+    for i in range(n):
+        for t in range(rp[i], rp[i + 1]):
+            lookup[(i, col[t])] = mu[t]
+    for (i, k), v in lookup.items():
+        assert lookup[(k, i)] == v
+        yi, yk = pos[i, 1], pos[k, 1]
+        crosses = (yi - yc) * (yk - yc) < 0
+        if not crosses:
+            assert v == 1
+    # node just above the crack line, far from the tip and the strip edge:
+    # its 11 neighbours below the line are cut -> damage 11/28
+    phi = o.get(O.DAMAGE)
+    nx = inst["pd_n"][0]
+    ny = inst["pd_n"][1]
+    row = ny // 2
+    i = row * nx + 5
+    assert pos[i, 1] > yc and pos[i, 0] < x1
+    assert phi[i] == pytest.approx(11 / 28, abs=1e-15)
+    # past the tip nothing is cut
+    i_far = row * nx + nx - 5
+    assert phi[i_far] == 0.0
+
+
+def test_precrack_tip_inclusive():
+    # four nodes: bond crossing the crack line exactly at the tip is cut
+    pos = np.array([[0.0, -0.5], [1.0, 0.5], [1.0, -0.5], [2.0, 0.5]])
+    inst = dict(dim=2, mode="pure_pd", pos=pos, dx=1.0, horizon_factor=1.5,
+                pd_lo=(-0.5, -1.0), pd_hi=(2.5, 1.0), dom_lo=(-0.5, -1.0), dom_hi=(2.5, 1.0),
+                cracks=[(0.0, -10.0, 0.5)], m=1, dt_pd=1e-6, E=1.0, rho=1.0, G0=1.0,
+                thickness=1.0, traction=0.0)
+    o = Oracle(inst)
+    rp, col, mu = o.bonds()
+    bonds = {(i, int(col[t])): int(mu[t]) for i in range(4) for t in range(rp[i], rp[i + 1])}
+    assert bonds[(0, 1)] == 0        # crosses at x* = 0.5 == tip: cut
+    assert bonds[(1, 2)] == 1        # vertical at x = 1: past the tip
+    assert bonds[(2, 3)] == 1
+    assert bonds[(0, 2)] == 1        # parallel to the crack
+
+
+# ---------------------------------------------------------------------------
+# Time integration (Sec. 2.4, velocity Verlet = Newmark gamma 1/2, beta 0)
+# ---------------------------------------------------------------------------
+def test_two_node_verlet_closed_form():
+    L = 1e-3
+    pos = np.array([[0.0, 0.0], [L, 0.0]])
+    dt = 1e-7
+    inst = dict(dim=2, mode="pure_pd", pos=pos, dx=1e-3, horizon_factor=1.2,
+                pd_lo=(-5e-4, -5e-4), pd_hi=(1.5e-3, 5e-4), dom_lo=(-5e-4, -5e-4),
+                dom_hi=(1.5e-3, 5e-4), cracks=[], m=1, dt_pd=dt, E=72e9, rho=2440.0,
+                G0=3.8, thickness=1.0, traction=0.0, breaking=False)
+    o = Oracle(inst)
+    info = o.info()
+    V, c0 = info["volume"], info["c0"]
+    k = c0 / L ** 3 * L * L * V * V          # force per unit relative displacement
+    mnode = inst["rho"] * V
+    w2 = 2 * k / mnode
+    q0 = 1e-7
+    u = np.array([[-q0 / 2, 0.0], [q0 / 2, 0.0]])
+    o.set(O.PD_U, u)
+    o.set(O.PD_A, o.pd_force(u) / mnode)
+    th = math.acos(1 - w2 * dt * dt / 2)
+    for n in range(1, 41):
+        o.advance(1)
+        q = np.diff(o.get(O.PD_U)[:, 0])[0]
+        assert q == pytest.approx(q0 * math.cos(n * th), rel=1e-9, abs=1e-12 * q0)
+
+
+def _energy_drift(dt, steps):
+    inst = mi.plate2d(20, 1, steps, dt, mode="pure_pd", breaking=False)
+    o = Oracle(inst)
+    errs = []
+    for _ in range(steps):
+        o.advance(1)
+        i = o.info()
+        errs.append(i["e_kin"] + i["e_pd"] - i["w_ext"])
+    scale = o.info()["w_ext"]
+    return np.abs(errs).max() / scale
+
+
+def test_energy_conservation_no_breaking():
+    e1 = _energy_drift(2e-7, 200)
+    e2 = _energy_drift(1e-7, 400)
+    assert e1 < 2e-2
+    assert 3.0 < e1 / e2 < 5.0
+
+
+# ---------------------------------------------------------------------------
+# Finite elements (Eq. 24-27, Eq. 34)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def coupled_small():
+    inst = mi.plate2d(40, 4, 8, 2e-8, name="coupled small")
+    return inst, Oracle(inst)
+
+
+def test_q4_element_stiffness_closed_form(coupled_small):
+    inst, o = coupled_small
+    info = o.info()
+    nfe = info["n_fe_nodes"]
+    E, nu, t = inst["E"], 1 / 3, inst["thickness"]
+    u = np.zeros((nfe, 2))
+    u[0, 0] = 1.0                    # node 0 belongs to corner element 0 only (alpha = 1)
+    f = o.fe_force(u)
+    assert f[0, 0] == pytest.approx(E * t / (1 - nu * nu) * (3 - nu) / 6, rel=1e-12)
+    assert f[0, 1] == pytest.approx(E * t / (1 - nu * nu) * (1 + nu) / 8, rel=1e-12)
+
+
+def test_fe_patch_and_rigid(coupled_small):
+    inst, o = coupled_small
+    X = o.get(O.FE_X)
+    mF = o.get(O.FE_MASS)
+    act = mF > 0
+    u = np.stack([2e-4 * X[:, 0] + 1e-4 * X[:, 1], -5e-5 * X[:, 1]], 1)
+    f = o.fe_force(u)
+    h = inst["fe_h"]
+    # nodes whose elements are all unweighted and away from the edges and the PD box
+    lo, hi = np.array(inst["pd_lo"]) - 2 * h, np.array(inst["pd_hi"]) + 2 * h
+    far = act & (X[:, 0] > h / 2) & (X[:, 0] < 0.1 - h / 2) & (X[:, 1] > h / 2) & (X[:, 1] < 0.04 - h / 2) \
+        & ~np.all((X > lo) & (X < hi), 1) & (np.abs(X[:, 1] - 0.02) > h / 2)
+    assert far.sum() > 5
+    assert np.abs(f[far]).max() <= 1e-9 * np.abs(f[act]).max()
+    th = 1e-6
+    ur = np.stack([-th * X[:, 1], th * X[:, 0]], 1) + 1e-5
+    assert np.abs(o.fe_force(ur)).max() <= 1e-8 * np.abs(f[act]).max() * th / 2e-4
+    # unweighted interior node mass: rho h^2 t
+    assert np.isclose(mF[far], inst["rho"] * h * h * inst["thickness"], rtol=1e-12).all()
+
+
+def test_coupling_interpolation_rows(coupled_small):
+    inst, o = coupled_small
+    G = o.get(O.GF).reshape(-1, 4)
+    assert np.allclose(G.sum(1), 1.0, atol=1e-14)
+    assert np.all(G > 0)
+
+
+# ---------------------------------------------------------------------------
+# Coupling (Sec. 2.5, Algorithm 1)
+# ---------------------------------------------------------------------------
+def test_velocity_continuity_and_momentum():
+    inst = mi.config(0)
+    o = Oracle(inst)
+    mP, mF = o.get(O.PD_MASS), o.get(O.FE_MASS)
+    for _ in range(inst["n_macro"]):
+        o.advance(1)
+        vP, vF = o.get(O.PD_V), o.get(O.FE_V)
+        r = o.constraint_residual()
+        assert np.abs(r).max() <= 1e-12 * np.abs(vP).max()
+        mom = (mP[:, None] * vP).sum(0) + (mF[:, None] * vF).sum(0)
+        scale = (mP[:, None] * np.abs(vP)).sum(0) + (mF[:, None] * np.abs(vF)).sum(0)
+        assert np.all(np.abs(mom) <= 1e-12 * scale.max())
+    assert o.info()["n_broken"] > 0
+
+
+def _dense_gf(o, inst):
+    info = o.info()
+    nen = 2 ** inst["dim"]
+    W = o.get(O.GF).reshape(-1, nen)
+    nodes = o.get(O.GF_NODES).reshape(-1, nen).astype(int)
+    GF = np.zeros((W.shape[0], info["n_fe_nodes"]))
+    for q in range(W.shape[0]):
+        for a in range(nen):
+            GF[q, nodes[q, a]] += W[q, a]
+    return GF
+
+
+def test_coupling_interpolation_reproduces_position(coupled_small):
+    inst, o = coupled_small
+    GF = _dense_gf(o, inst)
+    X = o.get(O.FE_X)
+    cn = o.get(O.CONSTRAINT_NODES).astype(int)
+    assert np.allclose(GF @ X, inst["pos"][cn], rtol=0, atol=1e-15)
+
+
+def test_m1_reduces_to_single_rate_schur():
+    """At m = 1 the multiplier system is the single-rate Schur complement
+    1/2 dt (G_F M_F^-1 G_F^T + G_P M_P^-1 G_P^T) (Sec. 2.5, m = 1 remark)."""
+    inst = mi.plate2d(20, 1, 4, 4e-8, name="m1")
+    o = Oracle(inst)
+    H = o.get(O.H)
+    cn = o.get(O.CONSTRAINT_NODES).astype(int)
+    mP, mF = o.get(O.PD_MASS), o.get(O.FE_MASS)
+    GF = _dense_gf(o, inst)
+    dt = o.info()["dt_pd"]
+    act = mF > 0
+    S = 0.5 * dt * (GF[:, act] / mF[act]) @ GF[:, act].T + np.diag(0.5 * dt / mP[cn])
+    Hs = np.kron(S, np.eye(2))
+    assert np.allclose(H, Hs, rtol=0, atol=1e-13 * np.abs(Hs).max())
+
+
+def _probe(fn, n):
+    K = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        K[:, c] = -fn(e)
+    return K
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_split_equals_monolithic(m):
+    """The free/link split with unit-load responses solves the coupled system of
+    Eq. 43 exactly (Sec. 2.5): compare one macro step with a dense solve of the
+    monolithic system (Eq. 33 per substep, Newmark rows, lambda interpolated
+    linearly between lambda_0 and lambda_m, velocity constraint at t_m)."""
+    inst = mi.plate2d(20, m, 2 * m, 3e-8, breaking=False, name="mono")
+    o = Oracle(inst)
+    d = 2
+    info = o.info()
+    nP = info["n_pd"] * d
+    nF = info["n_fe_nodes"] * d
+    cn = o.get(O.CONSTRAINT_NODES).astype(int)
+    nl = len(cn) * d
+    mP, mF = o.get(O.PD_MASS), o.get(O.FE_MASS)
+    act = np.repeat(mF > 0, d)
+    KP = _probe(lambda e: o.pd_force(e.reshape(-1, d)).ravel(), nP)
+    KF = -_probe(lambda e: o.fe_force(e.reshape(-1, d)).ravel(), nF)   # fe_force returns +K_F u
+    GF = np.kron(_dense_gf(o, inst), np.eye(d))
+    GP = np.zeros((nl, nP))
+    for q, i in enumerate(cn):
+        for a in range(d):
+            GP[q * d + a, i * d + a] = 1.0
+    PF = o.get(O.FE_P).ravel()
+    PP = o.get(O.PD_P).ravel()
+    MP = np.repeat(mP, d)
+    MF = np.repeat(mF, d)
+    # advance one macro step so the initial state is non-trivial
+    o.advance(1)
+    uF0, vF0, aF0 = (o.get(k).ravel() for k in (O.FE_U, O.FE_V, O.FE_A))
+    uP0, vP0, aP0 = (o.get(k).ravel() for k in (O.PD_U, O.PD_V, O.PD_A))
+    lam0 = o.get(O.LAMBDA).ravel()
+    dtP = info["dt_pd"]
+    dtF = m * dtP
+    # unknown layout: [aF vF uF | (aP vP uP)_j, j=1..m | lam]
+    iF = 0
+    iP = lambda j: 3 * nF + (j - 1) * 3 * nP
+    iL = 3 * nF + 3 * m * nP
+    n = iL + nl
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    r = 0
+    # FE rows (Eq. 39, gamma = 1/2, beta = 0); inactive FE dofs are held at zero
+    for k in range(nF):
+        if act[k]:
+            A[r, iF + k] = MF[k]
+            A[r, iF + 2 * nF:iF + 3 * nF] += KF[k]
+            A[r, iL:iL + nl] = GF[:, k]
+            b[r] = PF[k]
+        else:
+            A[r, iF + k] = 1.0
+        r += 1
+    for k in range(nF):
+        A[r, iF + nF + k] = 1.0
+        A[r, iF + k] = -0.5 * dtF
+        b[r] = vF0[k] + 0.5 * dtF * aF0[k]
+        r += 1
+    for k in range(nF):
+        A[r, iF + 2 * nF + k] = 1.0
+        b[r] = uF0[k] + dtF * vF0[k] + 0.5 * dtF * dtF * aF0[k]
+        r += 1
+    # PD rows, j = 1..m (Eq. 40), lambda_j = (1 - j/m) lambda_0 + (j/m) lambda_m
+    for j in range(1, m + 1):
+        p0 = iP(j)
+        for k in range(nP):
+            A[r, p0 + k] = MP[k]
+            A[r, p0 + 2 * nP:p0 + 3 * nP] += KP[k]
+            A[r, iL:iL + nl] = -(j / m) * GP[:, k]
+            b[r] = PP[k] + (1 - j / m) * (GP[:, k] @ lam0)
+            r += 1
+        for k in range(nP):
+            A[r, p0 + nP + k] = 1.0
+            A[r, p0 + k] = -0.5 * dtP
+            if j == 1:
+                b[r] = vP0[k] + 0.5 * dtP * aP0[k]
+            else:
+                q0 = iP(j - 1)
+                A[r, q0 + nP + k] = -1.0
+                A[r, q0 + k] = -0.5 * dtP
+            r += 1
+        for k in range(nP):
+            A[r, p0 + 2 * nP + k] = 1.0
+            if j == 1:
+                b[r] = uP0[k] + dtP * vP0[k] + 0.5 * dtP * dtP * aP0[k]
+            else:
+                q0 = iP(j - 1)
+                A[r, q0 + 2 * nP + k] = -1.0
+                A[r, q0 + nP + k] = -dtP
+                A[r, q0 + k] = -0.5 * dtP * dtP
+            r += 1
+    # velocity continuity at t_m (Eq. 41)
+    A[r:r + nl, iF + nF:iF + 2 * nF] = GF
+    A[r:r + nl, iP(m) + nP:iP(m) + 2 * nP] = -GP
+    r += nl
+    assert r == n
+    x = np.linalg.solve(A, b)
+    o.advance(1)
+    got = {"aF": o.get(O.FE_A).ravel(), "vF": o.get(O.FE_V).ravel(), "uF": o.get(O.FE_U).ravel(),
+           "aP": o.get(O.PD_A).ravel(), "vP": o.get(O.PD_V).ravel(), "uP": o.get(O.PD_U).ravel(),
+           "lam": o.get(O.LAMBDA).ravel()}
+    want = {"aF": x[0:nF], "vF": x[nF:2 * nF], "uF": x[2 * nF:3 * nF],
+            "aP": x[iP(m):iP(m) + nP], "vP": x[iP(m) + nP:iP(m) + 2 * nP],
+            "uP": x[iP(m) + 2 * nP:iP(m) + 3 * nP], "lam": x[iL:]}
+    for key in want:
+        w, g = want[key], got[key]
+        assert np.abs(w - g).max() <= 1e-8 * np.abs(w).max(), key
+
+
+def test_uniform_velocity_patch():
+    """A uniform velocity with no load is an exact solution: lambda stays 0."""
+    inst = mi.plate2d(20, 4, 16, 4e-8, traction=0.0, name="patch")
+    o = Oracle(inst)
+    v0 = np.array([3.0, -2.0])
+    nP, nF = o.info()["n_pd"], o.info()["n_fe_nodes"]
+    mF = o.get(O.FE_MASS)
+    o.set(O.PD_V, np.tile(v0, (nP, 1)))
+    o.set(O.FE_V, np.where((mF > 0)[:, None], v0, 0.0))
+    o.advance(4)
+    assert np.abs(o.get(O.LAMBDA)).max() <= 1e-12 * np.abs(o.get(O.H)).max() ** -1 * 1e-6 or \
+        np.abs(o.get(O.LAMBDA)).max() < 1e-6
+    vP = o.get(O.PD_V)
+    assert np.allclose(vP, v0, rtol=1e-12, atol=0)
+    t = 4 * inst["m"] * inst["dt_pd"]
+    assert np.allclose(o.get(O.PD_U), v0 * t, rtol=1e-10)
+    assert np.abs(o.get(O.PD_A)).max() <= 1e-6
+
+
+def test_config_time_steps_stable():
+    """dt of each 2D/3D workload is below 0.8 of the PD bound and of the
+    explicit-FE bound / m (power iteration) and below the Gershgorin FE bound / m.
+    The bounds scale with dx, so they are evaluated on small instances of the
+    same layout."""
+    p2 = mi.plate2d(50, 4, 8, 1e-9)
+    o2 = Oracle(p2)
+    b2 = [o2.dt_bound(k) / p2["dx"] for k in range(3)]
+    for k in (0, 1, 2):
+        c = mi.config(k) if k == 0 else None
+        dx = 0.05 / (50, 400, 1000)[k]
+        m = (4, 10, 10)[k]
+        dt = mi.DT[("C1", "C2", "C3")[k]]
+        assert dt <= 0.8 * b2[0] * dx
+        assert dt <= 0.8 * b2[1] * dx / m
+        assert dt <= b2[2] * dx / m
+    p3 = mi.block3d(20, 20, 6, 8, 16, 1e-9)
+    o3 = Oracle(p3)
+    b3 = [o3.dt_bound(k) / p3["dx"] for k in range(3)]
+    dx, m, dt = 1e-3, 8, mi.DT["C4"]
+    assert dt <= 0.8 * b3[0] * dx * 0.97      # PD bound shrinks slightly with block size
+    assert dt <= 0.8 * b3[1] * dx / m
+    assert dt <= b3[2] * dx / m
