@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Benchmark of the MTS PD/FE solver on one MI355X.
+
+A step is one macro step of Algorithm 1 (one FE step at dt_FE, m fused PD
+substeps at dt_PD, the multiplier solve of Eq. 49 and the final update of
+Eq. 50, plus a rebuild of the unit-load responses when bonds inside their
+support break).  The default workload is the 400 x 160 FP64 plate with m = 10
+and 4000 PD steps (400 macro steps).  `value` counts directed bond slots
+evaluated per PD substep (the free problem) per second over the timed macro
+steps; setup (neighbour build, unit-load responses) is timed separately.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PD bond-updates/s (FP64 vs mixed) at stated error; served p50/p99 latency"
+HBM_PEAK = 8.0e12
+
+
+def bytes_per_launch(info, inst):
+    """Algorithmic HBM bytes of one fused PD substep launch (layout of this build):
+    per bond slot: neighbour index 4 B + bond-state bit 1/8 B;
+    per node: position (8 dim), u read (8 dim), v and a read+write (32 dim),
+    predicted u write (8 dim), alpha 8, mass 8, constraint index 4, damage 8/m.
+    Neighbour positions, displacements and weights are counted once per node."""
+    dim = info["dim"]
+    real = 8 if info["precision"] == 0 else 8
+    per_bond = 4.0 + 1.0 / 8.0
+    per_node = real * dim * (1 + 1 + 4 + 1) + 8 + 8 + 4 + 8.0 / inst["m"]
+    return info["nnz"] * per_bond + info["n_pd"] * per_node, per_bond, per_node
+
+
+def cpu_baseline(inst, seconds=15.0):
+    """The oracle as it stands, single thread, on the same seeded lattice in
+    pure-PD mode (the PD substep path: bond pass with breaking + Verlet)."""
+    import mts_inputs as mi
+    from oracle import Oracle
+    sample = dict(inst)
+    sample.update(mode="pure_pd", dom_lo=inst["pd_lo"], dom_hi=inst["pd_hi"], fe_n=(0, 0, 0), m=1)
+    o = Oracle(sample)
+    nnz = o.info()["nnz"]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        o.advance(5)
+        n += 5
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": n * nnz / dt, "unit": "bond-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} PD substeps of the same {inst['pd_n'][0]}x{inst['pd_n'][1]} seeded lattice, "
+                      f"pure-PD mode (bond pass with breaking + Verlet), plain C FP64, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed macro steps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import mts_inputs as mi
+    import paper_2403_03605_amd as mts
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    inst = mi.config(args.config)
+    K = args.steps if args.steps is not None else inst["n_macro"]
+    W = args.warmup
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+
+    if W > 0:  # warm-up on a throwaway solver of the same workload
+        with torch.cuda.stream(stream):
+            w = mts.Solver(inst, stream=sh)
+            w.advance(W)
+            w.sync()
+            w.close()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = mts.Solver(inst, stream=sh)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = s.query()
+    if not args.no_profile:
+        s.profile(True)
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.advance(K)
+    ev1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    info = s.query()
+    bond_updates = K * inst["m"] * info["nnz"]
+    value = bond_updates / elapsed
+
+    roof = None
+    if not args.no_profile:
+        n_launch, ms = s.kernel_time(mts.KT_PD_SUBSTEP)
+        avg_s = ms / 1e3 / max(n_launch, 1)
+        b, per_bond, per_node = bytes_per_launch(info, inst)
+        achieved = b / avg_s
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None,
+                "kernel": "k_pd_substep", "launches": n_launch, "avg_launch_us": avg_s * 1e6,
+                "algorithmic_bytes_per_launch": b, "bytes_per_bond": per_bond,
+                "bytes_per_node": per_node,
+                "kernel_bond_updates_per_s": info["nnz"] / avg_s}
+        other = {}
+        for name, k in (("link", mts.KT_LINK), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA)):
+            n_l, ms_l = s.kernel_time(k)
+            other[name] = {"launch_groups": n_l, "total_ms": ms_l}
+        roof["other_phases"] = other
+    s.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst, args.cpu_seconds)
+
+    dtype = "f64" if inst["precision"] == "fp64" else "f32 bond math / f64 integration"
+    line = {
+        "metric": METRIC, "value": value, "unit": "bond-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": inst["name"] + f", {K * inst['m']} PD steps ({K} macro steps)",
+                   "pd_nodes": info["n_pd"], "bonds": info["nnz"], "m": inst["m"],
+                   "fe_nodes": info["n_fe_nodes"], "constraints": info["n_constraints"],
+                   "dt_pd": inst["dt_pd"], "rebuilds": info["n_rebuilds"], "setup_s": setup_s,
+                   "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * mtspd -- multi-time-step coupling of bond-based peridynamics (PD) and finite
+ * elements (FE) in the Arlequin framework, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhong, Han, Du, Guo, "Multi-time-step coupling of peridynamics and
+ * classical continuum mechanics for dynamic brittle fracture", arXiv 2403.03605.
+ * The PD subdomain is advanced m times per FE step (Sec. 2.5, Algorithm 1):
+ * neighbour lists (Sec. 2.1), pairwise force (Eq. 2), stretch (Eq. 3),
+ * irreversible bond breaking (Eq. 4), damage (Eq. 5), velocity Verlet
+ * (Newmark gamma = 1/2, beta = 0, Eq. 38).  Around it: the explicit
+ * lumped-mass FE step (Eq. 24-34) and the velocity-continuity multipliers of
+ * the free/link split (Eq. 47-50).
+ *
+ * Conventions of this interface
+ *  - Plain C types only.  Host pointers are named `host_*`, device pointers
+ *    `dev_*`.  The library never keeps a caller pointer after a call returns.
+ *  - Every call returns an mts_status; on failure mts_last_error() (per host
+ *    thread) describes it.  No C++ exception or abort crosses the interface.
+ *  - Node order of every per-node array is the order of `pd_pos` as given.
+ *    Vectors are node-major: value (node i, component c) at [i * dim + c].
+ *  - All work is enqueued on the HIP stream given at create; calls that return
+ *    host data synchronise that stream.
+ *  - One solver must not be used from two host threads at once.
+ */
+#ifndef MTSPD_H
+#define MTSPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mts_status {
+  MTS_OK = 0,
+  MTS_EINVAL = 1,    /* invalid argument or problem description */
+  MTS_ENOMEM = 2,    /* device or host allocation failed */
+  MTS_EDEVICE = 3,   /* a HIP call failed */
+  MTS_EUNSTABLE = 4, /* non-finite state detected at a macro-step boundary (sticky) */
+  MTS_EAGAIN = 5,    /* pool: request does not fit now; resubmit later */
+  MTS_ETOOBIG = 6,   /* pool: request can never fit the budget */
+  MTS_ESTATE = 7     /* call not valid in the current state */
+} mts_status;
+
+enum { MTS_COUPLED = 0, MTS_PURE_PD = 1 };            /* mts_problem.mode */
+enum { MTS_FP64 = 0, MTS_MIXED = 1 };                 /* mts_problem.precision */
+enum { MTS_W_CUBIC = 0, MTS_W_LINEAR = 1, MTS_W_CONSTANT = 2 }; /* weight_kind, Sec. 3.2 */
+enum { MTS_K_PMB = 0, MTS_K_EXP = 1 };                /* micromodulus kernel */
+
+/* Problem description (deep-copied by mts_create).
+ * Geometry: PD nodes at `pd_pos` with nodal volume dx^dim (x thickness in 2D),
+ * horizon delta = horizon_factor * dx.  The body is the box [dom_lo, dom_hi];
+ * the FE mesh is fe_n[] square (cube) elements of side fe_h starting at dom_lo.
+ * The PD box [pd_lo, pd_hi] overlaps the FE mesh over a band of width `overlap`
+ * along its faces that lie inside the body (Arlequin weights, Eq. 17-18).
+ * Cracks (2D): horizontal segments y = cracks[c][0], cracks[c][1] <= x <= cracks[c][2].
+ * Loads: traction on the faces y = dom_lo[1] and y = dom_hi[1] (outward,
+ * magnitude `traction`, Pa), prescribed x-velocity `vel_bc` on the face
+ * x = dom_lo[0].  In MTS_PURE_PD mode the PD box is the body and the traction
+ * becomes a body force traction/delta on nodes within delta of its y faces.
+ * s_crit <= 0 derives the critical stretch from G0. */
+typedef struct mts_problem {
+  int32_t dim;          /* 2 (plane stress, nu = 1/3) or 3 (nu = 1/4) */
+  int32_t mode;         /* MTS_COUPLED or MTS_PURE_PD */
+  int32_t precision;    /* MTS_FP64 or MTS_MIXED */
+  int32_t breaking;     /* 1: critical-stretch breaking on */
+  int32_t weight_kind;  /* MTS_W_* */
+  int32_t kernel;       /* MTS_K_* */
+  int32_t m;            /* step ratio dt_FE / dt_PD, >= 1 */
+  int32_t n_cracks;     /* 0..8 */
+  int32_t fe_n[3];      /* elements per axis (ignored in MTS_PURE_PD) */
+  int64_t n_pd;         /* number of PD nodes */
+  const double *host_pd_pos; /* n_pd * dim reference positions */
+  double dx, horizon_factor;
+  double pd_lo[3], pd_hi[3], dom_lo[3], dom_hi[3];
+  double fe_h, overlap;
+  double cracks[8][3];
+  double E, rho, G0, thickness, s_crit, l_over_delta;
+  double traction, vel_bc;
+  double dt_pd;         /* PD step (s) > 0; the FE step is m * dt_pd */
+} mts_problem;
+
+typedef struct mts_info {
+  double delta, volume, c0, s_crit, dt_pd, dt_fe;
+  int64_t n_pd, nnz, n_fe_nodes, n_fe_elems, n_constraints, n_region;
+  int64_t pd_steps, macro_steps, n_rebuilds, n_colors;
+  int64_t device_bytes;
+  int32_t dim, precision;
+} mts_info;
+
+typedef struct mts_plan_info {
+  int64_t n_pd, nnz_estimate, n_fe_nodes, n_constraints_estimate;
+  int64_t device_bytes_estimate; /* upper estimate of what mts_create allocates */
+} mts_plan_info;
+
+/* Quantities for mts_read / mts_write (vectors node-major, dim per node). */
+enum {
+  MTS_PD_U = 0, MTS_PD_V, MTS_PD_A, MTS_FE_U, MTS_FE_V, MTS_FE_A,
+  MTS_DAMAGE,       /* PD nodal damage phi (Eq. 5), n_pd values */
+  MTS_LAMBDA,       /* multipliers lambda (n_constraints * dim) */
+  MTS_PD_ALPHA,     /* Arlequin weight at PD nodes */
+  MTS_PD_MASS, MTS_FE_MASS, MTS_FE_X,
+  MTS_CONSTRAINT_NODES, /* PD node ids of the constraint set, as doubles */
+  MTS_H             /* multiplier matrix H of Eq. 49 at the last (re)build, row-major;
+                       kept only when n_constraints * dim <= 4096 */
+};
+
+/* Kernels that mts_kernel_time reports. */
+enum { MTS_KT_PD_SUBSTEP = 0, MTS_KT_LINK = 1, MTS_KT_FE = 2, MTS_KT_LAMBDA = 3, MTS_KT_COUNT = 4 };
+
+typedef struct mts_solver mts_solver;
+
+/* Host-only estimate of sizes and device bytes for a problem (no device use).
+ * Errors: MTS_EINVAL for an inconsistent description. */
+mts_status mts_plan(const mts_problem *p, mts_plan_info *out);
+
+/* Build a solver on the current HIP device: neighbour lists (Sec. 2.1) built on
+ * the device, Arlequin weights and masses (Eq. 17-18, 34), FE mesh, the
+ * constraint set, the unit-load responses and the multiplier matrix (eq. unit,
+ * Eq. 49), all enqueued on `hip_stream` (a hipStream_t, or NULL for the null
+ * stream).  The solver owns its device memory.  On error *out stays NULL.
+ * Errors: MTS_EINVAL (bad description: dim, m < 1, dt_pd <= 0, horizon_factor < 1,
+ * n_pd <= 0, a crack line off the FE node lines, a constraint node in an element
+ * with no weight), MTS_ENOMEM, MTS_EDEVICE. */
+mts_status mts_create(const mts_problem *p, void *hip_stream, mts_solver **out);
+
+/* Enqueue n_macro macro steps (one FE step and m PD substeps each,
+ * Algorithm 1).  Returns after enqueueing the last macro step; it may wait on
+ * the device between macro steps while bonds inside the support of the
+ * unit-load responses break (the responses are then rebuilt, Algorithm 1).
+ * Errors: MTS_EUNSTABLE (sticky) once a non-finite value was seen, MTS_EDEVICE. */
+mts_status mts_advance(mts_solver *s, int64_t n_macro);
+
+/* Wait for all enqueued work and surface sticky errors. */
+mts_status mts_sync(mts_solver *s);
+
+/* Copy a quantity to host memory (synchronous).  `cap` is the capacity of
+ * host_out in doubles; *n receives the count.  MTS_EINVAL if cap is too small
+ * or the quantity does not exist in this mode. */
+mts_status mts_read(mts_solver *s, int32_t what, double *host_out, int64_t cap, int64_t *n);
+
+/* Overwrite MTS_PD_U/V/A, MTS_FE_U/V/A or MTS_LAMBDA from host memory
+ * (synchronous; n must equal the quantity's size). */
+mts_status mts_write(mts_solver *s, int32_t what, const double *host_in, int64_t n);
+
+/* Bond lists in canonical CSR (rows ascending) and the bond states
+ * (1 intact, 0 broken or cut by a crack).  cap = capacity of col/intact.
+ * row_ptr must hold n_pd + 1 entries.  Any pointer may be NULL. */
+mts_status mts_read_bonds(mts_solver *s, int64_t *host_row_ptr, int32_t *host_col,
+                          uint8_t *host_intact, int64_t cap, int64_t *nnz);
+
+mts_status mts_query(mts_solver *s, mts_info *out);
+
+/* Per-kernel HIP-event timing (on the solver's stream) while enabled. */
+mts_status mts_profile(mts_solver *s, int32_t enable);
+mts_status mts_kernel_time(mts_solver *s, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Frees everything the solver owns.  Accepts NULL. */
+void mts_destroy(mts_solver *s);
+
+const char *mts_status_str(mts_status st);
+const char *mts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTSPD_H */

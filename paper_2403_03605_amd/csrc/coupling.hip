@@ -1,0 +1,376 @@
+// Arlequin coupling with velocity-continuity multipliers across the overlap and
+// the multi-time-step free/link split (Sec. 2.5, Eq. 41-50, Algorithm 1).
+//
+// Constraints sit at every PD node with alpha > 0; G_P is Boolean and the rows
+// of G_F interpolate the FE velocity at the PD node (N_a(x_p)).  The multiplier
+// matrix H = G_P Ydot^PD_m + 1/2 dt_FE G_F M_F^-1 G_F^T is assembled from link
+// runs (m substeps of the linear PD response to a unit multiplier ramp, no
+// breaking) batched over colour classes of constraints whose supports do not
+// overlap, then inverted once.  Every macro step solves H lambda_m = G_F v~_F -
+// G_P V_m and applies U = V + Y lambda_m, the PD part by re-running the link
+// problem with the actual multipliers over the region the response can reach
+// ((m-1) horizons from the constraints), which equals Y^PD lambda_m.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <unordered_map>
+
+namespace mts {
+
+void link_zero(Solver &s, double *u0, double *u1, double *v, double *a, int nrhs);
+void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const double *lam,
+                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
+void link_add(Solver &s, const double *Wu, const double *Wv, const double *Wa);
+void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
+
+namespace {
+
+inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+__device__ inline double shape_c(int dim, int a, const double *xi) {
+  const int q4[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+  double v = (dim == 2 ? 0.25 : 0.125) * (1.0 + q4[a & 3][0] * xi[0]) * (1.0 + q4[a & 3][1] * xi[1]);
+  if (dim == 3) v = v * (1.0 + (a < 4 ? -1.0 : 1.0) * xi[2]);
+  return v;
+}
+
+// Element containing each constraint node and the interpolation weights N_a(x_p).
+__global__ void k_gf(int64_t nc, int dim, int nen, const int32_t *cn, const double *x, int64_t N, double lo0,
+                     double lo1, double lo2, double h, int64_t ne0, int64_t ne1, int64_t ne2, int32_t *cel,
+                     double *cw) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  int64_t i = cn[q];
+  double lo[3] = {lo0, lo1, lo2};
+  int64_t nen_ax[3] = {ne0, ne1, ne2};
+  int64_t ei[3] = {0, 0, 0};
+  double xi[3] = {0, 0, 0};
+  for (int a = 0; a < dim; a++) {
+    double t = (x[a * N + i] - lo[a]) / h;
+    ei[a] = (int64_t)floor(t);
+    if (ei[a] >= nen_ax[a]) ei[a] = nen_ax[a] - 1;
+    if (ei[a] < 0) ei[a] = 0;
+    xi[a] = 2.0 * (t - (double)ei[a]) - 1.0;
+  }
+  int64_t e = (ei[2] * ne1 + ei[1]) * ne0 + ei[0];
+  cel[q] = (int32_t)e;
+  for (int a = 0; a < nen; a++) {
+    double v;
+    if (dim == 2) {
+      const int q4[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+      v = 0.25 * (1.0 + q4[a][0] * xi[0]) * (1.0 + q4[a][1] * xi[1]);
+    } else {
+      v = shape_c(3, a, xi);
+    }
+    cw[q * nen + a] = v;
+  }
+}
+
+__global__ void k_region(const double *x, int64_t N, int dim, const int32_t *cn, int64_t nc, double R2,
+                         uint8_t *flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  uint8_t f = 0;
+  for (int64_t q = 0; q < nc && !f; q++) {
+    int64_t c = cn[q];
+    double d0 = x[i] - x[c];
+    double d1 = x[N + i] - x[N + c];
+    double r2 = d0 * d0 + d1 * d1;
+    if (dim == 3) {
+      double d2 = x[2 * N + i] - x[2 * N + c];
+      r2 = r2 + d2 * d2;
+    }
+    if (r2 <= R2) f = 1;
+  }
+  flag[i] = f;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_set_cidx(const int32_t *cn, int64_t nc, int32_t *cidx) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nc) cidx[cn[q]] = (int32_t)q;
+}
+
+// H[(q, d'), (p, dir)] = Wv_b[d'][node q] for the loaded constraint p of RHS b
+// that owns q (the only loaded node whose response can reach q).
+__global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32_t *cn, const int32_t *owner,
+                          const int32_t *rhs_color, const int32_t *rhs_dir, const double *Wv, int64_t N, double *H) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  int64_t node = cn[q];
+  for (int b = 0; b < nrhs; b++) {
+    int c = rhs_color[b];
+    if (c < 0) continue;
+    int32_t p = owner[(int64_t)c * nc + q];
+    if (p < 0) continue;
+    for (int d = 0; d < dim; d++)
+      H[(q * dim + d) * nl + (int64_t)p * dim + rhs_dir[b]] = Wv[((int64_t)b * dim + d) * N + node];
+  }
+}
+
+// + 1/2 dt_FE G_F M_F^-1 G_F^T (prescribed-velocity dofs do not respond).
+__global__ void k_add_hf(int64_t nc, int dim, int nen, int64_t nl, const int32_t *cel, const int32_t *conn,
+                         const double *cw, const double *mF, const uint8_t *bc, double hdtF, int64_t ne0,
+                         int64_t ne1, double *H) {
+  int64_t pq = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
+  int64_t qq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pq >= nc || qq >= nc) return;
+  int64_t ep = cel[pq], eq = cel[qq];
+  int64_t dx = ep % ne0 - eq % ne0, dy = (ep / ne0) % ne1 - (eq / ne0) % ne1, dz = ep / (ne0 * ne1) - eq / (ne0 * ne1);
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int ap = 0; ap < nen; ap++)
+    for (int aq = 0; aq < nen; aq++) {
+      int64_t np_ = conn[ep * nen + ap], nq_ = conn[eq * nen + aq];
+      if (np_ != nq_) continue;
+      for (int d = 0; d < dim; d++) {
+        if (bc[np_ * dim + d]) continue;
+        acc[d] += cw[pq * nen + ap] * cw[qq * nen + aq] / mF[np_];
+      }
+    }
+  for (int d = 0; d < dim; d++) H[(pq * dim + d) * nl + qq * dim + d] += hdtF * acc[d];
+}
+
+// r = G_F v~_F - G_P V_m  (right-hand side of Eq. 49, from Eq. 41)
+__global__ void k_rhs(int64_t nc, int dim, int nen, const int32_t *cn, const int32_t *cel, const int32_t *conn,
+                      const double *cw, const double *vt, const double *vP, int64_t N, double *r) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  int64_t e = cel[q];
+  for (int d = 0; d < dim; d++) {
+    double g = 0.0;
+    for (int a = 0; a < nen; a++) g += cw[q * nen + a] * vt[(int64_t)conn[e * nen + a] * dim + d];
+    r[q * dim + d] = g - vP[d * N + cn[q]];
+  }
+}
+
+}  // namespace
+
+void coupling_setup(Solver &s) {
+  const int dim = s.dim;
+  const int64_t N = s.N;
+  hipStream_t st = s.stream;
+  DeviceArena &ar = s.arena;
+  // constraint set: PD nodes with alpha > 0 (the overlap)
+  std::vector<double> al(N);
+  MTS_HIP(hipMemcpyAsync(al.data(), s.alpha, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  s.h_cn.clear();
+  for (int64_t i = 0; i < N; i++) {
+    if (al[i] >= 1.0) throw ArgError{"a PD node has alpha = 1 (zero PD mass)"};
+    if (al[i] > 0.0) s.h_cn.push_back((int32_t)i);
+  }
+  s.nc = (int64_t)s.h_cn.size();
+  s.nl = s.nc * dim;
+  if (s.nc == 0) throw ArgError{"coupled mode needs an overlap band inside the body"};
+  s.cn = ar.alloc<int32_t>(s.nc);
+  s.cidx = ar.alloc<int32_t>(N);
+  s.cel = ar.alloc<int32_t>(s.nc);
+  s.cw = ar.alloc<double>(s.nc * s.nen);
+  MTS_HIP(hipMemcpyAsync(s.cn, s.h_cn.data(), sizeof(int32_t) * s.nc, hipMemcpyHostToDevice, st));
+  k_fill_i32<<<nb(N), 256, 0, st>>>(s.cidx, N, -1);
+  MTS_LAUNCH_CHECK();
+  k_set_cidx<<<nb(s.nc), 256, 0, st>>>(s.cn, s.nc, s.cidx);
+  MTS_LAUNCH_CHECK();
+  k_gf<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, s.nen, s.cn, s.x, N, s.p.dom_lo[0], s.p.dom_lo[1],
+                                 dim == 3 ? s.p.dom_lo[2] : 0.0, s.p.fe_h, s.p.fe_n[0], s.p.fe_n[1],
+                                 dim == 3 ? s.p.fe_n[2] : 1, s.cel, s.cw);
+  MTS_LAUNCH_CHECK();
+  std::vector<int32_t> hcel(s.nc);
+  std::vector<uint8_t> heact(s.ne);
+  MTS_HIP(hipMemcpyAsync(hcel.data(), s.cel, sizeof(int32_t) * s.nc, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipMemcpyAsync(heact.data(), s.eact, s.ne, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  for (int64_t q = 0; q < s.nc; q++)
+    if (!heact[hcel[q]]) throw ArgError{"a constraint node lies in an FE element with zero weight"};
+  // FE node -> (constraint * nen + a), ascending constraint order
+  std::vector<int32_t> cnt(s.nfe + 1, 0);
+  for (int64_t q = 0; q < s.nc; q++)
+    for (int a = 0; a < s.nen; a++) cnt[s.h_conn[(int64_t)hcel[q] * s.nen + a] + 1]++;
+  for (int64_t n = 0; n < s.nfe; n++) cnt[n + 1] += cnt[n];
+  std::vector<int32_t> f2c(cnt[s.nfe]), fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t q = 0; q < s.nc; q++)
+    for (int a = 0; a < s.nen; a++) f2c[fill[s.h_conn[(int64_t)hcel[q] * s.nen + a]]++] = (int32_t)(q * s.nen + a);
+  s.f2c_ptr = ar.alloc<int32_t>(s.nfe + 1);
+  s.f2c = ar.alloc<int32_t>(f2c.size());
+  MTS_HIP(hipMemcpyAsync(s.f2c_ptr, cnt.data(), sizeof(int32_t) * (s.nfe + 1), hipMemcpyHostToDevice, st));
+  if (!f2c.empty())
+    MTS_HIP(hipMemcpyAsync(s.f2c, f2c.data(), sizeof(int32_t) * f2c.size(), hipMemcpyHostToDevice, st));
+
+  // link region: nodes within (m-1) horizons of a constraint node
+  double Rr = (double)(s.m - 1) * s.prm.delta;
+  s.in_region = ar.alloc<uint8_t>(N);
+  k_region<<<nb(N), 256, 0, st>>>(s.x, N, dim, s.cn, s.nc, Rr * Rr, s.in_region);
+  MTS_LAUNCH_CHECK();
+  std::vector<uint8_t> reg(N);
+  MTS_HIP(hipMemcpyAsync(reg.data(), s.in_region, N, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> rrows;
+  for (int64_t i = 0; i < N; i++)
+    if (reg[i]) rrows.push_back((int32_t)i);
+  s.n_region = (int64_t)rrows.size();
+  build_sell(s, s.rsell, rrows, s.sell.mask);
+
+  // colour classes: constraints closer than 2R + 2 delta get different colours,
+  // so the responses (support radius R) of one class never overlap.  This is a
+  // scheduling choice; every entry of H is still the single-load response.
+  const double sep = 2.0 * Rr + 2.0 * s.prm.delta;
+  const double own = Rr + 0.5 * s.prm.delta;
+  std::vector<int32_t> color(s.nc, -1);
+  {
+    const double cs = sep;
+    double lo[3] = {0, 0, 0};
+    for (int a = 0; a < dim; a++) lo[a] = s.p.pd_lo[a] - 2 * s.prm.delta;
+    auto key = [&](int64_t q, int64_t off[3]) {
+      int64_t c[3] = {0, 0, 0};
+      for (int a = 0; a < dim; a++) c[a] = (int64_t)std::floor((s.pos[(int64_t)s.h_cn[q] * dim + a] - lo[a]) / cs) + off[a];
+      return (c[2] * 1000003LL + c[1]) * 1000003LL + c[0];
+    };
+    std::unordered_map<int64_t, std::vector<int32_t>> cells;
+    int64_t zero[3] = {0, 0, 0};
+    for (int64_t q = 0; q < s.nc; q++) cells[key(q, zero)].push_back((int32_t)q);
+    auto d2 = [&](int64_t a, int64_t b) {
+      double r = 0;
+      for (int c = 0; c < dim; c++) {
+        double t = s.pos[(int64_t)s.h_cn[a] * dim + c] - s.pos[(int64_t)s.h_cn[b] * dim + c];
+        r += t * t;
+      }
+      return r;
+    };
+    std::vector<char> used;
+    int zr = dim == 3 ? 1 : 0;
+    for (int64_t q = 0; q < s.nc; q++) {
+      used.assign(used.size(), 0);
+      for (int dz = -zr; dz <= zr; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dxx = -1; dxx <= 1; dxx++) {
+            int64_t off[3] = {dxx, dy, dz};
+            auto it = cells.find(key(q, off));
+            if (it == cells.end()) continue;
+            for (int32_t p : it->second)
+              if (color[p] >= 0 && d2(p, q) <= sep * sep) {
+                if ((int64_t)used.size() <= color[p]) used.resize(color[p] + 1, 0);
+                used[color[p]] = 1;
+              }
+          }
+      int c = 0;
+      while (c < (int)used.size() && used[c]) c++;
+      color[q] = c;
+    }
+    s.n_colors = 0;
+    for (int32_t c : color) s.n_colors = std::max<int64_t>(s.n_colors, c + 1);
+    // owner[c][q]: the constraint of colour c whose support can reach q
+    std::vector<int32_t> owner((size_t)(s.n_colors * s.nc), -1);
+    for (int64_t q = 0; q < s.nc; q++)
+      for (int dz = -zr; dz <= zr; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dxx = -1; dxx <= 1; dxx++) {
+            int64_t off[3] = {dxx, dy, dz};
+            auto it = cells.find(key(q, off));
+            if (it == cells.end()) continue;
+            for (int32_t p : it->second)
+              if (d2(p, q) <= own * own) owner[(size_t)color[p] * s.nc + q] = p;
+          }
+    int32_t *dcolor = ar.alloc<int32_t>(s.nc);
+    int32_t *downer = ar.alloc<int32_t>(owner.size());
+    MTS_HIP(hipMemcpyAsync(dcolor, color.data(), sizeof(int32_t) * s.nc, hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemcpyAsync(downer, owner.data(), sizeof(int32_t) * owner.size(), hipMemcpyHostToDevice, st));
+    s.ccolor = dcolor;
+    s.owner = downer;
+    MTS_HIP(hipStreamSynchronize(st));
+  }
+  s.nrhs = dim == 2 ? 8 : 6;
+  size_t wsz = (size_t)s.nrhs * dim * N;
+  s.Wu[0] = ar.alloc<double>(wsz);
+  s.Wu[1] = ar.alloc<double>(wsz);
+  s.Wv = ar.alloc<double>(wsz);
+  s.Wa = ar.alloc<double>(wsz);
+  for (double *q : {s.Wu[0], s.Wu[1], s.Wv, s.Wa}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
+  s.lam = ar.alloc<double>(s.nl);
+  s.lam0 = ar.alloc<double>(s.nl);
+  s.rhs = ar.alloc<double>(s.nl);
+  MTS_HIP(hipMemsetAsync(s.lam, 0, sizeof(double) * s.nl, st));
+  MTS_HIP(hipMemsetAsync(s.lam0, 0, sizeof(double) * s.nl, st));
+  s.Hinv = ar.alloc<double>((size_t)s.nl * s.nl);
+  s.keep_h = s.nl <= 4096;
+  coupling_rebuild(s);
+}
+
+// Unit-load responses on the current bond states, H, and its inverse.
+void coupling_rebuild(Solver &s) {
+  const int dim = s.dim;
+  hipStream_t st = s.stream;
+  const int64_t nl = s.nl;
+  sell_regather_mask(s, s.rsell, s.sell.mask);
+  MTS_HIP(hipMemsetAsync(s.Hinv, 0, sizeof(double) * nl * nl, st));
+  const int cpb = s.nrhs / dim;  // colours per batch
+  int32_t rc[16], rd[16];
+  int32_t *drc = nullptr, *drd = nullptr;
+  if (!s.rhs_color_dev) {
+    s.rhs_color_dev = s.arena.alloc<int32_t>(16);
+    s.rhs_dir_dev = s.arena.alloc<int32_t>(16);
+  }
+  drc = s.rhs_color_dev;
+  drd = s.rhs_dir_dev;
+  for (int64_t c0 = 0; c0 < s.n_colors; c0 += cpb) {
+    for (int b = 0; b < s.nrhs; b++) {
+      int64_t c = c0 + b / dim;
+      rc[b] = c < s.n_colors ? (int32_t)c : -1;
+      rd[b] = b % dim;
+    }
+    link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, s.nrhs);
+    int k = 0;
+    for (int j = 1; j <= s.m; j++) {
+      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, nullptr, s.ccolor, rc, rd, s.nrhs);
+      k ^= 1;
+    }
+    MTS_HIP(hipMemcpyAsync(drc, rc, sizeof(rc), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemcpyAsync(drd, rd, sizeof(rd), hipMemcpyHostToDevice, st));
+    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drc, drd, s.Wv, s.N, s.Hinv);
+    MTS_LAUNCH_CHECK();
+    // the host arrays rc/rd are reused next iteration
+    MTS_HIP(hipStreamSynchronize(st));
+  }
+  // leave the W arrays zeroed for the per-step correction
+  link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, s.nrhs);
+  dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
+  k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
+                                s.p.fe_n[1], s.Hinv);
+  MTS_LAUNCH_CHECK();
+  if (s.keep_h) {
+    if (!s.Hcopy) s.Hcopy = s.arena.alloc<double>((size_t)nl * nl);
+    MTS_HIP(hipMemcpyAsync(s.Hcopy, s.Hinv, sizeof(double) * nl * nl, hipMemcpyDeviceToDevice, st));
+  }
+  dense_spd_inverse(s, s.Hinv, nl);
+  MTS_HIP(hipStreamSynchronize(st));
+}
+
+void coupling_solve_and_correct(Solver &s) {
+  hipStream_t st = s.stream;
+  hipEvent_t e0 = nullptr;
+  s.prof_begin(MTS_KT_LAMBDA, &e0);
+  k_rhs<<<nb(s.nc), 256, 0, st>>>(s.nc, s.dim, s.nen, s.cn, s.cel, s.conn, s.cw, s.vt, s.v, s.N, s.rhs);
+  MTS_LAUNCH_CHECK();
+  dense_gemv(st, s.Hinv, s.rhs, s.lam, s.nl);
+  s.prof_end(MTS_KT_LAMBDA, e0);
+  fe_correct(s);
+  // PD: U = V + Y lambda_m by re-running the link problem with lambda_m
+  hipEvent_t e1 = nullptr;
+  s.prof_begin(MTS_KT_LINK, &e1);
+  link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, 1);
+  int k = 0;
+  for (int j = 1; j <= s.m; j++) {
+    link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.lam, nullptr, nullptr, nullptr, 1);
+    k ^= 1;
+  }
+  link_add(s, s.Wu[k ^ 1], s.Wv, s.Wa);
+  s.prof_end(MTS_KT_LINK, e1);
+  MTS_HIP(hipMemcpyAsync(s.lam0, s.lam, sizeof(double) * s.nl, hipMemcpyDeviceToDevice, st));
+}
+
+}  // namespace mts

@@ -1,0 +1,190 @@
+// Internal declarations of the mtspd library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mtspd.h"
+
+namespace mts {
+
+struct HipError {
+  hipError_t err;
+  const char *expr;
+  const char *file;
+  int line;
+};
+struct ArgError {
+  std::string msg;
+};
+struct MemError {
+  std::string msg;
+};
+
+#define MTS_HIP(expr)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) throw ::mts::HipError{e_, #expr, __FILE__, __LINE__}; \
+  } while (0)
+
+#define MTS_LAUNCH_CHECK() MTS_HIP(hipGetLastError())
+
+// Device allocations owned by one solver.
+struct DeviceArena {
+  std::vector<void *> blocks;
+  size_t bytes = 0;
+  template <class T>
+  T *alloc(size_t n) {
+    void *p = nullptr;
+    size_t b = sizeof(T) * (n ? n : 1);
+    b = (b + 255) & ~size_t(255);
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      throw MemError{"hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+    blocks.push_back(p);
+    bytes += b;
+    return static_cast<T *>(p);
+  }
+  void release(void *p);
+  void free_all();
+};
+
+constexpr int WAVE = 64;
+
+// Scalars of one problem, passed by value to kernels.
+struct Params {
+  int dim;
+  int weight_kind;
+  int kernel;
+  int coupled;
+  double delta, d2, V, VV, c0, lexp, scrit;
+  double dtP, hdtP, hdt2P, dtF, hdtF, hdt2F;
+  double o2lo[3], o2hi[3];
+  double overlap;
+  double rho;
+};
+
+// Sliced-ELL bond layout: slices of 64 consecutive rows (one wavefront);
+// slot k of row (slice*64 + lane) sits at col[slice_off[slice] + k*64 + lane];
+// bond states are one 64-bit word per (slice, k): bit `lane` = intact.
+struct Sell {
+  int64_t n_rows = 0, n_slices = 0, n_slots = 0, n_words = 0;
+  int32_t *rows = nullptr;       // row -> node id (identity for the full lattice)
+  int32_t *width = nullptr;      // per slice
+  int64_t *slot_off = nullptr;   // per slice, in slots (multiple of 64)
+  int64_t *word_off = nullptr;   // per slice, in mask words
+  int32_t *col = nullptr;        // n_slots
+  uint64_t *mask = nullptr;      // n_words
+};
+
+struct Solver {
+  mts_problem p{};
+  std::vector<double> pos;   // host copy, node-major
+  std::vector<double> cracks;
+  int dim = 2;
+  int64_t N = 0;
+  hipStream_t stream = nullptr;
+  DeviceArena arena;
+  Params prm{};
+  int precision = MTS_FP64;
+  bool breaking = true;
+  int m = 1;
+  bool unstable = false;
+  int64_t pd_steps = 0, macro_steps = 0, n_rebuilds = 0;
+
+  // ---- PD ----
+  double *x = nullptr;           // SoA dim*N
+  float *xf = nullptr;           // SoA dim*N, positions minus the PD box origin (mixed)
+  double *alpha = nullptr, *mass = nullptr, *P = nullptr;
+  double *u[2] = {nullptr, nullptr};
+  double *v = nullptr, *a = nullptr;
+  int cur = 0;                   // u[cur] = current displacement, u[cur^1] = predicted next
+  int32_t *rp = nullptr;         // canonical CSR, N+1
+  int32_t *csr_col = nullptr;    // nnz
+  int64_t nnz = 0;
+  Sell sell;                     // full lattice, row = node
+  double *damage = nullptr;
+  int32_t *region_flag = nullptr;  // device flag: a bond in the link region broke
+  uint8_t *in_region = nullptr;    // per node
+
+  // ---- FE ----
+  int nen = 4, ngp = 4, nstr = 3;
+  int64_t nfe = 0, ne = 0;
+  int32_t *conn = nullptr;       // ne * nen
+  uint8_t *eact = nullptr;       // ne
+  double *gpa = nullptr;         // ne * ngp
+  int32_t *n2e_ptr = nullptr, *n2e = nullptr;  // node -> (element*nen + local) list
+  uint8_t *nact = nullptr, *bc = nullptr;
+  double *xF = nullptr, *mF = nullptr, *PF = nullptr;
+  double *uF = nullptr, *vF = nullptr, *aF = nullptr;
+  double *ut = nullptr, *vt = nullptr, *at = nullptr, *fe_buf = nullptr;
+  std::vector<int32_t> h_conn;
+  std::vector<uint8_t> h_bc;
+
+  // ---- coupling ----
+  int64_t nc = 0, nl = 0;
+  int32_t *cn = nullptr;         // constraint -> PD node
+  int32_t *cidx = nullptr;       // PD node -> constraint or -1
+  int32_t *cel = nullptr;        // constraint -> element
+  double *cw = nullptr;          // nc * nen interpolation weights N_a(x_p)
+  int32_t *f2c_ptr = nullptr, *f2c = nullptr;  // FE node -> (constraint*nen + a)
+  double *lam = nullptr, *lam0 = nullptr, *rhs = nullptr;
+  double *Hinv = nullptr;        // nl * nl, row-major
+  double *tmpA = nullptr, *tmpB = nullptr, *pinv = nullptr;
+  std::vector<int32_t> h_cn;
+  int64_t n_region = 0;
+  Sell rsell;                    // link region rows
+  uint64_t *mask_snap = nullptr; // full-lattice copy of the bond states at the last rebuild
+  double *Wu[2] = {nullptr, nullptr};
+  double *Wv = nullptr, *Wa = nullptr; // dim*N (zero outside the region)
+  int64_t n_colors = 0;
+  int32_t *ccolor = nullptr;     // colour of each constraint
+  int32_t *owner = nullptr;      // n_colors * nc: loaded constraint of that colour reaching q, or -1
+  int nrhs = 8;
+  int32_t *rhs_color_dev = nullptr, *rhs_dir_dev = nullptr;
+  bool keep_h = false;
+  double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)
+  int32_t *pinned_flag = nullptr;
+
+  // profiling
+  bool profiling = false;
+  hipEvent_t ev_start[MTS_KT_COUNT]{}, ev_stop[MTS_KT_COUNT]{};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[MTS_KT_COUNT];
+  int64_t kt_count[MTS_KT_COUNT]{};
+  double kt_ms[MTS_KT_COUNT]{};
+  std::vector<hipEvent_t> ev_pool;
+
+  void prof_begin(int k, hipEvent_t *e0);
+  void prof_end(int k, hipEvent_t e0);
+  void prof_collect();
+};
+
+// neighbour build and bond layout (neighbors.hip)
+void build_neighbors(Solver &s);
+void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full);
+void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
+void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
+// PD kernels (pd.hip)
+void pd_setup(Solver &s);
+void pd_predict_all(Solver &s);
+void pd_substep(Solver &s, int j);
+void pd_damage(Solver &s);
+// FE kernels (fe.hip)
+void fe_setup(Solver &s);
+void fe_free_step(Solver &s);
+void fe_correct(Solver &s);
+// coupling (coupling.hip)
+void coupling_setup(Solver &s);
+void coupling_rebuild(Solver &s);
+void coupling_solve_and_correct(Solver &s);
+// dense linear algebra (dense.hip)
+void dense_spd_inverse(Solver &s, double *A, int64_t n);
+void dense_gemv(hipStream_t st, const double *A, const double *x, double *y, int64_t n);
+// scans (neighbors.hip)
+void exclusive_scan_i64(hipStream_t st, DeviceArena &ar, const int64_t *in, int64_t *out, int64_t n);
+
+}  // namespace mts

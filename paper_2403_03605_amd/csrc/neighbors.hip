@@ -1,0 +1,406 @@
+// Neighbour families H_delta(x_i) = {k != i : |x_k - x_i| <= delta} (Sec. 2.1),
+// built on the device with a cell list, stored as canonical CSR (rows ascending)
+// and re-laid as sliced ELL for the bond pass.  Pre-crack bonds (horizontal
+// segments) start with state 0 (Eq. 4 with a history that is already broken).
+#include "internal.h"
+
+#include <algorithm>
+
+namespace mts {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int t = kThreads) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------- scan
+__global__ void scan_block_i64(const int64_t *in, int64_t *out, int64_t *block_sums, int64_t n) {
+  __shared__ int64_t sh[1024];
+  int64_t base = (int64_t)blockIdx.x * 1024;
+  int t = threadIdx.x;  // 256 threads, 4 items each
+  int64_t v[4];
+  int64_t s = 0;
+  for (int q = 0; q < 4; q++) {
+    int64_t idx = base + t * 4 + q;
+    v[q] = idx < n ? in[idx] : 0;
+    s += v[q];
+  }
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int64_t run = sh[t] - s;  // exclusive prefix of this thread
+  for (int q = 0; q < 4; q++) {
+    int64_t idx = base + t * 4 + q;
+    if (idx < n) out[idx] = run;
+    run += v[q];
+  }
+  if (t == 255 && block_sums) block_sums[blockIdx.x] = sh[255];
+}
+
+__global__ void scan_add_i64(int64_t *out, const int64_t *offs, int64_t n) {
+  int64_t idx = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  int64_t o = offs[blockIdx.x];
+  for (int q = 0; q < 4; q++)
+    if (idx + q < n) out[idx + q] += o;
+}
+
+// ---------------------------------------------------------------- cell list
+struct Grid {
+  double lo[3];
+  double cs;
+  int64_t nc[3];
+};
+
+__device__ inline int64_t cell_coord(double x, double lo, double cs, int64_t nc) {
+  int64_t c = (int64_t)floor((x - lo) / cs);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ void k_cell_of(const double *x, int64_t N, int dim, Grid g, int32_t *cell, int32_t *count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int64_t c0 = cell_coord(x[i], g.lo[0], g.cs, g.nc[0]);
+  int64_t c1 = cell_coord(x[N + i], g.lo[1], g.cs, g.nc[1]);
+  int64_t c2 = dim == 3 ? cell_coord(x[2 * N + i], g.lo[2], g.cs, g.nc[2]) : 0;
+  int64_t c = (c2 * g.nc[1] + c1) * g.nc[0] + c0;
+  cell[i] = (int32_t)c;
+  atomicAdd(&count[c], 1);
+}
+
+__global__ void k_i32_to_i64(const int32_t *a, int64_t *b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_scatter_cells(const int32_t *cell, int64_t N, const int64_t *start, int32_t *fill,
+                                int32_t *items) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int c = cell[i];
+  int slot = atomicAdd(&fill[c], 1);
+  items[start[c] + slot] = (int32_t)i;
+}
+
+// |x_k - x_i|^2 evaluated as ((dx*dx + dy*dy) + dz*dz), contraction off.
+__device__ inline double dist2_soa(const double *x, int64_t N, int dim, int64_t i, int64_t k) {
+  double d0 = x[k] - x[i];
+  double d1 = x[N + k] - x[N + i];
+  double r2 = d0 * d0 + d1 * d1;
+  if (dim == 3) {
+    double d2 = x[2 * N + k] - x[2 * N + i];
+    r2 = r2 + d2 * d2;
+  }
+  return r2;
+}
+
+template <bool kFill>
+__global__ void k_family(const double *x, int64_t N, int dim, Grid g, const int32_t *cell,
+                         const int64_t *cstart, const int32_t *items, double d2, int64_t *rowlen,
+                         const int64_t *rp, int32_t *col) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int64_t c = cell[i];
+  int64_t cx = c % g.nc[0], cy = (c / g.nc[0]) % g.nc[1], cz = c / (g.nc[0] * g.nc[1]);
+  int64_t cnt = 0;
+  int64_t out = kFill ? rp[i] : 0;
+  int zr = dim == 3 ? 1 : 0;
+  for (int dz = -zr; dz <= zr; dz++)
+    for (int dy = -1; dy <= 1; dy++)
+      for (int dx = -1; dx <= 1; dx++) {
+        int64_t ax = cx + dx, ay = cy + dy, az = cz + dz;
+        if (ax < 0 || ay < 0 || az < 0 || ax >= g.nc[0] || ay >= g.nc[1] || az >= g.nc[2]) continue;
+        int64_t q = (az * g.nc[1] + ay) * g.nc[0] + ax;
+        for (int64_t t = cstart[q]; t < cstart[q + 1]; t++) {
+          int64_t k = items[t];
+          if (k == i) continue;
+          if (dist2_soa(x, N, dim, i, k) <= d2) {
+            if (kFill) col[out + cnt] = (int32_t)k;
+            cnt++;
+          }
+        }
+      }
+  if (!kFill) {
+    rowlen[i] = cnt;
+  } else {
+    // canonical order: ascending neighbour id (insertion sort of a short row)
+    int32_t *r = col + out;
+    for (int64_t a = 1; a < cnt; a++) {
+      int32_t key = r[a];
+      int64_t b = a - 1;
+      while (b >= 0 && r[b] > key) {
+        r[b + 1] = r[b];
+        b--;
+      }
+      r[b + 1] = key;
+    }
+  }
+}
+
+__global__ void k_i64_to_i32(const int64_t *a, int32_t *b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+// ---------------------------------------------------------------- sliced ELL
+struct Cracks {
+  int n;
+  double c[8][3];
+};
+
+// Pre-crack (horizontal segment y = yc, x_start <= x* <= x_end, tip inclusive);
+// x* from the endpoint with the smaller id so both directions agree.
+__device__ inline bool crosses_crack(const double *x, int64_t N, int64_t i, int64_t k, const Cracks &cr) {
+  int64_t p = i < k ? i : k, q = i < k ? k : i;
+  double xp = x[p], yp = x[N + p], xq = x[q], yq = x[N + q];
+  for (int c = 0; c < cr.n; c++) {
+    double yc = cr.c[c][0];
+    if ((yp - yc) * (yq - yc) < 0.0) {
+      double xs = xp + (yc - yp) * (xq - xp) / (yq - yp);
+      if (xs >= cr.c[c][1] && xs <= cr.c[c][2]) return true;
+    }
+  }
+  return false;
+}
+
+__global__ void k_slice_width(const int32_t *rows, int64_t n_rows, const int32_t *rp, int32_t *width,
+                              int64_t n_slices) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices) return;
+  int w = 0;
+  for (int l = 0; l < WAVE; l++) {
+    int64_t r = s * WAVE + l;
+    if (r >= n_rows) break;
+    int64_t i = rows[r];
+    int len = rp[i + 1] - rp[i];
+    w = len > w ? len : w;
+  }
+  width[s] = w;
+}
+
+__global__ void k_sell_fill(const int32_t *rows, int64_t n_rows, const int32_t *rp, const int32_t *csr_col,
+                            const int32_t *width, const int64_t *slot_off, int32_t *col) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t n_pad = ((n_rows + WAVE - 1) / WAVE) * WAVE;
+  if (r >= n_pad) return;
+  int64_t s = r / WAVE;
+  int lane = (int)(r % WAVE);
+  int w = width[s];
+  int64_t base = slot_off[s];
+  if (r >= n_rows) {
+    for (int k = 0; k < w; k++) col[base + (int64_t)k * WAVE + lane] = 0;
+    return;
+  }
+  int64_t i = rows[r];
+  int len = rp[i + 1] - rp[i];
+  for (int k = 0; k < w; k++) col[base + (int64_t)k * WAVE + lane] = k < len ? csr_col[rp[i] + k] : (int32_t)i;
+}
+
+// One thread per (slice, k) word.  src_mask == nullptr: initial states from the
+// crack segments; otherwise bits are gathered from the full-lattice layout.
+__global__ void k_sell_mask(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
+                            const int32_t *csr_col, const int32_t *width, const int64_t *word_off,
+                            uint64_t *mask, const double *x, int64_t N, int dim, Cracks cr,
+                            const uint64_t *src_mask, const int64_t *src_word_off) {
+  int64_t s = blockIdx.y;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices || k >= width[s]) return;
+  uint64_t word = 0;
+  for (int l = 0; l < WAVE; l++) {
+    int64_t r = s * WAVE + l;
+    if (r >= n_rows) break;
+    int64_t i = rows[r];
+    int len = rp[i + 1] - rp[i];
+    if (k >= len) continue;
+    bool intact;
+    if (src_mask) {
+      intact = (src_mask[src_word_off[i / WAVE] + k] >> (i % WAVE)) & 1ull;
+    } else {
+      int64_t c = csr_col[rp[i] + k];
+      intact = !(dim == 2 && crosses_crack(x, N, i, c, cr));
+    }
+    if (intact) word |= 1ull << l;
+  }
+  mask[word_off[s] + k] = word;
+}
+
+__global__ void k_mask_to_csr(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask,
+                              uint8_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int64_t s = i / WAVE;
+  int lane = (int)(i % WAVE);
+  int len = rp[i + 1] - rp[i];
+  for (int k = 0; k < len; k++) out[rp[i] + k] = (uint8_t)((mask[word_off[s] + k] >> lane) & 1ull);
+}
+
+}  // namespace
+
+void bonds_to_csr_state(Solver &s, uint8_t *dev_out) {
+  k_mask_to_csr<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, dev_out);
+  MTS_LAUNCH_CHECK();
+}
+
+void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full) {
+  if (!out.n_slices) return;
+  std::vector<int32_t> w(out.n_slices);
+  MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * out.n_slices, hipMemcpyDeviceToHost, s.stream));
+  MTS_HIP(hipStreamSynchronize(s.stream));
+  int maxw = 0;
+  for (int32_t v : w) maxw = std::max(maxw, (int)v);
+  if (!maxw) return;
+  Cracks cr{};
+  dim3 grid((unsigned)((maxw + 63) / 64), (unsigned)out.n_slices);
+  k_sell_mask<<<grid, 64, 0, s.stream>>>(out.rows, out.n_rows, out.n_slices, s.rp, s.csr_col, out.width,
+                                          out.word_off, out.mask, s.x, s.N, s.dim, cr, src_mask_full,
+                                          s.sell.word_off);
+  MTS_LAUNCH_CHECK();
+}
+
+void exclusive_scan_i64(hipStream_t st, DeviceArena &ar, const int64_t *in, int64_t *out, int64_t n) {
+  if (n <= 0) return;
+  int64_t nb = (n + 1023) / 1024;
+  if (nb == 1) {
+    scan_block_i64<<<1, 256, 0, st>>>(in, out, nullptr, n);
+    MTS_LAUNCH_CHECK();
+    return;
+  }
+  int64_t *sums = ar.alloc<int64_t>(nb);
+  int64_t *offs = ar.alloc<int64_t>(nb);
+  scan_block_i64<<<(unsigned)nb, 256, 0, st>>>(in, out, sums, n);
+  MTS_LAUNCH_CHECK();
+  exclusive_scan_i64(st, ar, sums, offs, nb);
+  scan_add_i64<<<(unsigned)nb, 256, 0, st>>>(out, offs, n);
+  MTS_LAUNCH_CHECK();
+  MTS_HIP(hipStreamSynchronize(st));
+  ar.release(sums);
+  ar.release(offs);
+}
+
+void build_neighbors(Solver &s) {
+  const int dim = s.dim;
+  const int64_t N = s.N;
+  hipStream_t st = s.stream;
+  DeviceArena &ar = s.arena;
+  // Cell list with cells of side delta: two points within delta fall in the
+  // same or adjacent cells, so 3^dim cells are searched per node.
+  Grid g{};
+  g.cs = s.prm.delta;
+  for (int a = 0; a < 3; a++) {
+    g.lo[a] = 0.0;
+    g.nc[a] = 1;
+  }
+  for (int a = 0; a < dim; a++) {
+    double lo = s.pos[a], hi = s.pos[a];
+    for (int64_t i = 0; i < N; i++) {
+      lo = std::min(lo, s.pos[i * dim + a]);
+      hi = std::max(hi, s.pos[i * dim + a]);
+    }
+    g.lo[a] = lo;
+    g.nc[a] = (int64_t)std::floor((hi - lo) / g.cs) + 1;
+  }
+  int64_t ncell = g.nc[0] * g.nc[1] * g.nc[2];
+  if (ncell > (int64_t)1 << 30) throw ArgError{"cell grid too large"};
+  int32_t *cell = ar.alloc<int32_t>(N);
+  int32_t *count = ar.alloc<int32_t>(ncell);
+  int32_t *fill = ar.alloc<int32_t>(ncell);
+  int64_t *count64 = ar.alloc<int64_t>(ncell + 1);
+  int64_t *cstart = ar.alloc<int64_t>(ncell + 1);
+  int32_t *items = ar.alloc<int32_t>(N);
+  MTS_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * ncell, st));
+  MTS_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * ncell, st));
+  MTS_HIP(hipMemsetAsync(count64, 0, sizeof(int64_t) * (ncell + 1), st));
+  k_cell_of<<<blocks_for(N), kThreads, 0, st>>>(s.x, N, dim, g, cell, count);
+  MTS_LAUNCH_CHECK();
+  k_i32_to_i64<<<blocks_for(ncell), kThreads, 0, st>>>(count, count64, ncell);
+  MTS_LAUNCH_CHECK();
+  exclusive_scan_i64(st, ar, count64, cstart, ncell + 1);
+  k_scatter_cells<<<blocks_for(N), kThreads, 0, st>>>(cell, N, cstart, fill, items);
+  MTS_LAUNCH_CHECK();
+
+  int64_t *rowlen = ar.alloc<int64_t>(N + 1);
+  int64_t *rp64 = ar.alloc<int64_t>(N + 1);
+  MTS_HIP(hipMemsetAsync(rowlen, 0, sizeof(int64_t) * (N + 1), st));
+  k_family<false><<<blocks_for(N), kThreads, 0, st>>>(s.x, N, dim, g, cell, cstart, items, s.prm.d2,
+                                                       rowlen, nullptr, nullptr);
+  MTS_LAUNCH_CHECK();
+  exclusive_scan_i64(st, ar, rowlen, rp64, N + 1);
+  int64_t nnz = 0;
+  MTS_HIP(hipMemcpyAsync(&nnz, rp64 + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  if (nnz >= ((int64_t)1 << 31)) throw ArgError{"more than 2^31 bonds"};
+  s.nnz = nnz;
+  s.rp = ar.alloc<int32_t>(N + 1);
+  s.csr_col = ar.alloc<int32_t>(nnz);
+  k_i64_to_i32<<<blocks_for(N + 1), kThreads, 0, st>>>(rp64, s.rp, N + 1);
+  MTS_LAUNCH_CHECK();
+  k_family<true><<<blocks_for(N), kThreads, 0, st>>>(s.x, N, dim, g, cell, cstart, items, s.prm.d2, nullptr,
+                                                      rp64, s.csr_col);
+  MTS_LAUNCH_CHECK();
+  MTS_HIP(hipStreamSynchronize(st));
+  for (void *q : {(void *)cell, (void *)count, (void *)fill, (void *)count64, (void *)cstart,
+                  (void *)items, (void *)rowlen, (void *)rp64})
+    ar.release(q);
+
+  std::vector<int32_t> rows(N);
+  for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
+  build_sell(s, s.sell, rows, nullptr);
+}
+
+void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full) {
+  hipStream_t st = s.stream;
+  DeviceArena &ar = s.arena;
+  out.n_rows = (int64_t)rows_host.size();
+  out.n_slices = (out.n_rows + WAVE - 1) / WAVE;
+  int64_t ns = out.n_slices;
+  out.rows = ar.alloc<int32_t>(out.n_rows);
+  if (out.n_rows)
+    MTS_HIP(hipMemcpyAsync(out.rows, rows_host.data(), sizeof(int32_t) * out.n_rows, hipMemcpyHostToDevice, st));
+  out.width = ar.alloc<int32_t>(ns);
+  if (ns) {
+    k_slice_width<<<blocks_for(ns), kThreads, 0, st>>>(out.rows, out.n_rows, s.rp, out.width, ns);
+    MTS_LAUNCH_CHECK();
+  }
+  std::vector<int32_t> w(ns);
+  if (ns) MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  std::vector<int64_t> so(ns + 1), wo(ns + 1);
+  so[0] = wo[0] = 0;
+  int maxw = 0;
+  for (int64_t q = 0; q < ns; q++) {
+    so[q + 1] = so[q] + (int64_t)w[q] * WAVE;
+    wo[q + 1] = wo[q] + w[q];
+    maxw = std::max(maxw, w[q]);
+  }
+  out.n_slots = so[ns];
+  out.n_words = wo[ns];
+  out.slot_off = ar.alloc<int64_t>(ns + 1);
+  out.word_off = ar.alloc<int64_t>(ns + 1);
+  MTS_HIP(hipMemcpyAsync(out.slot_off, so.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(out.word_off, wo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+  out.col = ar.alloc<int32_t>(out.n_slots);
+  out.mask = ar.alloc<uint64_t>(out.n_words);
+  if (ns) {
+    k_sell_fill<<<blocks_for(ns * WAVE), kThreads, 0, st>>>(out.rows, out.n_rows, s.rp, s.csr_col, out.width,
+                                                            out.slot_off, out.col);
+    MTS_LAUNCH_CHECK();
+    Cracks cr{};
+    cr.n = s.p.n_cracks;
+    for (int c = 0; c < cr.n; c++)
+      for (int q = 0; q < 3; q++) cr.c[c][q] = s.p.cracks[c][q];
+    dim3 grid((unsigned)((maxw + 63) / 64), (unsigned)ns);
+    if (maxw > 0) {
+      k_sell_mask<<<grid, 64, 0, st>>>(out.rows, out.n_rows, ns, s.rp, s.csr_col, out.width, out.word_off,
+                                       out.mask, s.x, s.N, s.dim, cr, src_mask_full, s.sell.word_off);
+      MTS_LAUNCH_CHECK();
+    }
+  }
+  MTS_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace mts

@@ -1,0 +1,604 @@
+// C-ABI of the mtspd library: problem validation, solver construction, the
+// macro-step driver (Algorithm 1), state access and per-kernel timing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace mts {
+
+void DeviceArena::release(void *p) {
+  for (size_t k = 0; k < blocks.size(); k++)
+    if (blocks[k] == p) {
+      (void)hipFree(p);
+      blocks.erase(blocks.begin() + (long)k);
+      return;
+    }
+}
+
+void DeviceArena::free_all() {
+  for (void *p : blocks) (void)hipFree(p);
+  blocks.clear();
+  bytes = 0;
+}
+
+void Solver::prof_begin(int k, hipEvent_t *e0) {
+  *e0 = nullptr;
+  if (!profiling) return;
+  hipEvent_t e;
+  if (!ev_pool.empty()) {
+    e = ev_pool.back();
+    ev_pool.pop_back();
+  } else {
+    MTS_HIP(hipEventCreate(&e));
+  }
+  MTS_HIP(hipEventRecord(e, stream));
+  *e0 = e;
+  (void)k;
+}
+
+void Solver::prof_end(int k, hipEvent_t e0) {
+  if (!profiling || !e0) return;
+  hipEvent_t e;
+  if (!ev_pool.empty()) {
+    e = ev_pool.back();
+    ev_pool.pop_back();
+  } else {
+    MTS_HIP(hipEventCreate(&e));
+  }
+  MTS_HIP(hipEventRecord(e, stream));
+  ev_pending[k].push_back({e0, e});
+}
+
+void Solver::prof_collect() {
+  for (int k = 0; k < MTS_KT_COUNT; k++) {
+    for (auto &pr : ev_pending[k]) {
+      MTS_HIP(hipEventSynchronize(pr.second));
+      float ms = 0.f;
+      MTS_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      kt_ms[k] += ms;
+      kt_count[k]++;
+      ev_pool.push_back(pr.first);
+      ev_pool.push_back(pr.second);
+    }
+    ev_pending[k].clear();
+  }
+}
+
+namespace {
+
+thread_local char g_err[1024];
+
+// int_0^delta r^n exp(-r/l) dr in closed form.
+double exp_moment(int n, double delta, double l) {
+  double t = delta / l, term = 1.0, sum = 1.0, fact = 1.0;
+  for (int k = 1; k <= n; k++) {
+    term = term * t / (double)k;
+    sum = sum + term;
+    fact = fact * (double)k;
+  }
+  return std::pow(l, (double)(n + 1)) * fact * (1.0 - std::exp(-t) * sum);
+}
+
+void validate(const mts_problem *p) {
+  if (!p) throw ArgError{"null problem"};
+  if (p->dim != 2 && p->dim != 3) throw ArgError{"dim must be 2 or 3"};
+  if (p->mode != MTS_COUPLED && p->mode != MTS_PURE_PD) throw ArgError{"unknown mode"};
+  if (p->precision != MTS_FP64 && p->precision != MTS_MIXED) throw ArgError{"unknown precision"};
+  if (p->m < 1) throw ArgError{"m must be >= 1"};
+  if (!(p->dt_pd > 0.0) || !std::isfinite(p->dt_pd)) throw ArgError{"dt_pd must be > 0"};
+  if (!(p->horizon_factor >= 1.0)) throw ArgError{"horizon_factor must be >= 1"};
+  if (!(p->dx > 0.0)) throw ArgError{"dx must be > 0"};
+  if (p->n_pd <= 0 || !p->host_pd_pos) throw ArgError{"no PD nodes"};
+  if (p->n_pd >= ((int64_t)1 << 31)) throw ArgError{"too many PD nodes"};
+  if (p->n_cracks < 0 || p->n_cracks > 8) throw ArgError{"n_cracks must be 0..8"};
+  if (p->dim == 3 && p->n_cracks > 0) throw ArgError{"cracks are supported in 2D only"};
+  if (!(p->E > 0.0) || !(p->rho > 0.0) || !(p->thickness > 0.0)) throw ArgError{"E, rho, thickness must be > 0"};
+  if (!(p->s_crit > 0.0) && !(p->G0 > 0.0)) throw ArgError{"need s_crit > 0 or G0 > 0"};
+  if (p->kernel != MTS_K_PMB && p->kernel != MTS_K_EXP) throw ArgError{"unknown kernel"};
+  if (p->kernel == MTS_K_EXP && !(p->l_over_delta > 0.0)) throw ArgError{"l_over_delta must be > 0"};
+  if (p->mode == MTS_COUPLED) {
+    for (int a = 0; a < p->dim; a++)
+      if (p->fe_n[a] < 1) throw ArgError{"coupled mode needs fe_n >= 1 on every axis"};
+    if (!(p->fe_h > 0.0) || !(p->overlap > 0.0)) throw ArgError{"coupled mode needs fe_h > 0 and overlap > 0"};
+    if (p->weight_kind < 0 || p->weight_kind > 2) throw ArgError{"unknown weight_kind"};
+  }
+  for (int64_t i = 0; i < p->n_pd * p->dim; i++)
+    if (!std::isfinite(p->host_pd_pos[i])) throw ArgError{"non-finite node position"};
+}
+
+// Scalar parameters of the method (Eq. 2 calibration, critical stretch, steps).
+void derive_params(Solver &s) {
+  const mts_problem &p = s.p;
+  Params &P = s.prm;
+  const double pi = 3.14159265358979323846;
+  P.dim = p.dim;
+  P.weight_kind = p.weight_kind;
+  P.kernel = p.kernel;
+  P.coupled = p.mode == MTS_COUPLED ? 1 : 0;
+  P.delta = p.horizon_factor * p.dx;
+  P.d2 = P.delta * P.delta;
+  P.V = p.dim == 2 ? p.dx * p.dx * p.thickness : p.dx * p.dx * p.dx;
+  P.VV = P.V * P.V;
+  const double dl = P.delta, E = p.E;
+  double I6, I7;
+  if (p.kernel == MTS_K_EXP) {
+    P.lexp = dl * p.l_over_delta;
+    P.c0 = p.dim == 2 ? 3.0 * E / (pi * p.thickness * exp_moment(5, dl, P.lexp))
+                      : 3.0 * E / (pi * exp_moment(6, dl, P.lexp));
+    I6 = P.c0 * exp_moment(6, dl, P.lexp);
+    I7 = P.c0 * exp_moment(7, dl, P.lexp);
+  } else {
+    P.lexp = 1.0;
+    P.c0 = p.dim == 2 ? 9.0 * E / (pi * p.thickness * dl * dl * dl) : 12.0 * E / (pi * dl * dl * dl * dl);
+    I6 = P.c0 * dl * dl * dl * dl / 4.0;
+    I7 = P.c0 * dl * dl * dl * dl * dl / 5.0;
+  }
+  if (p.s_crit > 0.0) P.scrit = p.s_crit;
+  else if (p.dim == 2) P.scrit = std::sqrt(p.G0 / (p.thickness * I6));
+  else P.scrit = std::sqrt(2.0 * p.G0 / (pi * I7));
+  P.dtP = p.dt_pd;
+  P.hdtP = 0.5 * P.dtP;
+  P.hdt2P = 0.5 * P.dtP * P.dtP;
+  P.dtF = (double)p.m * P.dtP;
+  P.hdtF = 0.5 * P.dtF;
+  P.hdt2F = 0.5 * P.dtF * P.dtF;
+  for (int a = 0; a < 3; a++) {
+    P.o2lo[a] = 0.0;
+    P.o2hi[a] = 0.0;
+  }
+  for (int a = 0; a < p.dim; a++) {
+    double tol = 1e-9 * (p.dom_hi[a] - p.dom_lo[a]);
+    P.o2lo[a] = p.pd_lo[a] + (std::fabs(p.pd_lo[a] - p.dom_lo[a]) > tol ? p.overlap : 0.0);
+    P.o2hi[a] = p.pd_hi[a] - (std::fabs(p.pd_hi[a] - p.dom_hi[a]) > tol ? p.overlap : 0.0);
+  }
+  P.overlap = p.overlap;
+  P.rho = p.rho;
+}
+
+void create_impl(const mts_problem *pin, void *stream, Solver *s) {
+  validate(pin);
+  s->p = *pin;
+  const int dim = s->dim = pin->dim;
+  const int64_t N = s->N = pin->n_pd;
+  s->pos.assign(pin->host_pd_pos, pin->host_pd_pos + N * dim);
+  s->p.host_pd_pos = nullptr;
+  s->stream = (hipStream_t)stream;
+  s->precision = pin->precision;
+  s->breaking = pin->breaking != 0;
+  s->m = pin->m;
+  derive_params(*s);
+  DeviceArena &ar = s->arena;
+  hipStream_t st = s->stream;
+  // positions, SoA
+  s->x = ar.alloc<double>((size_t)dim * N);
+  {
+    std::vector<double> soa((size_t)dim * N);
+    for (int64_t i = 0; i < N; i++)
+      for (int d = 0; d < dim; d++) soa[(size_t)d * N + i] = s->pos[(size_t)i * dim + d];
+    MTS_HIP(hipMemcpyAsync(s->x, soa.data(), sizeof(double) * dim * N, hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
+  s->alpha = ar.alloc<double>(N);
+  s->mass = ar.alloc<double>(N);
+  s->u[0] = ar.alloc<double>((size_t)dim * N);
+  s->u[1] = ar.alloc<double>((size_t)dim * N);
+  s->v = ar.alloc<double>((size_t)dim * N);
+  s->a = ar.alloc<double>((size_t)dim * N);
+  s->damage = ar.alloc<double>(N);
+  for (double *q : {s->u[0], s->u[1], s->v, s->a}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * dim * N, st));
+  MTS_HIP(hipMemsetAsync(s->damage, 0, sizeof(double) * N, st));
+  s->region_flag = ar.alloc<int32_t>(1);
+  MTS_HIP(hipMemsetAsync(s->region_flag, 0, sizeof(int32_t), st));
+  build_neighbors(*s);
+  pd_setup(*s);
+  if (pin->mode == MTS_COUPLED) {
+    fe_setup(*s);
+    coupling_setup(*s);
+  }
+  pd_predict_all(*s);
+  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, sizeof(int32_t), hipHostMallocDefault));
+  pd_damage(*s);
+  MTS_HIP(hipStreamSynchronize(st));
+}
+
+mts_status fail_from_exception() {
+  try {
+    throw;
+  } catch (const HipError &e) {
+    std::snprintf(g_err, sizeof g_err, "HIP error %d (%s) in %s at %s:%d", (int)e.err, hipGetErrorString(e.err),
+                  e.expr, e.file, e.line);
+    return MTS_EDEVICE;
+  } catch (const ArgError &e) {
+    std::snprintf(g_err, sizeof g_err, "%s", e.msg.c_str());
+    return MTS_EINVAL;
+  } catch (const MemError &e) {
+    std::snprintf(g_err, sizeof g_err, "%s", e.msg.c_str());
+    return MTS_ENOMEM;
+  } catch (const std::bad_alloc &) {
+    std::snprintf(g_err, sizeof g_err, "host allocation failed");
+    return MTS_ENOMEM;
+  } catch (...) {
+    std::snprintf(g_err, sizeof g_err, "unexpected internal error");
+    return MTS_EDEVICE;
+  }
+}
+
+__global__ void k_soa_to_aos(const double *src, double *dst, int64_t N, int dim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < dim; d++) dst[i * dim + d] = src[(int64_t)d * N + i];
+}
+
+__global__ void k_aos_to_soa(const double *src, double *dst, int64_t N, int dim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < dim; d++) dst[(int64_t)d * N + i] = src[i * dim + d];
+}
+
+__global__ void k_nonfinite(const double *a, int64_t n, int32_t *flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(a[i])) flag[0] = 1;
+}
+
+void check_finite(Solver &s) {
+  int32_t *f = s.arena.alloc<int32_t>(1);
+  MTS_HIP(hipMemsetAsync(f, 0, sizeof(int32_t), s.stream));
+  int64_t n = (int64_t)s.dim * s.N;
+  k_nonfinite<<<(unsigned)((n + 255) / 256), 256, 0, s.stream>>>(s.v, n, f);
+  MTS_LAUNCH_CHECK();
+  int32_t h = 0;
+  MTS_HIP(hipMemcpyAsync(&h, f, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  MTS_HIP(hipStreamSynchronize(s.stream));
+  s.arena.release(f);
+  if (h) s.unstable = true;
+}
+
+void advance_impl(Solver &s, int64_t n) {
+  const bool coupled = s.p.mode == MTS_COUPLED;
+  for (int64_t k = 0; k < n; k++) {
+    if (coupled) {
+      hipEvent_t e0 = nullptr;
+      s.prof_begin(MTS_KT_FE, &e0);
+      fe_free_step(s);
+      s.prof_end(MTS_KT_FE, e0);
+    }
+    for (int j = 1; j <= s.m; j++) pd_substep(s, j);
+    if (coupled) {
+      coupling_solve_and_correct(s);
+      if (s.m >= 2) {
+        // Algorithm 1, last step: rebuild the unit-load responses when a bond
+        // inside their support broke during this macro step.
+        MTS_HIP(hipMemcpyAsync(s.pinned_flag, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+        MTS_HIP(hipStreamSynchronize(s.stream));
+        if (*s.pinned_flag) {
+          MTS_HIP(hipMemsetAsync(s.region_flag, 0, sizeof(int32_t), s.stream));
+          coupling_rebuild(s);
+          s.n_rebuilds++;
+        }
+      }
+    }
+    s.macro_steps++;
+  }
+}
+
+int64_t qsize(Solver &s, int what) {
+  switch (what) {
+    case MTS_PD_U: case MTS_PD_V: case MTS_PD_A: return s.N * s.dim;
+    case MTS_FE_U: case MTS_FE_V: case MTS_FE_A: case MTS_FE_X: return s.nfe * s.dim;
+    case MTS_DAMAGE: case MTS_PD_ALPHA: case MTS_PD_MASS: return s.N;
+    case MTS_LAMBDA: return s.nl;
+    case MTS_FE_MASS: return s.nfe;
+    case MTS_CONSTRAINT_NODES: return s.nc;
+    case MTS_H: return s.Hcopy ? s.nl * s.nl : -1;
+    default: return -1;
+  }
+}
+
+}  // namespace
+}  // namespace mts
+
+using namespace mts;
+
+struct mts_solver {
+  Solver s;
+};
+
+extern "C" {
+
+const char *mts_last_error(void) { return g_err; }
+
+const char *mts_status_str(mts_status st) {
+  switch (st) {
+    case MTS_OK: return "ok";
+    case MTS_EINVAL: return "invalid argument";
+    case MTS_ENOMEM: return "out of memory";
+    case MTS_EDEVICE: return "device error";
+    case MTS_EUNSTABLE: return "unstable (non-finite state)";
+    case MTS_EAGAIN: return "try again";
+    case MTS_ETOOBIG: return "request too big";
+    case MTS_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
+  try {
+    if (!out) throw ArgError{"null output"};
+    validate(p);
+    std::memset(out, 0, sizeof *out);
+    const double hf = p->horizon_factor;
+    // lattice family size for this horizon (upper estimate for near-lattice inputs)
+    int64_t fam = 0;
+    int r = (int)std::floor(hf + 0.01);
+    for (int c = (p->dim == 3 ? -r : 0); c <= (p->dim == 3 ? r : 0); c++)
+      for (int b = -r; b <= r; b++)
+        for (int a = -r; a <= r; a++)
+          if ((a || b || c) && (double)(a * a + b * b + c * c) <= (hf + 0.01) * (hf + 0.01)) fam++;
+    out->n_pd = p->n_pd;
+    out->nnz_estimate = p->n_pd * fam;
+    int64_t nfe = 0, ne = 0;
+    if (p->mode == MTS_COUPLED) {
+      nfe = (int64_t)(p->fe_n[0] + 1) * (p->fe_n[1] + 1) * (p->dim == 3 ? p->fe_n[2] + 1 : 1);
+      ne = (int64_t)p->fe_n[0] * p->fe_n[1] * (p->dim == 3 ? p->fe_n[2] : 1);
+      nfe += p->fe_n[0] + 1;
+    }
+    out->n_fe_nodes = nfe;
+    // constraint estimate: nodes within `overlap` of the PD box faces
+    int64_t nc = 0;
+    if (p->mode == MTS_COUPLED) {
+      double vol_in = 1.0, vol = 1.0;
+      for (int a = 0; a < p->dim; a++) {
+        double L = p->pd_hi[a] - p->pd_lo[a];
+        vol *= L;
+        vol_in *= std::max(0.0, L - 2 * p->overlap);
+      }
+      nc = (int64_t)std::ceil(p->n_pd * (1.0 - vol_in / vol)) + 64;
+    }
+    out->n_constraints_estimate = nc;
+    int64_t nl = nc * p->dim;
+    int64_t rhs = p->dim == 2 ? 8 : 6;
+    int64_t bytes = out->nnz_estimate * (4 + 4 + 1) + p->n_pd * (8 * (6 * p->dim + 6) + 16);
+    if (p->mode == MTS_COUPLED) {
+      bytes += nl * nl * 8 + nl * 64 * 16 + ne * 8 * 8 * 4 + nfe * 8 * 12 + 4 * rhs * p->dim * p->n_pd * 8;
+      bytes += out->nnz_estimate * 5;
+    }
+    out->device_bytes_estimate = bytes;
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_create(const mts_problem *p, void *hip_stream, mts_solver **out) {
+  if (!out) {
+    std::snprintf(g_err, sizeof g_err, "null output pointer");
+    return MTS_EINVAL;
+  }
+  *out = nullptr;
+  mts_solver *h = nullptr;
+  try {
+    h = new mts_solver();
+    create_impl(p, hip_stream, &h->s);
+    *out = h;
+    return MTS_OK;
+  } catch (...) {
+    mts_status st = fail_from_exception();
+    if (h) {
+      (void)hipStreamSynchronize(h->s.stream);
+      (void)hipGetLastError();
+      if (h->s.pinned_flag) (void)hipHostFree(h->s.pinned_flag);
+      h->s.arena.free_all();
+      delete h;
+    }
+    return st;
+  }
+}
+
+mts_status mts_advance(mts_solver *h, int64_t n) {
+  if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
+  if (n < 0) return (std::snprintf(g_err, sizeof g_err, "negative step count"), MTS_EINVAL);
+  if (h->s.unstable) return (std::snprintf(g_err, sizeof g_err, "solver is unstable"), MTS_EUNSTABLE);
+  try {
+    advance_impl(h->s, n);
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_sync(mts_solver *h) {
+  if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
+  try {
+    MTS_HIP(hipStreamSynchronize(h->s.stream));
+    check_finite(h->s);
+    if (h->s.unstable) {
+      std::snprintf(g_err, sizeof g_err, "non-finite PD velocity");
+      return MTS_EUNSTABLE;
+    }
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_read(mts_solver *h, int32_t what, double *out, int64_t cap, int64_t *n) {
+  if (!h || !out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  try {
+    Solver &s = h->s;
+    int64_t sz = qsize(s, what);
+    if (sz < 0) throw ArgError{"quantity not available"};
+    if (cap < sz) throw ArgError{"output capacity too small"};
+    if (n) *n = sz;
+    if (sz == 0) return MTS_OK;
+    hipStream_t st = s.stream;
+    const double *src = nullptr;
+    double *tmp = nullptr;
+    switch (what) {
+      case MTS_PD_U: case MTS_PD_V: case MTS_PD_A: {
+        const double *soa = what == MTS_PD_U ? s.u[s.cur] : (what == MTS_PD_V ? s.v : s.a);
+        tmp = s.arena.alloc<double>(sz);
+        k_soa_to_aos<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(soa, tmp, s.N, s.dim);
+        MTS_LAUNCH_CHECK();
+        src = tmp;
+        break;
+      }
+      case MTS_FE_U: src = s.uF; break;
+      case MTS_FE_V: src = s.vF; break;
+      case MTS_FE_A: src = s.aF; break;
+      case MTS_FE_X: src = s.xF; break;
+      case MTS_FE_MASS: src = s.mF; break;
+      case MTS_DAMAGE: pd_damage(s); src = s.damage; break;
+      case MTS_PD_ALPHA: src = s.alpha; break;
+      case MTS_PD_MASS: src = s.mass; break;
+      case MTS_LAMBDA: src = s.lam0; break;
+      case MTS_H: src = s.Hcopy; break;
+      case MTS_CONSTRAINT_NODES:
+        for (int64_t q = 0; q < s.nc; q++) out[q] = (double)s.h_cn[q];
+        return MTS_OK;
+      default: throw ArgError{"unknown quantity"};
+    }
+    MTS_HIP(hipMemcpyAsync(out, src, sizeof(double) * sz, hipMemcpyDeviceToHost, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    if (tmp) s.arena.release(tmp);
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_write(mts_solver *h, int32_t what, const double *in, int64_t n) {
+  if (!h || !in) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  try {
+    Solver &s = h->s;
+    hipStream_t st = s.stream;
+    if (what == MTS_PD_U || what == MTS_PD_V || what == MTS_PD_A) {
+      if (n != s.N * s.dim) throw ArgError{"size mismatch"};
+      double *tmp = s.arena.alloc<double>(n);
+      MTS_HIP(hipMemcpyAsync(tmp, in, sizeof(double) * n, hipMemcpyHostToDevice, st));
+      double *dst = what == MTS_PD_U ? s.u[s.cur] : (what == MTS_PD_V ? s.v : s.a);
+      k_aos_to_soa<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(tmp, dst, s.N, s.dim);
+      MTS_LAUNCH_CHECK();
+      pd_predict_all(s);
+      MTS_HIP(hipStreamSynchronize(st));
+      s.arena.release(tmp);
+      return MTS_OK;
+    }
+    double *dst = nullptr;
+    int64_t want = 0;
+    switch (what) {
+      case MTS_FE_U: dst = s.uF; want = s.nfe * s.dim; break;
+      case MTS_FE_V: dst = s.vF; want = s.nfe * s.dim; break;
+      case MTS_FE_A: dst = s.aF; want = s.nfe * s.dim; break;
+      case MTS_LAMBDA: dst = s.lam0; want = s.nl; break;
+      default: throw ArgError{"quantity cannot be written"};
+    }
+    if (!dst || n != want) throw ArgError{"size mismatch or quantity not present"};
+    MTS_HIP(hipMemcpyAsync(dst, in, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_read_bonds(mts_solver *h, int64_t *row_ptr, int32_t *col, uint8_t *intact, int64_t cap,
+                          int64_t *nnz) {
+  if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
+  try {
+    Solver &s = h->s;
+    if (nnz) *nnz = s.nnz;
+    if ((col || intact) && cap < s.nnz) throw ArgError{"capacity too small"};
+    hipStream_t st = s.stream;
+    if (row_ptr) {
+      std::vector<int32_t> rp(s.N + 1);
+      MTS_HIP(hipMemcpyAsync(rp.data(), s.rp, sizeof(int32_t) * (s.N + 1), hipMemcpyDeviceToHost, st));
+      MTS_HIP(hipStreamSynchronize(st));
+      for (int64_t i = 0; i <= s.N; i++) row_ptr[i] = rp[i];
+    }
+    if (col) MTS_HIP(hipMemcpyAsync(col, s.csr_col, sizeof(int32_t) * s.nnz, hipMemcpyDeviceToHost, st));
+    if (intact) {
+      uint8_t *tmp = s.arena.alloc<uint8_t>(s.nnz);
+      bonds_to_csr_state(s, tmp);
+      MTS_HIP(hipMemcpyAsync(intact, tmp, s.nnz, hipMemcpyDeviceToHost, st));
+      MTS_HIP(hipStreamSynchronize(st));
+      s.arena.release(tmp);
+    }
+    MTS_HIP(hipStreamSynchronize(st));
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_query(mts_solver *h, mts_info *o) {
+  if (!h || !o) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  Solver &s = h->s;
+  std::memset(o, 0, sizeof *o);
+  o->delta = s.prm.delta;
+  o->volume = s.prm.V;
+  o->c0 = s.prm.c0;
+  o->s_crit = s.prm.scrit;
+  o->dt_pd = s.prm.dtP;
+  o->dt_fe = s.prm.dtF;
+  o->n_pd = s.N;
+  o->nnz = s.nnz;
+  o->n_fe_nodes = s.nfe;
+  o->n_fe_elems = s.ne;
+  o->n_constraints = s.nc;
+  o->n_region = s.n_region;
+  o->pd_steps = s.pd_steps;
+  o->macro_steps = s.macro_steps;
+  o->n_rebuilds = s.n_rebuilds;
+  o->n_colors = s.n_colors;
+  o->device_bytes = (int64_t)s.arena.bytes;
+  o->dim = s.dim;
+  o->precision = s.precision;
+  return MTS_OK;
+}
+
+mts_status mts_profile(mts_solver *h, int32_t enable) {
+  if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
+  try {
+    h->s.prof_collect();
+    h->s.profiling = enable != 0;
+    for (int k = 0; k < MTS_KT_COUNT; k++) {
+      h->s.kt_ms[k] = 0.0;
+      h->s.kt_count[k] = 0;
+    }
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_kernel_time(mts_solver *h, int32_t kernel, int64_t *launches, double *total_ms) {
+  if (!h || kernel < 0 || kernel >= MTS_KT_COUNT) return (std::snprintf(g_err, sizeof g_err, "bad argument"), MTS_EINVAL);
+  try {
+    h->s.prof_collect();
+    if (launches) *launches = h->s.kt_count[kernel];
+    if (total_ms) *total_ms = h->s.kt_ms[kernel];
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+void mts_destroy(mts_solver *h) {
+  if (!h) return;
+  Solver &s = h->s;
+  (void)hipStreamSynchronize(s.stream);
+  for (int k = 0; k < MTS_KT_COUNT; k++)
+    for (auto &pr : s.ev_pending[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
+  if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
+  s.arena.free_all();
+  delete h;
+}
+
+}  // extern "C"

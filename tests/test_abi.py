@@ -1,0 +1,76 @@
+"""The C-ABI library loads and exports every symbol the header declares (CPU;
+no compute calls), plus host-side error paths that need no device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mts_inputs as mi
+import paper_2403_03605_amd as mts
+from paper_2403_03605_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mtspd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mts_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert _declared() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = C.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """sizeof/offsetof of the C structs, as the host C compiler lays them out,
+    equal the ctypes mirrors used by the binding."""
+    checks = []
+    for cname, cls in (("mts_problem", _lib.Problem), ("mts_info", _lib.Info), ("mts_plan_info", _lib.PlanInfo)):
+        checks.append((f"sizeof({cname})", C.sizeof(cls)))
+        for fname, _ in cls._fields_:
+            checks.append((f"offsetof({cname}, {fname})", getattr(cls, fname).offset))
+    body = "\n".join(f'  printf("%zu\\n", (size_t){e});' for e, _ in checks)
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mtspd.h"\nint main(void){\n' + body + "\n  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == [v for _, v in checks]
+
+
+def test_plan_and_validation_on_host():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    inst = mi.config(0)
+    pl = mts.plan(inst)
+    assert pl["n_pd"] == 1000
+    assert pl["nnz_estimate"] >= 25516
+    assert pl["device_bytes_estimate"] > 0
+    bad = dict(inst, m=0)
+    with pytest.raises(mts.MtsError) as e:
+        mts.plan(bad)
+    assert e.value.status == _lib.EINVAL
+    bad = dict(inst, dt_pd=-1.0)
+    with pytest.raises(mts.MtsError):
+        mts.plan(bad)
+    bad = dict(inst, dim=4)
+    with pytest.raises(mts.MtsError):
+        mts.plan(bad)
+    lib = _lib.load()
+    assert lib.mts_status_str(_lib.EINVAL) == b"invalid argument"
+    lib.mts_destroy(None)
+    h = C.c_void_p()
+    assert lib.mts_create(None, None, C.byref(h)) == _lib.EINVAL
+    assert h.value is None

@@ -1,0 +1,154 @@
+"""Parity of the HIP library (through the C-ABI) with the oracle, on the GPU."""
+import numpy as np
+import pytest
+
+import mts_inputs as mi
+from oracle import Oracle
+import oracle.oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mts():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_03605_amd as m
+    m.load()
+    return m
+
+
+def _rel(g, w):
+    g = np.asarray(g, float)
+    w = np.asarray(w, float)
+    return np.abs(g - w).max() / max(np.abs(w).max(), 1e-300)
+
+
+def _instances():
+    a = mi.config(0)
+    b = mi.plate2d(40, 4, 8, 4e-8, perturb=1e-6, seed=11, name="plate40")
+    c = mi.block3d(12, 12, 12, 2, 4, 1e-8, perturb=1e-6, seed=12, mode="pure_pd", name="cube12")
+    d = mi.plate2d(30, 2, 4, 1e-8, perturb=1e-6, seed=13, mode="pure_pd", name="pure30")
+    e = mi.block3d(12, 12, 6, 2, 4, 1e-8, perturb=1e-6, seed=14, name="block12")
+    return [a, b, c, d, e]
+
+
+@pytest.mark.parametrize("inst", _instances(), ids=lambda x: x["name"])
+def test_bonds_bitexact(mts, inst):
+    """CSR neighbour lists and initial bond states are identical to the oracle."""
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    rp, col, mu = s.bonds()
+    rpo, colo, muo = o.bonds()
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(col, colo)
+    assert np.array_equal(mu, muo)
+
+
+@pytest.mark.parametrize("inst", _instances(), ids=lambda x: x["name"])
+def test_setup_quantities(mts, inst):
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    gi, oi = s.query(), o.info()
+    for k in ("delta", "c0", "s_crit", "dt_pd", "dt_fe"):
+        assert gi[k] == pytest.approx(oi[k], rel=1e-15), k
+    for k in ("n_pd", "nnz", "n_constraints"):
+        assert gi[k] == oi[k], k
+    assert _rel(s.read(mts.PD_ALPHA), o.get(O.PD_ALPHA)) <= 1e-15
+    assert _rel(s.read(mts.PD_MASS), o.get(O.PD_MASS)) <= 1e-15
+    if inst["mode"] == "coupled":
+        assert gi["n_fe_nodes"] == oi["n_fe_nodes"]
+        assert _rel(s.read(mts.FE_MASS), o.get(O.FE_MASS)) <= 1e-14
+        assert _rel(s.read(mts.FE_X), o.get(O.FE_X)) == 0.0
+        assert np.array_equal(s.read(mts.CONSTRAINT_NODES), o.get(O.CONSTRAINT_NODES))
+        assert _rel(s.read(mts.FE_A), o.get(O.FE_A)) <= 1e-14
+
+
+@pytest.mark.parametrize("inst", [i for i in _instances() if i["mode"] == "coupled"], ids=lambda x: x["name"])
+def test_multiplier_matrix(mts, inst):
+    """H of Eq. 49 from the coloured link runs equals the oracle's column-by-column H."""
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    Hg, Ho = s.read(mts.H), o.get(O.H)
+    assert Hg.shape == Ho.shape
+    assert _rel(Hg, Ho) <= 1e-13
+
+
+def _run_pair(mts, inst, n_macro, tol, check_every=1):
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    worst = 0.0
+    for k in range(0, n_macro, check_every):
+        s.advance(check_every)
+        o.advance(check_every)
+        if o.info()["n_broken"] > 0:
+            break
+        for gq, oq in ((mts.PD_U, O.PD_U), (mts.PD_V, O.PD_V)):
+            e = _rel(s.read(gq), o.get(oq))
+            worst = max(worst, e)
+            assert e <= tol, (k, gq, e)
+        if inst["mode"] == "coupled":
+            for gq, oq in ((mts.FE_U, O.FE_U), (mts.FE_V, O.FE_V), (mts.LAMBDA, O.LAMBDA)):
+                e = _rel(s.read(gq), o.get(oq))
+                worst = max(worst, e)
+                assert e <= tol, (k, gq, e)
+    s.sync()
+    return s, o, worst
+
+
+def test_pure_pd_trajectory(mts):
+    inst = mi.plate2d(30, 1, 300, 1e-7, perturb=1e-6, seed=21, mode="pure_pd", traction=20e6, name="pure30")
+    s, o, worst = _run_pair(mts, inst, 300, 1e-10, check_every=25)
+    print("pure PD worst rel diff before first break", worst)
+
+
+def test_coupled_trajectory_before_break(mts):
+    inst = mi.config(0)
+    s, o, worst = _run_pair(mts, inst, inst["n_macro"], 1e-10)
+    print("coupled C1 worst rel diff before first break", worst)
+
+
+def _tip(pos, phi, thresh=0.35):
+    idx = np.where(phi >= thresh)[0]
+    if idx.size == 0:
+        return None
+    j = idx[np.argmax(pos[idx, 0])]
+    return pos[j]
+
+
+def test_coupled_crack_tip_after_breaking(mts):
+    """After bonds break, the crack tip (largest x with damage >= 0.35) stays
+    within one grid spacing of the oracle's at every macro step."""
+    inst = mi.config(0)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    pos = inst["pos"]
+    for k in range(inst["n_macro"]):
+        s.advance(1)
+        o.advance(1)
+        tg, to = _tip(pos, s.read(mts.DAMAGE)), _tip(pos, o.get(O.DAMAGE))
+        assert (tg is None) == (to is None)
+        if tg is not None:
+            assert np.linalg.norm(tg - to) <= inst["dx"] * (1 + 1e-9), k
+    _, _, mug = s.bonds()
+    _, _, muo = o.bonds()
+    print("broken (oracle)", o.info()["n_broken"], "differing bond states", int((mug != muo).sum()))
+    assert o.info()["n_broken"] > 0
+
+
+def test_velocity_continuity_on_device(mts):
+    inst = mi.config(0, n_pd_steps=80)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    s.advance(inst["n_macro"])
+    # G_F, G_P from the oracle's description of the constraint set
+    W = o.get(O.GF).reshape(-1, 4)
+    nodes = o.get(O.GF_NODES).reshape(-1, 4).astype(int)
+    cn = o.get(O.CONSTRAINT_NODES).astype(int)
+    vF, vP = s.read(mts.FE_V), s.read(mts.PD_V)
+    r = (W[:, :, None] * vF[nodes]).sum(1) - vP[cn]
+    assert np.abs(r).max() <= 1e-12 * np.abs(vP).max()
