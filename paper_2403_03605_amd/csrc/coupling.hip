@@ -67,12 +67,16 @@ __global__ void k_gf(int64_t nc, int dim, int nen, const int32_t *cn, const doub
   }
 }
 
+// Link region: nodes within (m-1) horizons of a constraint node (the reach of
+// the unit-load responses).  layer: smallest h with a constraint within h
+// horizons (slightly generous), used to skip rows whose link state is still
+// exactly zero at a given link substep.
 __global__ void k_region(const double *x, int64_t N, int dim, const int32_t *cn, int64_t nc, double R2,
-                         uint8_t *flag) {
+                         double delta, int m, uint8_t *flag, int32_t *layer) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  uint8_t f = 0;
-  for (int64_t q = 0; q < nc && !f; q++) {
+  double best = 1e300;
+  for (int64_t q = 0; q < nc; q++) {
     int64_t c = cn[q];
     double d0 = x[i] - x[c];
     double d1 = x[N + i] - x[N + c];
@@ -81,9 +85,30 @@ __global__ void k_region(const double *x, int64_t N, int dim, const int32_t *cn,
       double d2 = x[2 * N + i] - x[2 * N + c];
       r2 = r2 + d2 * d2;
     }
-    if (r2 <= R2) f = 1;
+    best = r2 < best ? r2 : best;
   }
-  flag[i] = f;
+  flag[i] = best <= R2 ? 1 : 0;
+  int h = m;
+  for (int k = m - 1; k >= 0; k--) {
+    double hk = (double)k * delta;
+    if (best <= hk * hk * (1.0 + 1e-9)) h = k;
+  }
+  layer[i] = h;
+}
+
+__global__ void k_slice_layer(const int32_t *rows, int64_t n_rows, int64_t n_slices, int L, const int32_t *layer,
+                              int32_t *slice_layer) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices) return;
+  const int S = WAVE / L;
+  int h = 1 << 30;
+  for (int j = 0; j < S; j++) {
+    int64_t r = s * S + j;
+    if (r >= n_rows) break;
+    int v = layer[rows[r]];
+    h = v < h ? v : h;
+  }
+  slice_layer[s] = h;
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -205,7 +230,8 @@ void coupling_setup(Solver &s) {
   // link region: nodes within (m-1) horizons of a constraint node
   double Rr = (double)(s.m - 1) * s.prm.delta;
   s.in_region = ar.alloc<uint8_t>(N);
-  k_region<<<nb(N), 256, 0, st>>>(s.x, N, dim, s.cn, s.nc, Rr * Rr, s.in_region);
+  s.layer = ar.alloc<int32_t>(N);
+  k_region<<<nb(N), 256, 0, st>>>(s.x, N, dim, s.cn, s.nc, Rr * Rr, s.prm.delta, s.m, s.in_region, s.layer);
   MTS_LAUNCH_CHECK();
   std::vector<uint8_t> reg(N);
   MTS_HIP(hipMemcpyAsync(reg.data(), s.in_region, N, hipMemcpyDeviceToHost, st));
@@ -214,7 +240,14 @@ void coupling_setup(Solver &s) {
   for (int64_t i = 0; i < N; i++)
     if (reg[i]) rrows.push_back((int32_t)i);
   s.n_region = (int64_t)rrows.size();
-  build_sell(s, s.rsell, rrows, s.sell.mask);
+  build_sell(s, s.rsell, rrows, s.sell.mask, pick_lanes(s.n_region));
+  sell_coefficients(s, s.rsell);
+  s.rsell.slice_layer = ar.alloc<int32_t>(s.rsell.n_slices);
+  if (s.rsell.n_slices) {
+    k_slice_layer<<<nb(s.rsell.n_slices), 256, 0, st>>>(s.rsell.rows, s.rsell.n_rows, s.rsell.n_slices, s.rsell.L,
+                                                        s.layer, s.rsell.slice_layer);
+    MTS_LAUNCH_CHECK();
+  }
 
   // colour classes: constraints closer than 2R + 2 delta get different colours,
   // so the responses (support radius R) of one class never overlap.  This is a
@@ -298,15 +331,19 @@ void coupling_setup(Solver &s) {
   MTS_HIP(hipMemsetAsync(s.lam0, 0, sizeof(double) * s.nl, st));
   s.Hinv = ar.alloc<double>((size_t)s.nl * s.nl);
   s.keep_h = s.nl <= 4096;
-  coupling_rebuild(s);
+  for (int k = 0; k < 2; k++) {
+    s.mask_snap[k] = ar.alloc<uint64_t>(s.sell.n_words);
+    MTS_HIP(hipEventCreateWithFlags(&s.flag_event[k], hipEventDisableTiming));
+  }
+  coupling_rebuild(s, s.sell.mask);
 }
 
-// Unit-load responses on the current bond states, H, and its inverse.
-void coupling_rebuild(Solver &s) {
+// Unit-load responses on the given bond states (full-lattice layout), H, and its inverse.
+void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   const int dim = s.dim;
   hipStream_t st = s.stream;
   const int64_t nl = s.nl;
-  sell_regather_mask(s, s.rsell, s.sell.mask);
+  sell_regather_mask(s, s.rsell, full_mask);
   MTS_HIP(hipMemsetAsync(s.Hinv, 0, sizeof(double) * nl * nl, st));
   const int cpb = s.nrhs / dim;  // colours per batch
   int32_t rc[16], rd[16];

@@ -54,6 +54,7 @@ struct DeviceArena {
 };
 
 constexpr int WAVE = 64;
+constexpr int kSpareIters = 4;  // zero iterations appended to every sliced-ELL array
 
 // Scalars of one problem, passed by value to kernels.
 struct Params {
@@ -61,25 +62,40 @@ struct Params {
   int weight_kind;
   int kernel;
   int coupled;
-  double delta, d2, V, VV, c0, lexp, scrit;
+  double delta, d2, V, VV, c0, lexp, scrit, K2;  // K2 = (1 + s_crit)^2
   double dtP, hdtP, hdt2P, dtF, hdtF, hdt2F;
   double o2lo[3], o2hi[3];
   double overlap;
   double rho;
+  float K2m1f;  // (1 + s_crit)^2 - 1 in single precision (mixed-form stretch test)
 };
 
-// Sliced-ELL bond layout: slices of 64 consecutive rows (one wavefront);
-// slot k of row (slice*64 + lane) sits at col[slice_off[slice] + k*64 + lane];
-// bond states are one 64-bit word per (slice, k): bit `lane` = intact.
+// Sliced-ELL bond layout with L lanes per row: a slice is 64/L consecutive rows
+// (one wavefront).  Slot k of local row j sits at
+//   slot_off[slice] + (k / L) * 64 + j * L + k % L,
+// so iteration t = k / L of the wavefront reads 64 consecutive slots.  Bond
+// states are one 64-bit word per (slice, t), bit = lane, owned by the wavefront.
 struct Sell {
   int64_t n_rows = 0, n_slices = 0, n_slots = 0, n_words = 0;
+  int L = 1;
+  int T = 0;                     // iterations per slice (same for every slice)
   int32_t *rows = nullptr;       // row -> node id (identity for the full lattice)
-  int32_t *width = nullptr;      // per slice
+  int32_t *width = nullptr;      // per slice, slots per row rounded up to a multiple of L
   int64_t *slot_off = nullptr;   // per slice, in slots (multiple of 64)
   int64_t *word_off = nullptr;   // per slice, in mask words
   int32_t *col = nullptr;        // n_slots
   uint64_t *mask = nullptr;      // n_words
+  double *coef = nullptr;        // n_slots: w_ik c(|xi_ik|) V_i V_k (0 on padding)
+  int32_t *slice_layer = nullptr; // link region: smallest h with a row within h horizons of a constraint
+  float *coef32 = nullptr;       // mixed form: coef / m_i in single precision
 };
+
+// Lanes per row: enough wavefronts to cover the chip several times over.
+inline int pick_lanes(int64_t rows) {
+  int L = 1;
+  while (L < 8 && rows * L < ((int64_t)1 << 19)) L *= 2;
+  return L;
+}
 
 struct Solver {
   mts_problem p{};
@@ -110,6 +126,7 @@ struct Solver {
   double *damage = nullptr;
   int32_t *region_flag = nullptr;  // device flag: a bond in the link region broke
   uint8_t *in_region = nullptr;    // per node
+  int32_t *layer = nullptr;        // per node: smallest h <= m-1 within h horizons of a constraint, else m
 
   // ---- FE ----
   int nen = 4, ngp = 4, nstr = 3;
@@ -138,7 +155,6 @@ struct Solver {
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;
   Sell rsell;                    // link region rows
-  uint64_t *mask_snap = nullptr; // full-lattice copy of the bond states at the last rebuild
   double *Wu[2] = {nullptr, nullptr};
   double *Wv = nullptr, *Wa = nullptr; // dim*N (zero outside the region)
   int64_t n_colors = 0;
@@ -148,7 +164,11 @@ struct Solver {
   int32_t *rhs_color_dev = nullptr, *rhs_dir_dev = nullptr;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)
-  int32_t *pinned_flag = nullptr;
+  int32_t *pinned_flag = nullptr;  // 2 slots, host-pinned
+  uint64_t *mask_snap[2] = {nullptr, nullptr};  // full-lattice bond states at the end of a macro step
+  hipEvent_t flag_event[2] = {nullptr, nullptr};
+  bool pending = false;
+  int pending_slot = 0;
 
   // profiling
   bool profiling = false;
@@ -165,8 +185,9 @@ struct Solver {
 
 // neighbour build and bond layout (neighbors.hip)
 void build_neighbors(Solver &s);
-void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full);
+void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full, int L);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
+void sell_coefficients(Solver &s, Sell &out);
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
 // PD kernels (pd.hip)
 void pd_setup(Solver &s);
@@ -179,7 +200,7 @@ void fe_free_step(Solver &s);
 void fe_correct(Solver &s);
 // coupling (coupling.hip)
 void coupling_setup(Solver &s);
-void coupling_rebuild(Solver &s);
+void coupling_rebuild(Solver &s, const uint64_t *full_mask);
 void coupling_solve_and_correct(Solver &s);
 // dense linear algebra (dense.hip)
 void dense_spd_inverse(Solver &s, double *A, int64_t n);

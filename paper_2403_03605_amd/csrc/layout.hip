@@ -1,0 +1,270 @@
+// Sliced-ELL bond layout for the bond pass: neighbour indices, bond-state words
+// (pre-crack bonds start broken, i.e. Eq. 4 with an already-exceeded history)
+// and the per-bond coefficient w_ik c(|xi_ik|) V_i V_k of Eq. 2 with the
+// Arlequin bond weight w_ik = 1 - (alpha_i + alpha_k)/2.
+#include <algorithm>
+
+#include "device_math.h"
+
+namespace mts {
+
+namespace {
+
+constexpr int kThreads = 256;
+inline unsigned blocks_for(int64_t n, int t = kThreads) { return (unsigned)((n + t - 1) / t); }
+
+struct Cracks {
+  int n;
+  double c[8][3];
+};
+
+// Pre-crack (horizontal segment y = yc, x_start <= x* <= x_end, tip inclusive);
+// x* from the endpoint with the smaller id so both directions agree.
+__device__ inline bool crosses_crack(const double *x, int64_t N, int64_t i, int64_t k, const Cracks &cr) {
+  int64_t p = i < k ? i : k, q = i < k ? k : i;
+  double xp = x[p], yp = x[N + p], xq = x[q], yq = x[N + q];
+  for (int c = 0; c < cr.n; c++) {
+    double yc = cr.c[c][0];
+    if ((yp - yc) * (yq - yc) < 0.0) {
+      double xs = xp + (yc - yp) * (xq - xp) / (yq - yp);
+      if (xs >= cr.c[c][1] && xs <= cr.c[c][2]) return true;
+    }
+  }
+  return false;
+}
+
+__global__ void k_slice_width(const int32_t *rows, int64_t n_rows, const int32_t *rp, int L, int32_t *width,
+                              int64_t n_slices) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices) return;
+  const int S = WAVE / L;
+  int w = 0;
+  for (int j = 0; j < S; j++) {
+    int64_t r = s * S + j;
+    if (r >= n_rows) break;
+    int64_t i = rows[r];
+    int len = rp[i + 1] - rp[i];
+    w = len > w ? len : w;
+  }
+  width[s] = ((w + L - 1) / L) * L;
+}
+
+// One thread per (slice, lane).
+__global__ void k_sell_fill(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
+                            const int32_t *csr_col, int L, const int32_t *width, const int64_t *slot_off,
+                            int32_t *col) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t s = g / WAVE;
+  if (s >= n_slices) return;
+  int lane = (int)(g % WAVE);
+  const int S = WAVE / L;
+  int j = lane / L, l = lane % L;
+  int64_t r = s * S + j;
+  int T = width[s] / L;
+  int64_t i = r < n_rows ? rows[r] : -1;
+  int len = i >= 0 ? rp[i + 1] - rp[i] : 0;
+  for (int t = 0; t < T; t++) {
+    int k = t * L + l;
+    int32_t v = 0;
+    if (i >= 0) v = k < len ? csr_col[rp[i] + k] : (int32_t)i;
+    col[slot_off[s] + (int64_t)t * WAVE + lane] = v;
+  }
+}
+
+// One thread per (slice, t) word.  src_mask == nullptr: initial states from the
+// crack segments; otherwise bits gathered from the full-lattice layout.
+__global__ void k_sell_mask(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
+                            const int32_t *csr_col, int L, const int32_t *width, const int64_t *word_off,
+                            uint64_t *mask, const double *x, int64_t N, int dim, Cracks cr,
+                            const uint64_t *src_mask, const int64_t *src_word_off, int src_L) {
+  int64_t s = blockIdx.y;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices || t >= width[s] / L) return;
+  const int S = WAVE / L;
+  uint64_t word = 0;
+  for (int lane = 0; lane < WAVE; lane++) {
+    int j = lane / L, l = lane % L;
+    int64_t r = s * S + j;
+    if (r >= n_rows) break;
+    int64_t i = rows[r];
+    int len = rp[i + 1] - rp[i];
+    int k = t * L + l;
+    if (k >= len) continue;
+    bool intact;
+    if (src_mask) {
+      intact = full_bit(src_word_off, src_mask, src_L, i, k);
+    } else {
+      int64_t c = csr_col[rp[i] + k];
+      intact = !(dim == 2 && crosses_crack(x, N, i, c, cr));
+    }
+    if (intact) word |= 1ull << lane;
+  }
+  mask[word_off[s] + t] = word;
+}
+
+// Per-bond coefficient ((w_ik c(r)) V_i V_k) for the fused bond pass; the
+// mixed form stores coef / m_i in single precision.
+__global__ void k_sell_coef(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
+                            const int32_t *csr_col, int L, const int32_t *width, const int64_t *slot_off,
+                            const double *x, int64_t N, const double *alpha, const double *mass, Params P,
+                            double *coef, float *coef32) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t s = g / WAVE;
+  if (s >= n_slices) return;
+  int lane = (int)(g % WAVE);
+  const int S = WAVE / L;
+  int j = lane / L, l = lane % L;
+  int64_t r = s * S + j;
+  int T = width[s] / L;
+  int64_t i = r < n_rows ? rows[r] : -1;
+  int len = i >= 0 ? rp[i + 1] - rp[i] : 0;
+  for (int t = 0; t < T; t++) {
+    int k = t * L + l;
+    double cf = 0.0;
+    if (i >= 0 && k < len) {
+      int64_t c = csr_col[rp[i] + k];
+      double d0 = x[c] - x[i], d1 = x[N + c] - x[N + i];
+      double r2 = d0 * d0 + d1 * d1;
+      if (P.dim == 3) {
+        double d2 = x[2 * N + c] - x[2 * N + i];
+        r2 = r2 + d2 * d2;
+      }
+      double w = 1.0 - 0.5 * (alpha[i] + alpha[c]);
+      cf = ((w * cfun(P, sqrt(r2))) * P.VV);
+    }
+    int64_t pos = slot_off[s] + (int64_t)t * WAVE + lane;
+    if (coef) coef[pos] = cf;
+    if (coef32) coef32[pos] = (float)(i >= 0 ? cf / mass[i] : 0.0);
+  }
+}
+
+__global__ void k_mask_to_csr(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask, int L,
+                              uint8_t *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int len = rp[i + 1] - rp[i];
+  for (int k = 0; k < len; k++) out[rp[i] + k] = (uint8_t)full_bit(word_off, mask, L, i, k);
+}
+
+__global__ void k_damage(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask, int L,
+                         double *phi) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int len = rp[i + 1] - rp[i];
+  int cnt = 0;
+  for (int k = 0; k < len; k++) cnt += (int)full_bit(word_off, mask, L, i, k);
+  phi[i] = len > 0 ? 1.0 - (double)cnt / (double)len : 0.0;  // Eq. 5, uniform nodal volumes
+}
+
+}  // namespace
+
+void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full, int L) {
+  hipStream_t st = s.stream;
+  DeviceArena &ar = s.arena;
+  out.L = L;
+  const int S = WAVE / L;
+  out.n_rows = (int64_t)rows_host.size();
+  out.n_slices = (out.n_rows + S - 1) / S;
+  int64_t ns = out.n_slices;
+  out.rows = ar.alloc<int32_t>(out.n_rows);
+  if (out.n_rows)
+    MTS_HIP(hipMemcpyAsync(out.rows, rows_host.data(), sizeof(int32_t) * out.n_rows, hipMemcpyHostToDevice, st));
+  out.width = ar.alloc<int32_t>(ns);
+  if (ns) {
+    k_slice_width<<<blocks_for(ns), kThreads, 0, st>>>(out.rows, out.n_rows, s.rp, L, out.width, ns);
+    MTS_LAUNCH_CHECK();
+  }
+  std::vector<int32_t> w(ns);
+  if (ns) MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  // One width for every slice (the largest family, rounded up to L): the bond
+  // pass then computes slice offsets instead of loading them.  Families shorter
+  // than the width are padded with state-0 slots.
+  int maxw = 0;
+  for (int64_t q = 0; q < ns; q++) maxw = std::max(maxw, (int)w[q]);
+  for (int64_t q = 0; q < ns; q++) w[q] = maxw;
+  if (ns) MTS_HIP(hipMemcpyAsync(out.width, w.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+  out.T = maxw / L;
+  std::vector<int64_t> so(ns + 1), wo(ns + 1);
+  so[0] = wo[0] = 0;
+  int maxt = 0;
+  for (int64_t q = 0; q < ns; q++) {
+    so[q + 1] = so[q] + (int64_t)(w[q] / L) * WAVE;
+    wo[q + 1] = wo[q] + w[q] / L;
+    maxt = std::max(maxt, w[q] / L);
+  }
+  out.n_slots = so[ns];
+  out.n_words = wo[ns];
+  out.slot_off = ar.alloc<int64_t>(ns + 1);
+  out.word_off = ar.alloc<int64_t>(ns + 1);
+  MTS_HIP(hipMemcpyAsync(out.slot_off, so.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(out.word_off, wo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+  // kSpareIters iterations of zeros past the last slice keep unrolled loads in bounds
+  out.col = ar.alloc<int32_t>(out.n_slots + kSpareIters * WAVE);
+  out.mask = ar.alloc<uint64_t>(out.n_words + kSpareIters);
+  MTS_HIP(hipMemsetAsync(out.col, 0, sizeof(int32_t) * (out.n_slots + kSpareIters * WAVE), st));
+  MTS_HIP(hipMemsetAsync(out.mask, 0, sizeof(uint64_t) * (out.n_words + kSpareIters), st));
+  if (ns) {
+    k_sell_fill<<<blocks_for(ns * WAVE), kThreads, 0, st>>>(out.rows, out.n_rows, ns, s.rp, s.csr_col, L, out.width,
+                                                            out.slot_off, out.col);
+    MTS_LAUNCH_CHECK();
+    Cracks cr{};
+    cr.n = s.p.n_cracks;
+    for (int c = 0; c < cr.n; c++)
+      for (int q = 0; q < 3; q++) cr.c[c][q] = s.p.cracks[c][q];
+    if (maxt > 0) {
+      dim3 grid((unsigned)((maxt + 63) / 64), (unsigned)ns);
+      k_sell_mask<<<grid, 64, 0, st>>>(out.rows, out.n_rows, ns, s.rp, s.csr_col, L, out.width, out.word_off,
+                                       out.mask, s.x, s.N, s.dim, cr, src_mask_full, s.sell.word_off, s.sell.L);
+      MTS_LAUNCH_CHECK();
+    }
+  }
+  MTS_HIP(hipStreamSynchronize(st));
+}
+
+void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full) {
+  if (!out.n_slices) return;
+  std::vector<int32_t> w(out.n_slices);
+  MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * out.n_slices, hipMemcpyDeviceToHost, s.stream));
+  MTS_HIP(hipStreamSynchronize(s.stream));
+  int maxt = 0;
+  for (int32_t v : w) maxt = std::max(maxt, (int)v / out.L);
+  if (!maxt) return;
+  Cracks cr{};
+  dim3 grid((unsigned)((maxt + 63) / 64), (unsigned)out.n_slices);
+  k_sell_mask<<<grid, 64, 0, s.stream>>>(out.rows, out.n_rows, out.n_slices, s.rp, s.csr_col, out.L, out.width,
+                                          out.word_off, out.mask, s.x, s.N, s.dim, cr, src_mask_full,
+                                          s.sell.word_off, s.sell.L);
+  MTS_LAUNCH_CHECK();
+}
+
+void sell_coefficients(Solver &s, Sell &out) {
+  if (!out.n_slices) return;
+  bool mixed = s.precision == MTS_MIXED;
+  const int64_t ns = out.n_slots + kSpareIters * WAVE;
+  if (!out.coef) {
+    out.coef = s.arena.alloc<double>(ns);
+    MTS_HIP(hipMemsetAsync(out.coef, 0, sizeof(double) * ns, s.stream));
+  }
+  if (mixed && !out.coef32) {
+    out.coef32 = s.arena.alloc<float>(ns);
+    MTS_HIP(hipMemsetAsync(out.coef32, 0, sizeof(float) * ns, s.stream));
+  }
+  k_sell_coef<<<blocks_for(out.n_slices * WAVE), kThreads, 0, s.stream>>>(
+      out.rows, out.n_rows, out.n_slices, s.rp, s.csr_col, out.L, out.width, out.slot_off, s.x, s.N, s.alpha,
+      s.mass, s.prm, out.coef, mixed ? out.coef32 : nullptr);
+  MTS_LAUNCH_CHECK();
+}
+
+void bonds_to_csr_state(Solver &s, uint8_t *dev_out) {
+  k_mask_to_csr<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, s.sell.L,
+                                                            dev_out);
+  MTS_LAUNCH_CHECK();
+}
+
+void pd_damage(Solver &s) {
+  k_damage<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, s.sell.L, s.damage);
+  MTS_LAUNCH_CHECK();
+}
+
+}  // namespace mts

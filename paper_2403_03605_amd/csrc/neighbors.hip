@@ -1,7 +1,6 @@
 // Neighbour families H_delta(x_i) = {k != i : |x_k - x_i| <= delta} (Sec. 2.1),
 // built on the device with a cell list, stored as canonical CSR (rows ascending)
-// and re-laid as sliced ELL for the bond pass.  Pre-crack bonds (horizontal
-// segments) start with state 0 (Eq. 4 with a history that is already broken).
+// (re-laid as sliced ELL for the bond pass in layout.hip).
 #include "internal.h"
 
 #include <algorithm>
@@ -147,120 +146,7 @@ __global__ void k_i64_to_i32(const int64_t *a, int32_t *b, int64_t n) {
   if (i < n) b[i] = (int32_t)a[i];
 }
 
-// ---------------------------------------------------------------- sliced ELL
-struct Cracks {
-  int n;
-  double c[8][3];
-};
-
-// Pre-crack (horizontal segment y = yc, x_start <= x* <= x_end, tip inclusive);
-// x* from the endpoint with the smaller id so both directions agree.
-__device__ inline bool crosses_crack(const double *x, int64_t N, int64_t i, int64_t k, const Cracks &cr) {
-  int64_t p = i < k ? i : k, q = i < k ? k : i;
-  double xp = x[p], yp = x[N + p], xq = x[q], yq = x[N + q];
-  for (int c = 0; c < cr.n; c++) {
-    double yc = cr.c[c][0];
-    if ((yp - yc) * (yq - yc) < 0.0) {
-      double xs = xp + (yc - yp) * (xq - xp) / (yq - yp);
-      if (xs >= cr.c[c][1] && xs <= cr.c[c][2]) return true;
-    }
-  }
-  return false;
-}
-
-__global__ void k_slice_width(const int32_t *rows, int64_t n_rows, const int32_t *rp, int32_t *width,
-                              int64_t n_slices) {
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_slices) return;
-  int w = 0;
-  for (int l = 0; l < WAVE; l++) {
-    int64_t r = s * WAVE + l;
-    if (r >= n_rows) break;
-    int64_t i = rows[r];
-    int len = rp[i + 1] - rp[i];
-    w = len > w ? len : w;
-  }
-  width[s] = w;
-}
-
-__global__ void k_sell_fill(const int32_t *rows, int64_t n_rows, const int32_t *rp, const int32_t *csr_col,
-                            const int32_t *width, const int64_t *slot_off, int32_t *col) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t n_pad = ((n_rows + WAVE - 1) / WAVE) * WAVE;
-  if (r >= n_pad) return;
-  int64_t s = r / WAVE;
-  int lane = (int)(r % WAVE);
-  int w = width[s];
-  int64_t base = slot_off[s];
-  if (r >= n_rows) {
-    for (int k = 0; k < w; k++) col[base + (int64_t)k * WAVE + lane] = 0;
-    return;
-  }
-  int64_t i = rows[r];
-  int len = rp[i + 1] - rp[i];
-  for (int k = 0; k < w; k++) col[base + (int64_t)k * WAVE + lane] = k < len ? csr_col[rp[i] + k] : (int32_t)i;
-}
-
-// One thread per (slice, k) word.  src_mask == nullptr: initial states from the
-// crack segments; otherwise bits are gathered from the full-lattice layout.
-__global__ void k_sell_mask(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
-                            const int32_t *csr_col, const int32_t *width, const int64_t *word_off,
-                            uint64_t *mask, const double *x, int64_t N, int dim, Cracks cr,
-                            const uint64_t *src_mask, const int64_t *src_word_off) {
-  int64_t s = blockIdx.y;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n_slices || k >= width[s]) return;
-  uint64_t word = 0;
-  for (int l = 0; l < WAVE; l++) {
-    int64_t r = s * WAVE + l;
-    if (r >= n_rows) break;
-    int64_t i = rows[r];
-    int len = rp[i + 1] - rp[i];
-    if (k >= len) continue;
-    bool intact;
-    if (src_mask) {
-      intact = (src_mask[src_word_off[i / WAVE] + k] >> (i % WAVE)) & 1ull;
-    } else {
-      int64_t c = csr_col[rp[i] + k];
-      intact = !(dim == 2 && crosses_crack(x, N, i, c, cr));
-    }
-    if (intact) word |= 1ull << l;
-  }
-  mask[word_off[s] + k] = word;
-}
-
-__global__ void k_mask_to_csr(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask,
-                              uint8_t *out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int64_t s = i / WAVE;
-  int lane = (int)(i % WAVE);
-  int len = rp[i + 1] - rp[i];
-  for (int k = 0; k < len; k++) out[rp[i] + k] = (uint8_t)((mask[word_off[s] + k] >> lane) & 1ull);
-}
-
 }  // namespace
-
-void bonds_to_csr_state(Solver &s, uint8_t *dev_out) {
-  k_mask_to_csr<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, dev_out);
-  MTS_LAUNCH_CHECK();
-}
-
-void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full) {
-  if (!out.n_slices) return;
-  std::vector<int32_t> w(out.n_slices);
-  MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * out.n_slices, hipMemcpyDeviceToHost, s.stream));
-  MTS_HIP(hipStreamSynchronize(s.stream));
-  int maxw = 0;
-  for (int32_t v : w) maxw = std::max(maxw, (int)v);
-  if (!maxw) return;
-  Cracks cr{};
-  dim3 grid((unsigned)((maxw + 63) / 64), (unsigned)out.n_slices);
-  k_sell_mask<<<grid, 64, 0, s.stream>>>(out.rows, out.n_rows, out.n_slices, s.rp, s.csr_col, out.width,
-                                          out.word_off, out.mask, s.x, s.N, s.dim, cr, src_mask_full,
-                                          s.sell.word_off);
-  MTS_LAUNCH_CHECK();
-}
 
 void exclusive_scan_i64(hipStream_t st, DeviceArena &ar, const int64_t *in, int64_t *out, int64_t n) {
   if (n <= 0) return;
@@ -349,58 +235,7 @@ void build_neighbors(Solver &s) {
 
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
-  build_sell(s, s.sell, rows, nullptr);
-}
-
-void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full) {
-  hipStream_t st = s.stream;
-  DeviceArena &ar = s.arena;
-  out.n_rows = (int64_t)rows_host.size();
-  out.n_slices = (out.n_rows + WAVE - 1) / WAVE;
-  int64_t ns = out.n_slices;
-  out.rows = ar.alloc<int32_t>(out.n_rows);
-  if (out.n_rows)
-    MTS_HIP(hipMemcpyAsync(out.rows, rows_host.data(), sizeof(int32_t) * out.n_rows, hipMemcpyHostToDevice, st));
-  out.width = ar.alloc<int32_t>(ns);
-  if (ns) {
-    k_slice_width<<<blocks_for(ns), kThreads, 0, st>>>(out.rows, out.n_rows, s.rp, out.width, ns);
-    MTS_LAUNCH_CHECK();
-  }
-  std::vector<int32_t> w(ns);
-  if (ns) MTS_HIP(hipMemcpyAsync(w.data(), out.width, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
-  MTS_HIP(hipStreamSynchronize(st));
-  std::vector<int64_t> so(ns + 1), wo(ns + 1);
-  so[0] = wo[0] = 0;
-  int maxw = 0;
-  for (int64_t q = 0; q < ns; q++) {
-    so[q + 1] = so[q] + (int64_t)w[q] * WAVE;
-    wo[q + 1] = wo[q] + w[q];
-    maxw = std::max(maxw, w[q]);
-  }
-  out.n_slots = so[ns];
-  out.n_words = wo[ns];
-  out.slot_off = ar.alloc<int64_t>(ns + 1);
-  out.word_off = ar.alloc<int64_t>(ns + 1);
-  MTS_HIP(hipMemcpyAsync(out.slot_off, so.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
-  MTS_HIP(hipMemcpyAsync(out.word_off, wo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
-  out.col = ar.alloc<int32_t>(out.n_slots);
-  out.mask = ar.alloc<uint64_t>(out.n_words);
-  if (ns) {
-    k_sell_fill<<<blocks_for(ns * WAVE), kThreads, 0, st>>>(out.rows, out.n_rows, s.rp, s.csr_col, out.width,
-                                                            out.slot_off, out.col);
-    MTS_LAUNCH_CHECK();
-    Cracks cr{};
-    cr.n = s.p.n_cracks;
-    for (int c = 0; c < cr.n; c++)
-      for (int q = 0; q < 3; q++) cr.c[c][q] = s.p.cracks[c][q];
-    dim3 grid((unsigned)((maxw + 63) / 64), (unsigned)ns);
-    if (maxw > 0) {
-      k_sell_mask<<<grid, 64, 0, st>>>(out.rows, out.n_rows, ns, s.rp, s.csr_col, out.width, out.word_off,
-                                       out.mask, s.x, s.N, s.dim, cr, src_mask_full, s.sell.word_off);
-      MTS_LAUNCH_CHECK();
-    }
-  }
-  MTS_HIP(hipStreamSynchronize(st));
+  build_sell(s, s.sell, rows, nullptr, pick_lanes(N));
 }
 
 }  // namespace mts

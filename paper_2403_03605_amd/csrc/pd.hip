@@ -6,37 +6,15 @@
 // Equations: Eq. 2 (force), Eq. 3 (stretch), Eq. 4 (bond state), Eq. 5 (damage),
 // Eq. 38 with gamma = 1/2, beta = 0 (velocity Verlet), Eq. 48a/48b (free and
 // link problems), Eq. 17-18 and Eq. 34 (Arlequin weights of stiffness and mass).
-#include "internal.h"
+#include <type_traits>
+
+#include "device_math.h"
 
 namespace mts {
 
 namespace {
 
 constexpr int kBlock = 256;  // 4 wavefronts = 4 slices per workgroup
-
-__device__ inline double cfun(const Params &P, double r) {
-  if (P.kernel == MTS_K_EXP) return P.c0 * exp(-r / P.lexp);
-  return P.c0 / (r * r * r);
-}
-
-// alpha(x): cubic / linear / constant in the L-infinity distance l1 to the
-// PD-only box Omega^2, 1 beyond the overlap width (Sec. 3.2 weight functions).
-__device__ inline double alpha_of(const Params &P, const double *xp) {
-  if (!P.coupled) return 0.0;
-  double l1 = 0.0;
-  for (int a = 0; a < P.dim; a++) {
-    double d = P.o2lo[a] - xp[a];
-    double e = xp[a] - P.o2hi[a];
-    if (e > d) d = e;
-    if (d > l1) l1 = d;
-  }
-  if (l1 >= P.overlap) return 1.0;
-  if (l1 <= 0.0) return 0.0;
-  double t = l1 / P.overlap;
-  if (P.weight_kind == MTS_W_LINEAR) return t;
-  if (P.weight_kind == MTS_W_CONSTANT) return 0.5;
-  return t * t * t;
-}
 
 __global__ void k_alpha_mass(Params P, const double *x, int64_t N, double *alpha, double *mass) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,11 +58,14 @@ __global__ void k_predict(int64_t N, int dim, double dt, double hdt2, const doub
 struct SubstepArgs {
   const double *x;
   int64_t N, n_slices;
+  int T;
   const int32_t *width;
   const int64_t *slot_off, *word_off;
   const int32_t *col;
+  const double *coef;
+  const float *coef32;
   uint64_t *mask;
-  const double *alpha, *mass, *P;
+  const double *mass, *P;
   const double *u_in;   // u_j (predicted)
   double *u_out;        // u_{j+1} predicted
   double *v, *a;
@@ -98,82 +79,167 @@ struct SubstepArgs {
   int breaking;
 };
 
-// One lane = one PD node, one wavefront = one slice of 64 consecutive nodes.
-// The lane sums its own family in canonical order (no atomics); bond states of
-// the slice's slot k form one 64-bit word owned by the wavefront.
-template <int DIM>
+// One wavefront = one slice of 64/L consecutive nodes; the L lanes of a node
+// take every L-th slot of its family, their partial sums are combined by a
+// fixed butterfly (deterministic, no atomics).  Bond states of one iteration of
+// the slice form one 64-bit word owned by the wavefront.
+template <int DIM, int L, bool MX>
 __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) {
+  // MX: mixed form -- stretch, force and accumulation in FP32 on differences
+  // formed in FP64; the accumulated value is the acceleration (coefficient
+  // pre-divided by the node mass).  Integration stays FP64.
+  using R = typename std::conditional<MX, float, double>::type;
+  constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t slice = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  // wave-uniform slice index: offsets and state words come through scalar loads
+  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;  // uniform per wavefront
   const int64_t N = A.N;
-  const int64_t i = slice * WAVE + lane;
+  const int jl = lane / L, l = lane % L;
+  const int64_t i = slice * S + jl;
   const bool valid = i < N;
   const int64_t ii = valid ? i : 0;
-  const int w = A.width[slice];
-  const int64_t so = A.slot_off[slice], wo = A.word_off[slice];
-  double xi_[3], ui_[3];
+  const int T = A.T;
+  const int64_t wo = slice * T, so = wo * WAVE;
+  double xi_[DIM], ui_[DIM];
   for (int d = 0; d < DIM; d++) {
     xi_[d] = A.x[d * N + ii];
     ui_[d] = A.u_in[d * N + ii];
   }
-  const double al_i = A.alpha[ii];
-  double F[3] = {0.0, 0.0, 0.0};
+  // node data of the corrector, fetched up front so it shares the first round trip
+  double v_o[DIM], a_o[DIM], p_o[DIM];
+  for (int d = 0; d < DIM; d++) {
+    v_o[d] = A.v[d * N + ii];
+    a_o[d] = A.a[d * N + ii];
+    p_o[d] = A.P ? A.P[d * N + ii] : 0.0;
+  }
+  const int32_t q_i = A.cidx ? A.cidx[ii] : -1;
+  const double m_i = A.mass[ii];
+  R F[DIM];
+  for (int d = 0; d < DIM; d++) F[d] = R(0);
   int n_intact = 0;
-  bool broke = false;
-  for (int k = 0; k < w; k++) {
-    const uint64_t word = A.mask[wo + k];
-    bool bit = (word >> lane) & 1ull;
-    if (bit) {
-      const int64_t c = A.col[so + (int64_t)k * WAVE + lane];
-      double xi[3], eta[3];
+  int broke = 0;
+  // Chunks of TM iterations: every load of a chunk is issued before any of its
+  // results is used (state words, indices and coefficients first, then the
+  // neighbour gathers), so a wavefront waits on two memory round trips per
+  // chunk instead of three per slot.
+  constexpr int TM = 4;
+  for (int t0 = 0; t0 < T; t0 += TM) {
+    uint64_t word[TM];
+    int64_t c[TM];
+    R cf[TM];
+    // The slot arrays carry TM spare iterations past the last slice, so these
+    // loads are always in bounds; slots past T are masked out afterwards.
+#pragma unroll
+    for (int q = 0; q < TM; q++) {
+      const int64_t pos = so + (int64_t)(t0 + q) * WAVE + lane;
+      word[q] = A.mask[wo + t0 + q];
+      c[q] = A.col[pos];
+      if constexpr (MX) cf[q] = A.coef32[pos];
+      else cf[q] = A.coef[pos];
+    }
+#pragma unroll
+    for (int q = 0; q < TM; q++)
+      if (t0 + q >= T) word[q] = 0ull;
+    double xk[TM][DIM], uk[TM][DIM];
+#pragma unroll
+    for (int q = 0; q < TM; q++)
       for (int d = 0; d < DIM; d++) {
-        xi[d] = A.x[d * N + c] - xi_[d];
-        eta[d] = A.u_in[d * N + c] - ui_[d];
+        xk[q][d] = A.x[d * N + c[q]];
+        uk[q][d] = A.u_in[d * N + c[q]];
       }
-      double r2 = xi[0] * xi[0] + xi[1] * xi[1];
-      if (DIM == 3) r2 = r2 + xi[2] * xi[2];
-      const double r = sqrt(r2);
-      if (A.breaking) {
-        double y[3];
-        for (int d = 0; d < DIM; d++) y[d] = xi[d] + eta[d];
-        double y2 = y[0] * y[0] + y[1] * y[1];
-        if (DIM == 3) y2 = y2 + y[2] * y[2];
-        const double ly = sqrt(y2);
-        const double st = (ly - r) / r;  // Eq. 3
-        if (st >= P.scrit) {             // Eq. 4, inclusive
-          bit = false;
-          broke = true;
+#pragma unroll
+    for (int q = 0; q < TM; q++) {
+      bool bit = (word[q] >> lane) & 1ull;
+      if (bit) {
+        if constexpr (!MX) {
+          double xi[DIM], eta[DIM];
+          for (int d = 0; d < DIM; d++) {
+            xi[d] = xk[q][d] - xi_[d];
+            eta[d] = uk[q][d] - ui_[d];
+          }
+          if (A.breaking) {
+            double r2 = xi[0] * xi[0] + xi[1] * xi[1];
+            double y0 = xi[0] + eta[0], y1 = xi[1] + eta[1];
+            double y2 = y0 * y0 + y1 * y1;
+            if (DIM == 3) {
+              double yz = xi[2] + eta[2];
+              r2 = r2 + xi[2] * xi[2];
+              y2 = y2 + yz * yz;
+            }
+            if (breaks(r2, y2, P.K2, P.scrit)) {  // Eq. 3-4
+              bit = false;
+              broke = 1;
+            }
+          }
+          if (bit) {
+            double xe = xi[0] * eta[0] + xi[1] * eta[1];
+            if (DIM == 3) xe = xe + xi[2] * eta[2];
+            const double tt = cf[q] * xe;  // Eq. 2 times V_i V_k, Arlequin-weighted
+            for (int d = 0; d < DIM; d++) F[d] += tt * xi[d];
+            n_intact++;
+          }
+        } else {
+          float xi[DIM], eta[DIM];
+          for (int d = 0; d < DIM; d++) {
+            xi[d] = (float)(xk[q][d] - xi_[d]);
+            eta[d] = (float)(uk[q][d] - ui_[d]);
+          }
+          float xe = xi[0] * eta[0] + xi[1] * eta[1];
+          if (DIM == 3) xe = xe + xi[2] * eta[2];
+          if (A.breaking) {
+            // |xi+eta|^2 - |xi|^2 = 2 xi.eta + eta.eta >= ((1+s_c)^2 - 1) |xi|^2
+            float r2 = xi[0] * xi[0] + xi[1] * xi[1];
+            float ee = eta[0] * eta[0] + eta[1] * eta[1];
+            if (DIM == 3) {
+              r2 = r2 + xi[2] * xi[2];
+              ee = ee + eta[2] * eta[2];
+            }
+            if (2.0f * xe + ee >= P.K2m1f * r2) {
+              bit = false;
+              broke = 1;
+            }
+          }
+          if (bit) {
+            const float tt = cf[q] * xe;
+            for (int d = 0; d < DIM; d++) F[d] += tt * xi[d];
+            n_intact++;
+          }
         }
       }
-      if (bit) {
-        double xe = xi[0] * eta[0] + xi[1] * eta[1];
-        if (DIM == 3) xe = xe + xi[2] * eta[2];
-        const double wgt = 1.0 - 0.5 * (al_i + A.alpha[c]);
-        const double tt = ((wgt * cfun(P, r)) * xe) * P.VV;  // Eq. 2 times V_i V_k
-        for (int d = 0; d < DIM; d++) F[d] += tt * xi[d];
-        n_intact++;
+      if (t0 + q < T) {
+        const uint64_t nw = __ballot(bit);
+        if (nw != word[q] && lane == 0) A.mask[wo + t0 + q] = nw;
       }
     }
-    const uint64_t nw = __ballot(bit);
-    if (nw != word && lane == 0) A.mask[wo + k] = nw;
+  }
+  for (int off = L / 2; off >= 1; off >>= 1) {
+    for (int d = 0; d < DIM; d++) F[d] += __shfl_xor(F[d], off, WAVE);
+    n_intact += __shfl_xor(n_intact, off, WAVE);
+    broke |= __shfl_xor(broke, off, WAVE);
   }
   if (!valid) return;
-  if (broke && A.in_region && A.in_region[i]) A.region_flag[0] = 1;
-  const int32_t q = A.cidx ? A.cidx[i] : -1;
-  const double m_i = A.mass[i];
+  if (l == 0 && broke && A.in_region && A.in_region[i]) A.region_flag[0] = 1;
   for (int d = 0; d < DIM; d++) {
-    const int64_t t = d * N + i;
-    double fl = F[d] + (A.P ? A.P[t] : 0.0);
-    if (q >= 0) fl = fl + A.sfac * A.lam0[q * DIM + d];  // + G_P^T S_j
-    const double an = fl / m_i;
-    const double ao = A.a[t];
-    const double vn = A.v[t] + P.hdtP * (ao + an);
-    A.a[t] = an;
-    A.v[t] = vn;
-    A.u_out[t] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
+    if (d % L != l) continue;
+    const int64_t tix = d * N + i;
+    double an;
+    if constexpr (MX) {
+      // F already holds the bond acceleration; external and multiplier forces in FP64
+      double ext = p_o[d];
+      if (q_i >= 0) ext = ext + A.sfac * A.lam0[q_i * DIM + d];
+      an = (double)F[d] + ext / m_i;
+    } else {
+      double fl = F[d] + p_o[d];
+      if (q_i >= 0) fl = fl + A.sfac * A.lam0[q_i * DIM + d];  // + G_P^T S_j
+      an = fl / m_i;
+    }
+    const double vn = v_o[d] + P.hdtP * (a_o[d] + an);
+    A.a[tix] = an;
+    A.v[tix] = vn;
+    A.u_out[tix] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
   }
-  if (A.damage) {
+  if (A.damage && l == 0) {
     const int fam = A.rp[i + 1] - A.rp[i];
     A.damage[i] = fam > 0 ? 1.0 - (double)n_intact / (double)fam : 0.0;
   }
@@ -186,11 +252,14 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) 
 struct LinkArgs {
   const double *x;
   int64_t N, n_rows, n_slices;
-  const int32_t *rows, *width;
+  int T;
+  const int32_t *rows, *width, *slice_layer;
+  int jmax;               // rows farther than jmax horizons still hold exact zeros
   const int64_t *slot_off, *word_off;
   const int32_t *col;
+  const double *coef;
   const uint64_t *mask;
-  const double *alpha, *mass;
+  const double *mass;
   const double *u_in;
   double *u_out, *v, *a;  // [NRHS][DIM][N]
   const int32_t *cidx;
@@ -201,49 +270,73 @@ struct LinkArgs {
   double lfac;
 };
 
-template <int DIM, int NRHS, bool kColor>
+template <int DIM, int NRHS, bool kColor, int L>
 __global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
+  constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t slice = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;
-  const int64_t r = slice * WAVE + lane;
+  if (A.slice_layer[slice] > A.jmax) return;  // uniform per wavefront
+  const int jl = lane / L, l = lane % L;
+  const int64_t r = slice * S + jl;
   const bool valid = r < A.n_rows;
   const int64_t N = A.N;
   const int64_t i = valid ? A.rows[r] : A.rows[0];
-  const int w = A.width[slice];
-  const int64_t so = A.slot_off[slice], wo = A.word_off[slice];
+  const int T = A.T;
+  const int64_t wo = slice * T, so = wo * WAVE;
   const int64_t stride = (int64_t)DIM * N;
-  double xi_[3], ui_[NRHS][3];
+  double xi_[DIM], ui_[NRHS][DIM];
   for (int d = 0; d < DIM; d++) xi_[d] = A.x[d * N + i];
   for (int b = 0; b < NRHS; b++)
     for (int d = 0; d < DIM; d++) ui_[b][d] = A.u_in[b * stride + d * N + i];
-  const double al_i = A.alpha[i];
-  double F[NRHS][3];
-  for (int b = 0; b < NRHS; b++) F[b][0] = F[b][1] = F[b][2] = 0.0;
-  for (int k = 0; k < w; k++) {
-    const uint64_t word = A.mask[wo + k];
-    if (!((word >> lane) & 1ull)) continue;
-    const int64_t c = A.col[so + (int64_t)k * WAVE + lane];
-    double xi[3];
-    for (int d = 0; d < DIM; d++) xi[d] = A.x[d * N + c] - xi_[d];
-    double r2 = xi[0] * xi[0] + xi[1] * xi[1];
-    if (DIM == 3) r2 = r2 + xi[2] * xi[2];
-    const double rr = sqrt(r2);
-    const double wgt = 1.0 - 0.5 * (al_i + A.alpha[c]);
-    const double coef = (wgt * cfun(P, rr));
-    for (int b = 0; b < NRHS; b++) {
-      double xe = xi[0] * (A.u_in[b * stride + c] - ui_[b][0]) + xi[1] * (A.u_in[b * stride + N + c] - ui_[b][1]);
-      if (DIM == 3) xe = xe + xi[2] * (A.u_in[b * stride + 2 * N + c] - ui_[b][2]);
-      const double tt = (coef * xe) * P.VV;
-      for (int d = 0; d < DIM; d++) F[b][d] += tt * xi[d];
+  double F[NRHS][DIM];
+  for (int b = 0; b < NRHS; b++)
+    for (int d = 0; d < DIM; d++) F[b][d] = 0.0;
+  constexpr int TM = NRHS == 1 ? 4 : 1;
+  for (int t0 = 0; t0 < T; t0 += TM) {
+    bool bit[TM];
+    int64_t c[TM];
+    double cf[TM];
+#pragma unroll
+    for (int q = 0; q < TM; q++) {
+      const int64_t pos = so + (int64_t)(t0 + q) * WAVE + lane;
+      bit[q] = (A.mask[wo + t0 + q] >> lane) & 1ull;
+      c[q] = A.col[pos];
+      cf[q] = A.coef[pos];
+    }
+#pragma unroll
+    for (int q = 0; q < TM; q++)
+      if (t0 + q >= T) bit[q] = false;
+    double xk[TM][DIM], uk[TM][NRHS][DIM];
+#pragma unroll
+    for (int q = 0; q < TM; q++)
+      for (int d = 0; d < DIM; d++) {
+        xk[q][d] = A.x[d * N + c[q]];
+        for (int b = 0; b < NRHS; b++) uk[q][b][d] = A.u_in[b * stride + d * N + c[q]];
+      }
+#pragma unroll
+    for (int q = 0; q < TM; q++) {
+      if (!bit[q]) continue;
+      double xi[DIM];
+      for (int d = 0; d < DIM; d++) xi[d] = xk[q][d] - xi_[d];
+      for (int b = 0; b < NRHS; b++) {
+        double xe = xi[0] * (uk[q][b][0] - ui_[b][0]) + xi[1] * (uk[q][b][1] - ui_[b][1]);
+        if (DIM == 3) xe = xe + xi[2] * (uk[q][b][2] - ui_[b][2]);
+        const double tt = cf[q] * xe;
+        for (int d = 0; d < DIM; d++) F[b][d] += tt * xi[d];
+      }
     }
   }
+  for (int off = L / 2; off >= 1; off >>= 1)
+    for (int b = 0; b < NRHS; b++)
+      for (int d = 0; d < DIM; d++) F[b][d] += __shfl_xor(F[b][d], off, WAVE);
   if (!valid) return;
   const int32_t q = A.cidx[i];
   const double m_i = A.mass[i];
   for (int b = 0; b < NRHS; b++)
     for (int d = 0; d < DIM; d++) {
-      const int64_t t = b * stride + d * N + i;
+      if ((b * DIM + d) % L != l) continue;
+      const int64_t tix = b * stride + d * N + i;
       double fl = F[b][d];
       if (q >= 0) {
         if (kColor) {
@@ -253,10 +346,10 @@ __global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
         }
       }
       const double an = fl / m_i;
-      const double vn = A.v[t] + P.hdtP * (A.a[t] + an);
-      A.a[t] = an;
-      A.v[t] = vn;
-      A.u_out[t] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
+      const double vn = A.v[tix] + P.hdtP * (A.a[tix] + an);
+      A.a[tix] = an;
+      A.v[tix] = vn;
+      A.u_out[tix] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
     }
 }
 
@@ -294,18 +387,6 @@ __global__ void k_add_link(int64_t n_rows, const int32_t *rows, int64_t N, int d
   }
 }
 
-__global__ void k_damage(int64_t N, int64_t n_slices, const int32_t *width, const int64_t *word_off,
-                         const uint64_t *mask, const int32_t *rp, double *phi) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int64_t s = i / WAVE;
-  int lane = (int)(i % WAVE);
-  int cnt = 0;
-  for (int k = 0; k < width[s]; k++) cnt += (int)((mask[word_off[s] + k] >> lane) & 1ull);
-  int fam = rp[i + 1] - rp[i];
-  phi[i] = fam > 0 ? 1.0 - (double)cnt / (double)fam : 0.0;
-}
-
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -322,6 +403,7 @@ void pd_setup(Solver &s) {
   }
   k_init_accel<<<nblk(N), 256, 0, st>>>(N, s.dim, s.P, s.mass, s.a);
   MTS_LAUNCH_CHECK();
+  sell_coefficients(s, s.sell);
 }
 
 void pd_predict_all(Solver &s) {
@@ -337,12 +419,14 @@ void pd_substep(Solver &s, int j) {
   A.x = s.x;
   A.N = s.N;
   A.n_slices = s.sell.n_slices;
+  A.T = s.sell.T;
   A.width = s.sell.width;
   A.slot_off = s.sell.slot_off;
   A.word_off = s.sell.word_off;
   A.col = s.sell.col;
+  A.coef = s.sell.coef;
+  A.coef32 = s.sell.coef32;
   A.mask = s.sell.mask;
-  A.alpha = s.alpha;
   A.mass = s.mass;
   A.P = s.P;
   A.u_in = s.u[s.cur ^ 1];
@@ -360,18 +444,25 @@ void pd_substep(Solver &s, int j) {
   unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   hipEvent_t e0 = nullptr;
   s.prof_begin(MTS_KT_PD_SUBSTEP, &e0);
-  if (s.dim == 2) k_pd_substep<2><<<grid, kBlock, 0, s.stream>>>(A, s.prm);
-  else k_pd_substep<3><<<grid, kBlock, 0, s.stream>>>(A, s.prm);
+  const int L = s.sell.L;
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+#define MTS_SUBL(D, MX)                                                                        \
+  if (L == 1) MTS_SUB(D, 1, MX);                                                              \
+  else if (L == 2) MTS_SUB(D, 2, MX);                                                         \
+  else if (L == 4) MTS_SUB(D, 4, MX);                                                         \
+  else MTS_SUB(D, 8, MX)
+  const bool mx = s.precision == MTS_MIXED;
+  if (s.dim == 2) {
+    if (mx) { MTS_SUBL(2, true); } else { MTS_SUBL(2, false); }
+  } else {
+    if (mx) { MTS_SUBL(3, true); } else { MTS_SUBL(3, false); }
+  }
+#undef MTS_SUBL
+#undef MTS_SUB
   MTS_LAUNCH_CHECK();
   s.prof_end(MTS_KT_PD_SUBSTEP, e0);
   s.cur ^= 1;
   s.pd_steps++;
-}
-
-void pd_damage(Solver &s) {
-  k_damage<<<nblk(s.N), 256, 0, s.stream>>>(s.N, s.sell.n_slices, s.sell.width, s.sell.word_off, s.sell.mask,
-                                            s.rp, s.damage);
-  MTS_LAUNCH_CHECK();
 }
 
 // ---- link runs (used by coupling.hip) ----
@@ -385,7 +476,12 @@ void link_zero(Solver &s, double *u0, double *u1, double *v, double *a, int nrhs
 template <int DIM, int NRHS, bool kColor>
 static void launch_link(Solver &s, LinkArgs &A) {
   unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
-  k_link_substep<DIM, NRHS, kColor><<<grid, kBlock, 0, s.stream>>>(A, s.prm);
+  switch (s.rsell.L) {
+    case 1: k_link_substep<DIM, NRHS, kColor, 1><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    case 2: k_link_substep<DIM, NRHS, kColor, 2><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    case 4: k_link_substep<DIM, NRHS, kColor, 4><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    default: k_link_substep<DIM, NRHS, kColor, 8><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+  }
   MTS_LAUNCH_CHECK();
 }
 
@@ -398,13 +494,16 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
   A.N = s.N;
   A.n_rows = s.rsell.n_rows;
   A.n_slices = s.rsell.n_slices;
+  A.T = s.rsell.T;
   A.rows = s.rsell.rows;
   A.width = s.rsell.width;
+  A.slice_layer = s.rsell.slice_layer;
+  A.jmax = j - 1;
   A.slot_off = s.rsell.slot_off;
   A.word_off = s.rsell.word_off;
   A.col = s.rsell.col;
+  A.coef = s.rsell.coef;
   A.mask = s.rsell.mask;
-  A.alpha = s.alpha;
   A.mass = s.mass;
   A.u_in = u_in;
   A.u_out = u_out;

@@ -139,6 +139,8 @@ void derive_params(Solver &s) {
   if (p.s_crit > 0.0) P.scrit = p.s_crit;
   else if (p.dim == 2) P.scrit = std::sqrt(p.G0 / (p.thickness * I6));
   else P.scrit = std::sqrt(2.0 * p.G0 / (pi * I7));
+  P.K2 = (1.0 + P.scrit) * (1.0 + P.scrit);
+  P.K2m1f = (float)(2.0 * P.scrit + P.scrit * P.scrit);
   P.dtP = p.dt_pd;
   P.hdtP = 0.5 * P.dtP;
   P.hdt2P = 0.5 * P.dtP * P.dtP;
@@ -199,7 +201,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
     coupling_setup(*s);
   }
   pd_predict_all(*s);
-  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, sizeof(int32_t), hipHostMallocDefault));
+  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+  s->pinned_flag[0] = s->pinned_flag[1] = 0;
   pd_damage(*s);
   MTS_HIP(hipStreamSynchronize(st));
 }
@@ -256,8 +259,26 @@ void check_finite(Solver &s) {
   if (h) s.unstable = true;
 }
 
+// Algorithm 1, last step: the unit-load responses are rebuilt after a macro step
+// in which a bond inside their support broke.  The check for step k-1 is
+// resolved after step k's free problem has been enqueued (it does not use the
+// responses), so the host wait overlaps device work; the rebuild uses the bond
+// states saved at the end of step k-1, exactly as if it had run right then.
+void resolve_pending(Solver &s) {
+  if (!s.pending) return;
+  const int slot = s.pending_slot;
+  MTS_HIP(hipEventSynchronize(s.flag_event[slot]));
+  s.pending = false;
+  if (s.pinned_flag[slot]) {
+    s.pinned_flag[slot] = 0;
+    coupling_rebuild(s, s.mask_snap[slot]);
+    s.n_rebuilds++;
+  }
+}
+
 void advance_impl(Solver &s, int64_t n) {
   const bool coupled = s.p.mode == MTS_COUPLED;
+  const bool track = coupled && s.m >= 2;
   for (int64_t k = 0; k < n; k++) {
     if (coupled) {
       hipEvent_t e0 = nullptr;
@@ -266,19 +287,20 @@ void advance_impl(Solver &s, int64_t n) {
       s.prof_end(MTS_KT_FE, e0);
     }
     for (int j = 1; j <= s.m; j++) pd_substep(s, j);
-    if (coupled) {
-      coupling_solve_and_correct(s);
-      if (s.m >= 2) {
-        // Algorithm 1, last step: rebuild the unit-load responses when a bond
-        // inside their support broke during this macro step.
-        MTS_HIP(hipMemcpyAsync(s.pinned_flag, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-        MTS_HIP(hipStreamSynchronize(s.stream));
-        if (*s.pinned_flag) {
-          MTS_HIP(hipMemsetAsync(s.region_flag, 0, sizeof(int32_t), s.stream));
-          coupling_rebuild(s);
-          s.n_rebuilds++;
-        }
-      }
+    int slot = -1;
+    if (track) {
+      slot = (int)(s.macro_steps & 1);
+      MTS_HIP(hipMemcpyAsync(s.mask_snap[slot], s.sell.mask, sizeof(uint64_t) * s.sell.n_words,
+                             hipMemcpyDeviceToDevice, s.stream));
+      MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+      MTS_HIP(hipMemsetAsync(s.region_flag, 0, sizeof(int32_t), s.stream));
+      MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
+    }
+    resolve_pending(s);  // previous macro step's check
+    if (coupled) coupling_solve_and_correct(s);
+    if (track) {
+      s.pending = true;
+      s.pending_slot = slot;
     }
     s.macro_steps++;
   }
@@ -412,6 +434,7 @@ mts_status mts_advance(mts_solver *h, int64_t n) {
 mts_status mts_sync(mts_solver *h) {
   if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
   try {
+    resolve_pending(h->s);
     MTS_HIP(hipStreamSynchronize(h->s.stream));
     check_finite(h->s);
     if (h->s.unstable) {
@@ -596,6 +619,8 @@ void mts_destroy(mts_solver *h) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s.flag_event)
+    if (e) (void)hipEventDestroy(e);
   if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
   s.arena.free_all();
   delete h;
