@@ -77,9 +77,13 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    os.environ.setdefault("MTS_VERBOSE", "1")  # setup progress on stderr
     import torch
     import mts_inputs as mi
     import paper_2403_03605_amd as mts
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -88,6 +92,7 @@ def main():
     W = args.warmup
     stream = torch.cuda.Stream()
     sh = stream.cuda_stream
+    log(f"workload {inst['name']}: {K} timed macro steps after {W} warm-up steps")
 
     if W > 0:  # warm-up on a throwaway solver of the same workload
         with torch.cuda.stream(stream):

@@ -83,6 +83,8 @@ def lattice_positions(n, lo, dx: float, perturb: float = 0.0, seed: int = SEED_B
 # Instances
 # ---------------------------------------------------------------------------
 GLASS = dict(E=72e9, rho=2440.0, G0=3.8)
+# steel of the paper's impact example (Sec. 4.2): critical stretch given directly
+STEEL = dict(E=191e9, rho=8000.0, G0=0.0, s_crit=0.01)
 
 
 def plate2d(nx: int, m: int, n_pd_steps: int, dt_pd: float, *, perturb: float = 0.0,
@@ -129,10 +131,10 @@ def plate2d(nx: int, m: int, n_pd_steps: int, dt_pd: float, *, perturb: float = 
 def block3d(nx: int, ny: int, nz: int, m: int, n_pd_steps: int, dt_pd: float, *,
             perturb: float = 0.0, seed: int = SEED_BASE, precision: str = "fp64",
             vel_bc: float = 20.0, mode: str = "coupled", breaking: bool = True,
-            name: str = "block3d") -> Dict:
+            material: str = "glass", name: str = "block3d") -> Dict:
     """3D PD block nx x ny x nz (dx = 1 mm scale: dx = 0.02 / nz) spanning the full
     width and thickness of a hex8 bar 2 nx dx long, centred along x; prescribed
-    velocity vel_bc on the bar face x = 0."""
+    velocity vel_bc on the bar face x = 0.  material: "glass" or "steel"."""
     dx = 0.02 / nz
     Lx, Ly, Lz = 2.0 * nx * dx, ny * dx, nz * dx
     pd_lo = (0.5 * nx * dx, 0.0, 0.0)
@@ -147,7 +149,7 @@ def block3d(nx: int, ny: int, nz: int, m: int, n_pd_steps: int, dt_pd: float, *,
         overlap=3.0 * dx, weight="cubic", cracks=[],
         thickness=1.0, kernel="pmb", l_over_delta=1.0 / 16.0,
         traction=0.0, vel_bc=vel_bc,
-        m=m, dt_pd=dt_pd, n_macro=n_pd_steps // m, **GLASS,
+        m=m, dt_pd=dt_pd, n_macro=n_pd_steps // m, **(STEEL if material == "steel" else GLASS),
     )
     if mode == "pure_pd":
         inst.update(dom_lo=pd_lo, dom_hi=pd_hi, fe_n=(0, 0, 0))
@@ -185,7 +187,8 @@ def config(k: int, **over) -> Dict:
         return plate2d(**kw)
     if k == 3:
         kw = dict(nx=100, ny=100, nz=20, m=8, n_pd_steps=2000, dt_pd=DT["C4"], perturb=1e-6,
-                  seed=SEED_BASE + 3, precision="mixed", name="C4 block 100x100x20 m=8 mixed")
+                  seed=SEED_BASE + 3, precision="mixed", material="steel",
+                  name="C4 block 100x100x20 m=8 mixed")
         kw.update(over)
         return block3d(**kw)
     raise ValueError(k)

@@ -226,6 +226,16 @@ void coupling_setup(Solver &s) {
   MTS_HIP(hipMemcpyAsync(s.f2c_ptr, cnt.data(), sizeof(int32_t) * (s.nfe + 1), hipMemcpyHostToDevice, st));
   if (!f2c.empty())
     MTS_HIP(hipMemcpyAsync(s.f2c, f2c.data(), sizeof(int32_t) * f2c.size(), hipMemcpyHostToDevice, st));
+  {
+    std::vector<int32_t> ring;
+    for (int64_t n = 0; n < s.nfe; n++)
+      if (cnt[n + 1] > cnt[n]) ring.push_back((int32_t)n);
+    s.n_ring = (int64_t)ring.size();
+    s.fe_ring = ar.alloc<int32_t>(ring.size());
+    if (!ring.empty())
+      MTS_HIP(hipMemcpyAsync(s.fe_ring, ring.data(), sizeof(int32_t) * ring.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
 
   // link region: nodes within (m-1) horizons of a constraint node
   double Rr = (double)(s.m - 1) * s.prm.delta;
@@ -329,8 +339,63 @@ void coupling_setup(Solver &s) {
   s.rhs = ar.alloc<double>(s.nl);
   MTS_HIP(hipMemsetAsync(s.lam, 0, sizeof(double) * s.nl, st));
   MTS_HIP(hipMemsetAsync(s.lam0, 0, sizeof(double) * s.nl, st));
-  s.Hinv = ar.alloc<double>((size_t)s.nl * s.nl);
+  s.H = ar.alloc<double>((size_t)s.nl * s.nl);
   s.keep_h = s.nl <= 4096;
+  // connected components of the coupling graph: constraints farther apart than
+  // both the response reach and two element diagonals never share an entry of H
+  {
+    const double h = s.p.fe_h;
+    const double J = std::max(Rr, 2.0 * std::sqrt((double)dim) * h) + s.prm.delta;
+    std::vector<int32_t> parent(s.nc);
+    for (int64_t q = 0; q < s.nc; q++) parent[q] = (int32_t)q;
+    auto find = [&](int32_t a) {
+      while (parent[a] != a) a = parent[a] = parent[parent[a]];
+      return a;
+    };
+    double lo[3] = {0, 0, 0};
+    for (int a = 0; a < dim; a++) lo[a] = s.p.pd_lo[a] - 2 * s.prm.delta;
+    auto key = [&](int64_t q, const int64_t off[3]) {
+      int64_t c[3] = {0, 0, 0};
+      for (int a = 0; a < dim; a++) c[a] = (int64_t)std::floor((s.pos[(int64_t)s.h_cn[q] * dim + a] - lo[a]) / J) + off[a];
+      return (c[2] * 1000003LL + c[1]) * 1000003LL + c[0];
+    };
+    std::unordered_map<int64_t, std::vector<int32_t>> cells;
+    const int64_t zero[3] = {0, 0, 0};
+    for (int64_t q = 0; q < s.nc; q++) cells[key(q, zero)].push_back((int32_t)q);
+    int zr = dim == 3 ? 1 : 0;
+    for (int64_t q = 0; q < s.nc; q++)
+      for (int dz = -zr; dz <= zr; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dxx = -1; dxx <= 1; dxx++) {
+            const int64_t off[3] = {dxx, dy, dz};
+            auto it = cells.find(key(q, off));
+            if (it == cells.end()) continue;
+            for (int32_t p : it->second) {
+              double r2 = 0;
+              for (int a = 0; a < dim; a++) {
+                double t = s.pos[(int64_t)s.h_cn[p] * dim + a] - s.pos[(int64_t)s.h_cn[q] * dim + a];
+                r2 += t * t;
+              }
+              if (r2 <= J * J) {
+                int32_t ra = find((int32_t)q), rb = find(p);
+                if (ra != rb) parent[std::max(ra, rb)] = std::min(ra, rb);
+              }
+            }
+          }
+    std::vector<int32_t> label(s.nc, -1);
+    std::vector<std::vector<int32_t>> comps;
+    for (int64_t q = 0; q < s.nc; q++) {
+      int32_t r = find((int32_t)q);
+      if (label[r] < 0) {
+        label[r] = (int32_t)comps.size();
+        comps.emplace_back();
+      }
+      for (int d = 0; d < dim; d++) comps[label[r]].push_back((int32_t)(q * dim + d));
+    }
+    sym_blocks_setup(s, comps);
+    vlog(s, "coupling: %lld constraints, %lld colours, %lld components, largest %lld dofs", (long long)s.nc,
+         (long long)s.n_colors, (long long)s.sym.n_comp, (long long)s.sym.n_max);
+  }
   for (int k = 0; k < 2; k++) {
     s.mask_snap[k] = ar.alloc<uint64_t>(s.sell.n_words);
     MTS_HIP(hipEventCreateWithFlags(&s.flag_event[k], hipEventDisableTiming));
@@ -344,7 +409,7 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   hipStream_t st = s.stream;
   const int64_t nl = s.nl;
   sell_regather_mask(s, s.rsell, full_mask);
-  MTS_HIP(hipMemsetAsync(s.Hinv, 0, sizeof(double) * nl * nl, st));
+  MTS_HIP(hipMemsetAsync(s.H, 0, sizeof(double) * nl * nl, st));
   const int cpb = s.nrhs / dim;  // colours per batch
   int32_t rc[16], rd[16];
   int32_t *drc = nullptr, *drd = nullptr;
@@ -368,7 +433,7 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     }
     MTS_HIP(hipMemcpyAsync(drc, rc, sizeof(rc), hipMemcpyHostToDevice, st));
     MTS_HIP(hipMemcpyAsync(drd, rd, sizeof(rd), hipMemcpyHostToDevice, st));
-    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drc, drd, s.Wv, s.N, s.Hinv);
+    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drc, drd, s.Wv, s.N, s.H);
     MTS_LAUNCH_CHECK();
     // the host arrays rc/rd are reused next iteration
     MTS_HIP(hipStreamSynchronize(st));
@@ -377,14 +442,16 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, s.nrhs);
   dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
   k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
-                                s.p.fe_n[1], s.Hinv);
+                                s.p.fe_n[1], s.H);
   MTS_LAUNCH_CHECK();
+  vlog(s, "coupling: unit-load responses done (%lld colour batches)", (long long)((s.n_colors + cpb - 1) / cpb));
   if (s.keep_h) {
     if (!s.Hcopy) s.Hcopy = s.arena.alloc<double>((size_t)nl * nl);
-    MTS_HIP(hipMemcpyAsync(s.Hcopy, s.Hinv, sizeof(double) * nl * nl, hipMemcpyDeviceToDevice, st));
+    MTS_HIP(hipMemcpyAsync(s.Hcopy, s.H, sizeof(double) * nl * nl, hipMemcpyDeviceToDevice, st));
   }
-  dense_spd_inverse(s, s.Hinv, nl);
+  sym_blocks_build(s);
   MTS_HIP(hipStreamSynchronize(st));
+  vlog(s, "coupling: H inverted");
 }
 
 void coupling_solve_and_correct(Solver &s) {
@@ -393,7 +460,7 @@ void coupling_solve_and_correct(Solver &s) {
   s.prof_begin(MTS_KT_LAMBDA, &e0);
   k_rhs<<<nb(s.nc), 256, 0, st>>>(s.nc, s.dim, s.nen, s.cn, s.cel, s.conn, s.cw, s.vt, s.v, s.N, s.rhs);
   MTS_LAUNCH_CHECK();
-  dense_gemv(st, s.Hinv, s.rhs, s.lam, s.nl);
+  sym_blocks_apply(s, s.rhs, s.lam);
   s.prof_end(MTS_KT_LAMBDA, e0);
   fe_correct(s);
   // PD: U = V + Y lambda_m by re-running the link problem with lambda_m

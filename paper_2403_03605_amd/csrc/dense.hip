@@ -1,8 +1,13 @@
-// Dense FP64 linear algebra for the multiplier system of Eq. 49: the symmetric
-// positive-definite matrix H is inverted once per (re)build by blocked in-place
-// Gauss-Jordan elimination (no pivoting, SPD), and every macro step applies
-// the inverse with a row-per-wavefront GEMV.
+// Dense FP64 linear algebra for the multiplier system of Eq. 49: each diagonal
+// block of the symmetric positive-definite matrix H (one per connected
+// component of the coupling graph) is inverted once per (re)build by blocked
+// in-place Gauss-Jordan elimination (no pivoting, SPD) and stored as its
+// lower-triangle 64 x 64 tiles; every macro step applies the inverse with a
+// tile-parallel symmetric GEMV whose partial sums are combined in a fixed order.
 #include "internal.h"
+
+#include <algorithm>
+#include <cmath>
 
 namespace mts {
 
@@ -118,25 +123,15 @@ __global__ __launch_bounds__(256) void k_rank_update(double *A, int64_t n, int k
   }
 }
 
-__global__ __launch_bounds__(256) void k_gemv(const double *A, const double *x, double *y, int64_t n) {
-  int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  int lane = threadIdx.x & (WAVE - 1);
-  if (row >= n) return;
-  const double *a = A + row * n;
-  double s = 0.0;
-  for (int64_t j = lane; j < n; j += WAVE) s += a[j] * x[j];
-  for (int off = WAVE / 2; off > 0; off >>= 1) s += __shfl_down(s, off, WAVE);
-  if (lane == 0) y[row] = s;
-}
-
 }  // namespace
 
 void dense_spd_inverse(Solver &s, double *A, int64_t n) {
   hipStream_t st = s.stream;
   if (n <= 0) return;
-  if (!s.tmpA) {
-    s.tmpA = s.arena.alloc<double>((size_t)n * NB);
-    s.tmpB = s.arena.alloc<double>((size_t)n * NB);
+  if (!s.tmpA) {  // sized for the largest block this solver will ever invert
+    const int64_t cap = std::max<int64_t>(n, s.sym.n_max);
+    s.tmpA = s.arena.alloc<double>((size_t)cap * NB);
+    s.tmpB = s.arena.alloc<double>((size_t)cap * NB);
     s.pinv = s.arena.alloc<double>((size_t)NB * NB);
   }
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
@@ -154,10 +149,155 @@ void dense_spd_inverse(Solver &s, double *A, int64_t n) {
   }
 }
 
-void dense_gemv(hipStream_t st, const double *A, const double *x, double *y, int64_t n) {
-  if (n <= 0) return;
-  unsigned grid = (unsigned)((n * WAVE + 255) / 256);
-  k_gemv<<<grid, 256, 0, st>>>(A, x, y, n);
+
+// ---------------------------------------------------------------------------
+// Block-diagonal inverse in packed lower-triangle tiles
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int TS = 64;  // tile side
+
+// work[i][j] = H[idx[i]][idx[j]] for one component
+__global__ void k_gather_block(const double *H, int64_t nl, const int32_t *idx, int64_t n, double *work) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  int64_t i = t / n, j = t % n;
+  work[t] = H[(int64_t)idx[i] * nl + idx[j]];
+}
+
+// packed[tile (I, J), J <= I][r][c] = work[64 I + r][64 J + c] (0 outside)
+__global__ void k_pack_tiles(const double *work, int64_t n, int64_t T, double *packed) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t ntile = T * (T + 1) / 2;
+  if (t >= ntile * TS * TS) return;
+  int64_t tile = t / (TS * TS);
+  int e = (int)(t % (TS * TS));
+  int64_t I = (int64_t)((sqrt(8.0 * (double)tile + 1.0) - 1.0) / 2.0);
+  while (I * (I + 1) / 2 > tile) I--;
+  while ((I + 1) * (I + 2) / 2 <= tile) I++;
+  int64_t J = tile - I * (I + 1) / 2;
+  int64_t i = I * TS + e / TS, j = J * TS + e % TS;
+  packed[t] = (i < n && j < n) ? work[i * n + j] : 0.0;
+}
+
+// One workgroup per tile: row partial A_IJ x_J (for block row I) and, off the
+// diagonal, column partial A_IJ^T x_I (for block row J).
+__global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
+                                                   const int64_t *off, const int32_t *idx, const double *r,
+                                                   double *rowpart, double *colpart) {
+  __shared__ double A[TS][TS + 1];
+  __shared__ double xI[TS], xJ[TS];
+  const int64_t tile = blockIdx.x;
+  const int comp = tile_meta[tile * 3 + 0], I = tile_meta[tile * 3 + 1], J = tile_meta[tile * 3 + 2];
+  const int64_t base = off[comp], n = off[comp + 1] - off[comp];
+  const double *src = packed + tile * TS * TS;
+  for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) A[e / TS][e % TS] = src[e];
+  if (threadIdx.x < TS) {
+    int64_t gi = (int64_t)I * TS + threadIdx.x, gj = (int64_t)J * TS + threadIdx.x;
+    xI[threadIdx.x] = gi < n ? r[idx[base + gi]] : 0.0;
+    xJ[threadIdx.x] = gj < n ? r[idx[base + gj]] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < TS) {
+    int rr = threadIdx.x;
+    double s = 0.0;
+    for (int c = 0; c < TS; c++) s += A[rr][c] * xJ[c];
+    rowpart[tile * TS + rr] = s;
+  } else if (threadIdx.x < 2 * TS && I != J) {
+    int c = threadIdx.x - TS;
+    double s = 0.0;
+    for (int rr = 0; rr < TS; rr++) s += A[rr][c] * xI[rr];
+    colpart[tile * TS + c] = s;
+  }
+}
+
+// y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I), fixed order.
+__global__ void k_sym_reduce(const int64_t *off, const int64_t *tile_base, int64_t n_comp, int64_t nl,
+                             const int32_t *idx, const double *rowpart, const double *colpart, double *y) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nl) return;
+  int64_t c = 0;
+  while (c + 1 < n_comp && off[c + 1] <= p) c++;
+  const int64_t i = p - off[c], n = off[c + 1] - off[c];
+  const int64_t T = (n + TS - 1) / TS, I = i / TS, rr = i % TS;
+  const int64_t tb = tile_base[c];
+  double s = 0.0;
+  for (int64_t J = 0; J <= I; J++) s += rowpart[(tb + I * (I + 1) / 2 + J) * TS + rr];
+  for (int64_t J = I + 1; J < T; J++) s += colpart[(tb + J * (J + 1) / 2 + I) * TS + rr];
+  y[idx[p]] = s;
+}
+
+}  // namespace
+
+void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps) {
+  auto &B = s.sym;
+  DeviceArena &ar = s.arena;
+  hipStream_t st = s.stream;
+  B.n_comp = (int64_t)comps.size();
+  B.h_off.assign(B.n_comp + 1, 0);
+  B.h_idx.clear();
+  std::vector<int64_t> tbase(B.n_comp + 1, 0);
+  std::vector<int32_t> meta;
+  B.n_max = 0;
+  for (int64_t c = 0; c < B.n_comp; c++) {
+    int64_t n = (int64_t)comps[c].size();
+    B.h_off[c + 1] = B.h_off[c] + n;
+    B.h_idx.insert(B.h_idx.end(), comps[c].begin(), comps[c].end());
+    B.n_max = std::max(B.n_max, n);
+    int64_t T = (n + TS - 1) / TS;
+    tbase[c + 1] = tbase[c] + T * (T + 1) / 2;
+    for (int64_t I = 0; I < T; I++)
+      for (int64_t J = 0; J <= I; J++) {
+        meta.push_back((int32_t)c);
+        meta.push_back((int32_t)I);
+        meta.push_back((int32_t)J);
+      }
+  }
+  B.n_tiles = tbase[B.n_comp];
+  B.idx = ar.alloc<int32_t>(B.h_idx.size());
+  B.off = ar.alloc<int64_t>(B.n_comp + 1);
+  B.tile_meta = ar.alloc<int32_t>(meta.size());
+  B.tile_base = ar.alloc<int64_t>(B.n_comp + 1);
+  B.packed = ar.alloc<double>((size_t)B.n_tiles * TS * TS);
+  B.rowpart = ar.alloc<double>((size_t)B.n_tiles * TS);
+  B.colpart = ar.alloc<double>((size_t)B.n_tiles * TS);
+  B.work = ar.alloc<double>((size_t)B.n_max * B.n_max);
+  MTS_HIP(hipMemcpyAsync(B.idx, B.h_idx.data(), sizeof(int32_t) * B.h_idx.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.off, B.h_off.data(), sizeof(int64_t) * (B.n_comp + 1), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.tile_meta, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.tile_base, tbase.data(), sizeof(int64_t) * (B.n_comp + 1), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemsetAsync(B.colpart, 0, sizeof(double) * B.n_tiles * TS, st));
+  MTS_HIP(hipStreamSynchronize(st));
+}
+
+// Invert every component block of H (already assembled in s.H) and pack it.
+void sym_blocks_build(Solver &s) {
+  auto &B = s.sym;
+  hipStream_t st = s.stream;
+  std::vector<int64_t> tbase(B.n_comp + 1, 0);
+  for (int64_t c = 0; c < B.n_comp; c++) {
+    int64_t n = B.h_off[c + 1] - B.h_off[c];
+    int64_t T = (n + TS - 1) / TS;
+    tbase[c + 1] = tbase[c] + T * (T + 1) / 2;
+    k_gather_block<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(s.H, s.nl, B.idx + B.h_off[c], n, B.work);
+    MTS_LAUNCH_CHECK();
+    dense_spd_inverse(s, B.work, n);
+    int64_t ne = T * (T + 1) / 2 * TS * TS;
+    k_pack_tiles<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(B.work, n, T, B.packed + tbase[c] * TS * TS);
+    MTS_LAUNCH_CHECK();
+    vlog(s, "coupling: block %lld of %lld inverted (%lld dofs)", (long long)(c + 1), (long long)B.n_comp,
+         (long long)n);
+  }
+}
+
+void sym_blocks_apply(Solver &s, const double *r, double *y) {
+  auto &B = s.sym;
+  if (!B.n_tiles) return;
+  k_sym_tiles<<<(unsigned)B.n_tiles, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.rowpart,
+                                                         B.colpart);
+  MTS_LAUNCH_CHECK();
+  k_sym_reduce<<<(unsigned)((s.nl + 255) / 256), 256, 0, s.stream>>>(B.off, B.tile_base, B.n_comp, s.nl, B.idx,
+                                                                    B.rowpart, B.colpart, y);
   MTS_LAUNCH_CHECK();
 }
 

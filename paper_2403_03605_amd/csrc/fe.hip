@@ -247,10 +247,13 @@ __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *
 
 // Gather element forces per node (ascending element order), then the free
 // problem's acceleration and velocity (Eq. 47a).
+// Nodes that carry no multiplier (no constraint interpolates from them) are
+// final after the free problem and are written to the state directly.
 __global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n2e_ptr, const int32_t *n2e,
                                  const uint8_t *eact, const uint8_t *nact, const uint8_t *bc, const double *fe_buf,
-                                 const double *PF, const double *mF, const double *v, const double *a, double hdt,
-                                 double vbc, double *at, double *vt) {
+                                 const double *PF, const double *mF, double *v, double *a, double hdt,
+                                 double vbc, double *at, double *vt, const int32_t *f2c_ptr, const double *ut,
+                                 double *u) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nfe || !nact[n]) return;
   double f[3] = {0.0, 0.0, 0.0};
@@ -260,14 +263,59 @@ __global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n
     if (!eact[e]) continue;
     for (int d = 0; d < dim; d++) f[d] += fe_buf[(e * nen + la) * dim + d];
   }
+  const bool final_now = !f2c_ptr || f2c_ptr[n + 1] == f2c_ptr[n];
   for (int d = 0; d < dim; d++) {
     int64_t t = n * dim + d;
+    double an, vn;
     if (bc[t]) {
-      at[t] = 0.0;
-      vt[t] = vbc;
+      an = 0.0;
+      vn = vbc;
     } else {
-      at[t] = (PF[t] - f[d]) / mF[n];
-      vt[t] = v[t] + hdt * (a[t] + at[t]);
+      an = (PF[t] - f[d]) / mF[n];
+      vn = v[t] + hdt * (a[t] + an);
+    }
+    if (final_now) {
+      u[t] = ut[t];
+      v[t] = vn;
+      a[t] = an;
+    } else {
+      at[t] = an;
+      vt[t] = vn;
+    }
+  }
+}
+
+// Final update of the overlap FE nodes: U = V + Y^FE lambda with
+// Y^FE = (-M^-1 G_F^T, -dt/2 M^-1 G_F^T, 0) (Eq. 50, link problem Eq. 47b at
+// beta = 0).  One wavefront per node, lanes over its constraint entries.
+__global__ void k_fe_correct_ring(int64_t n_ring, const int32_t *ring, int dim, int nen, const uint8_t *bc,
+                                  const int32_t *f2c_ptr, const int32_t *f2c, const double *cw, const double *lam,
+                                  const double *mF, const double *ut, const double *vt, const double *at,
+                                  double hdt, double *uF, double *vF, double *aF) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  if (w >= n_ring) return;
+  const int64_t n = ring[w];
+  double tl[3] = {0.0, 0.0, 0.0};
+  for (int t = f2c_ptr[n] + lane; t < f2c_ptr[n + 1]; t += WAVE) {
+    const int64_t q = f2c[t] / nen;
+    const int aa = f2c[t] % nen;
+    const double wgt = cw[q * nen + aa];
+    for (int d = 0; d < dim; d++) tl[d] += wgt * lam[q * dim + d];
+  }
+  for (int off = WAVE / 2; off >= 1; off >>= 1)
+    for (int d = 0; d < 3; d++) tl[d] += __shfl_down(tl[d], off, WAVE);
+  if (lane != 0) return;
+  for (int d = 0; d < dim; d++) {
+    const int64_t t = n * dim + d;
+    uF[t] = ut[t];
+    if (bc[t]) {
+      vF[t] = vt[t];
+      aF[t] = at[t];
+    } else {
+      const double g = tl[d] / mF[n];
+      aF[t] = at[t] - g;
+      vF[t] = vt[t] - hdt * g;
     }
   }
 }
@@ -447,13 +495,16 @@ void fe_free_step(Solver &s) {
     k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness, s.fe_buf);
   MTS_LAUNCH_CHECK();
   k_fe_gather_free<<<nb(nfe), 256, 0, st>>>(nfe, s.dim, s.nen, s.n2e_ptr, s.n2e, s.eact, s.nact, s.bc, s.fe_buf,
-                                            s.PF, s.mF, s.vF, s.aF, s.prm.hdtF, s.p.vel_bc, s.at, s.vt);
+                                            s.PF, s.mF, s.vF, s.aF, s.prm.hdtF, s.p.vel_bc, s.at, s.vt, s.f2c_ptr,
+                                            s.ut, s.uF);
   MTS_LAUNCH_CHECK();
 }
 
 void fe_correct(Solver &s) {
-  k_fe_correct<<<nb(s.nfe), 256, 0, s.stream>>>(s.nfe, s.dim, s.nen, s.nact, s.bc, s.f2c_ptr, s.f2c, s.cw, s.lam,
-                                                s.mF, s.ut, s.vt, s.at, s.prm.hdtF, s.uF, s.vF, s.aF);
+  if (!s.n_ring) return;
+  k_fe_correct_ring<<<(unsigned)((s.n_ring * WAVE + 255) / 256), 256, 0, s.stream>>>(
+      s.n_ring, s.fe_ring, s.dim, s.nen, s.bc, s.f2c_ptr, s.f2c, s.cw, s.lam, s.mF, s.ut, s.vt, s.at, s.prm.hdtF,
+      s.uF, s.vF, s.aF);
   MTS_LAUNCH_CHECK();
 }
 

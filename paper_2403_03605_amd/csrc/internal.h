@@ -149,8 +149,24 @@ struct Solver {
   int32_t *cel = nullptr;        // constraint -> element
   double *cw = nullptr;          // nc * nen interpolation weights N_a(x_p)
   int32_t *f2c_ptr = nullptr, *f2c = nullptr;  // FE node -> (constraint*nen + a)
+  int32_t *fe_ring = nullptr;    // FE nodes with constraint entries
+  int64_t n_ring = 0;
   double *lam = nullptr, *lam0 = nullptr, *rhs = nullptr;
-  double *Hinv = nullptr;        // nl * nl, row-major
+  double *H = nullptr;           // nl * nl, row-major assembly buffer of H
+  // Inverse of H, block-diagonal over connected components of the coupling
+  // graph; each block stored as its lower-triangle 64 x 64 tiles.
+  struct SymBlocks {
+    int64_t n_comp = 0, n_tiles = 0, n_max = 0;
+    std::vector<int64_t> h_off;     // component dof offsets (n_comp + 1)
+    std::vector<int32_t> h_idx;     // concatenated dof indices
+    int32_t *idx = nullptr;         // device copy
+    int64_t *off = nullptr;         // device copy of h_off
+    int32_t *tile_meta = nullptr;   // per tile: component, I, J
+    int64_t *tile_base = nullptr;   // per component: first tile
+    double *packed = nullptr;       // n_tiles * 4096
+    double *rowpart = nullptr, *colpart = nullptr;  // n_tiles * 64
+    double *work = nullptr;         // n_max * n_max
+  } sym;
   double *tmpA = nullptr, *tmpB = nullptr, *pinv = nullptr;
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;
@@ -169,6 +185,9 @@ struct Solver {
   hipEvent_t flag_event[2] = {nullptr, nullptr};
   bool pending = false;
   int pending_slot = 0;
+
+  bool verbose = false;
+  double t_create0 = 0.0;
 
   // profiling
   bool profiling = false;
@@ -204,7 +223,11 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask);
 void coupling_solve_and_correct(Solver &s);
 // dense linear algebra (dense.hip)
 void dense_spd_inverse(Solver &s, double *A, int64_t n);
-void dense_gemv(hipStream_t st, const double *A, const double *x, double *y, int64_t n);
+void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
+void sym_blocks_build(Solver &s);
+void sym_blocks_apply(Solver &s, const double *r, double *y);
+// progress log on stderr when MTS_VERBOSE is set
+void vlog(const Solver &s, const char *fmt, ...);
 // scans (neighbors.hip)
 void exclusive_scan_i64(hipStream_t st, DeviceArena &ar, const int64_t *in, int64_t *out, int64_t n);
 

@@ -7,7 +7,26 @@
 
 #include "internal.h"
 
+#include <chrono>
+#include <cstdarg>
+#include <cstdlib>
+
 namespace mts {
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void vlog(const Solver &s, const char *fmt, ...) {
+  if (!s.verbose) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[mtspd %8.3f s] %s\n", now_s() - s.t_create0, buf);
+  std::fflush(stderr);
+}
 
 void DeviceArena::release(void *p) {
   for (size_t k = 0; k < blocks.size(); k++)
@@ -162,6 +181,8 @@ void derive_params(Solver &s) {
 
 void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   validate(pin);
+  s->verbose = std::getenv("MTS_VERBOSE") != nullptr;
+  s->t_create0 = now_s();
   s->p = *pin;
   const int dim = s->dim = pin->dim;
   const int64_t N = s->N = pin->n_pd;
@@ -195,9 +216,11 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   s->region_flag = ar.alloc<int32_t>(1);
   MTS_HIP(hipMemsetAsync(s->region_flag, 0, sizeof(int32_t), st));
   build_neighbors(*s);
+  vlog(*s, "neighbours: %lld nodes, %lld bonds, %d lanes per row", (long long)N, (long long)s->nnz, s->sell.L);
   pd_setup(*s);
   if (pin->mode == MTS_COUPLED) {
     fe_setup(*s);
+    vlog(*s, "fe: %lld nodes, %lld elements", (long long)s->nfe, (long long)s->ne);
     coupling_setup(*s);
   }
   pd_predict_all(*s);
