@@ -40,6 +40,34 @@ def bytes_per_launch(info, inst):
     return info["nnz"] * per_bond + info["n_pd"] * per_node, per_bond, per_node
 
 
+def source_digest():
+    """Digest of the sources the PD substep kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pd.hip", "device_math.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2403_03605_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(inst):
+    """Measured HBM bytes per PD substep launch (FETCH_SIZE + WRITE_SIZE from
+    two counter runs, scaled by the copy-kernel calibration), read from the
+    committed counter summary; None when it is missing, was taken for another
+    workload, or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_pd_substep_traffic.md")
+    try:
+        with open(path) as fh:
+            text = fh.read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
+    w = rec.get("workloads", {}).get(inst["name"])
+    if not w or rec.get("source_digest") != source_digest():
+        return None
+    return w["bytes_per_launch"]
+
+
 def cpu_baseline(inst, seconds=15.0):
     """The oracle as it stands, single thread, on the same seeded lattice in
     pure-PD mode (the PD substep path: bond pass with breaking + Verlet)."""
@@ -71,7 +99,10 @@ def main():
     ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (counter calibration)")
+    ap.add_argument("--profile-steps", type=int, default=100, help="macro steps of the event-timed pass")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -79,6 +110,15 @@ def main():
 
     os.environ.setdefault("MTS_VERBOSE", "1")  # setup progress on stderr
     import torch
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "reps": 5}), flush=True)
+        return
     import mts_inputs as mi
     import paper_2403_03605_amd as mts
 
@@ -107,42 +147,53 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = s.query()
-    if not args.no_profile:
-        s.profile(True)
 
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    s.advance(K)
-    ev1.record(stream)
-    s.sync()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(wall, gpu_ms / 1e3)
+    def timed(n):
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        s.advance(n)
+        ev1.record(stream)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        return max(wall, gpu_ms / 1e3), wall, gpu_ms
+
+    # timed region: K macro steps, no per-kernel events
+    elapsed, wall, gpu_ms = timed(K)
     info = s.query()
     bond_updates = K * inst["m"] * info["nnz"]
     value = bond_updates / elapsed
+    log(f"timed: {K} macro steps in {elapsed:.3f} s -> {value:.4g} bond-updates/s")
 
     roof = None
     if not args.no_profile:
+        # second timed region on the same solver with HIP events around every
+        # launch group (recorded on the solver's stream)
+        Kp = min(K, args.profile_steps)
+        s.profile(True)
+        p_elapsed, _, _ = timed(Kp)
         n_launch, ms = s.kernel_time(mts.KT_PD_SUBSTEP)
         avg_s = ms / 1e3 / max(n_launch, 1)
         b, per_bond, per_node = bytes_per_launch(info, inst)
         achieved = b / avg_s
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": traffic_per_launch(inst),
                 "kernel": "k_pd_substep", "launches": n_launch, "avg_launch_us": avg_s * 1e6,
                 "algorithmic_bytes_per_launch": b, "bytes_per_bond": per_bond,
                 "bytes_per_node": per_node,
-                "kernel_bond_updates_per_s": info["nnz"] / avg_s}
+                "kernel_bond_updates_per_s": info["nnz"] / avg_s,
+                "profiled_macro_steps": Kp,
+                "profiled_pass_bond_updates_per_s": Kp * inst["m"] * info["nnz"] / p_elapsed}
         other = {}
         for name, k in (("link", mts.KT_LINK), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA)):
             n_l, ms_l = s.kernel_time(k)
             other[name] = {"launch_groups": n_l, "total_ms": ms_l}
         roof["other_phases"] = other
+    info = s.query()
     s.close()
 
     cpu = None
@@ -158,6 +209,7 @@ def main():
                    "pd_nodes": info["n_pd"], "bonds": info["nnz"], "m": inst["m"],
                    "fe_nodes": info["n_fe_nodes"], "constraints": info["n_constraints"],
                    "dt_pd": inst["dt_pd"], "rebuilds": info["n_rebuilds"], "setup_s": setup_s,
+                   "source_digest": source_digest(),
                    "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3},
         "roofline": roof, "cpu_baseline": cpu,
     }

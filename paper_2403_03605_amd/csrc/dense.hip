@@ -181,7 +181,8 @@ __global__ void k_pack_tiles(const double *work, int64_t n, int64_t T, double *p
 }
 
 // One workgroup per tile: row partial A_IJ x_J (for block row I) and, off the
-// diagonal, column partial A_IJ^T x_I (for block row J).
+// diagonal, column partial A_IJ^T x_I (for block row J).  Four threads share a
+// row (or column), 16 products each, combined by a fixed butterfly.
 __global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
                                                    const int64_t *off, const int32_t *idx, const double *r,
                                                    double *rowpart, double *colpart) {
@@ -190,41 +191,62 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const i
   const int64_t tile = blockIdx.x;
   const int comp = tile_meta[tile * 3 + 0], I = tile_meta[tile * 3 + 1], J = tile_meta[tile * 3 + 2];
   const int64_t base = off[comp], n = off[comp + 1] - off[comp];
-  const double *src = packed + tile * TS * TS;
-  for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) A[e / TS][e % TS] = src[e];
-  if (threadIdx.x < TS) {
-    int64_t gi = (int64_t)I * TS + threadIdx.x, gj = (int64_t)J * TS + threadIdx.x;
-    xI[threadIdx.x] = gi < n ? r[idx[base + gi]] : 0.0;
-    xJ[threadIdx.x] = gj < n ? r[idx[base + gj]] : 0.0;
+  const double2 *src = reinterpret_cast<const double2 *>(packed + tile * TS * TS);
+  const int t = threadIdx.x;
+  double2 v[8];
+#pragma unroll
+  for (int q = 0; q < 8; q++) v[q] = src[q * 256 + t];
+  if (t < TS) {
+    int64_t gi = (int64_t)I * TS + t, gj = (int64_t)J * TS + t;
+    xI[t] = gi < n ? r[idx[base + gi]] : 0.0;
+    xJ[t] = gj < n ? r[idx[base + gj]] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    const int e = 2 * (q * 256 + t);
+    A[e / TS][e % TS] = v[q].x;
+    A[e / TS][e % TS + 1] = v[q].y;
   }
   __syncthreads();
-  if (threadIdx.x < TS) {
-    int rr = threadIdx.x;
-    double s = 0.0;
-    for (int c = 0; c < TS; c++) s += A[rr][c] * xJ[c];
-    rowpart[tile * TS + rr] = s;
-  } else if (threadIdx.x < 2 * TS && I != J) {
-    int c = threadIdx.x - TS;
-    double s = 0.0;
-    for (int rr = 0; rr < TS; rr++) s += A[rr][c] * xI[rr];
-    colpart[tile * TS + c] = s;
+  const int line = t >> 2, part = t & 3;
+  double rs = 0.0, cs = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    rs += A[line][part * 16 + k] * xJ[part * 16 + k];
+    cs += A[part * 16 + k][line] * xI[part * 16 + k];
+  }
+  rs += __shfl_xor(rs, 1, WAVE);
+  rs += __shfl_xor(rs, 2, WAVE);
+  cs += __shfl_xor(cs, 1, WAVE);
+  cs += __shfl_xor(cs, 2, WAVE);
+  if (part == 0) {
+    rowpart[tile * TS + line] = rs;
+    if (I != J) colpart[tile * TS + line] = cs;
   }
 }
 
-// y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I), fixed order.
-__global__ void k_sym_reduce(const int64_t *off, const int64_t *tile_base, int64_t n_comp, int64_t nl,
-                             const int32_t *idx, const double *rowpart, const double *colpart, double *y) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nl) return;
-  int64_t c = 0;
-  while (c + 1 < n_comp && off[c + 1] <= p) c++;
-  const int64_t i = p - off[c], n = off[c + 1] - off[c];
-  const int64_t T = (n + TS - 1) / TS, I = i / TS, rr = i % TS;
-  const int64_t tb = tile_base[c];
+// y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I).  One
+// workgroup per block row; wave w takes every 4th contribution and the four
+// wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_sym_reduce(const int64_t *off, const int64_t *tile_base,
+                                                    const int32_t *row_comp, const int32_t *row_block,
+                                                    const int32_t *idx, const double *rowpart,
+                                                    const double *colpart, double *y) {
+  __shared__ double part[4][TS];
+  const int64_t c = row_comp[blockIdx.x], I = row_block[blockIdx.x];
+  const int64_t n = off[c + 1] - off[c], T = (n + TS - 1) / TS, tb = tile_base[c];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
   double s = 0.0;
-  for (int64_t J = 0; J <= I; J++) s += rowpart[(tb + I * (I + 1) / 2 + J) * TS + rr];
-  for (int64_t J = I + 1; J < T; J++) s += colpart[(tb + J * (J + 1) / 2 + I) * TS + rr];
-  y[idx[p]] = s;
+  for (int64_t k = w; k < T; k += 4) {
+    s += k <= I ? rowpart[(tb + I * (I + 1) / 2 + k) * TS + lane] : colpart[(tb + k * (k + 1) / 2 + I) * TS + lane];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t i = I * TS + lane;
+    const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (i < n) y[idx[off[c] + i]] = tot;
+  }
 }
 
 }  // namespace
@@ -262,6 +284,19 @@ void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps)
   B.rowpart = ar.alloc<double>((size_t)B.n_tiles * TS);
   B.colpart = ar.alloc<double>((size_t)B.n_tiles * TS);
   B.work = ar.alloc<double>((size_t)B.n_max * B.n_max);
+  std::vector<int32_t> rc, rb;
+  for (int64_t c = 0; c < B.n_comp; c++) {
+    int64_t T = (B.h_off[c + 1] - B.h_off[c] + TS - 1) / TS;
+    for (int64_t I = 0; I < T; I++) {
+      rc.push_back((int32_t)c);
+      rb.push_back((int32_t)I);
+    }
+  }
+  B.n_rows = (int64_t)rc.size();
+  B.row_comp = ar.alloc<int32_t>(rc.size());
+  B.row_block = ar.alloc<int32_t>(rb.size());
+  MTS_HIP(hipMemcpyAsync(B.row_comp, rc.data(), sizeof(int32_t) * rc.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.row_block, rb.data(), sizeof(int32_t) * rb.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.idx, B.h_idx.data(), sizeof(int32_t) * B.h_idx.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.off, B.h_off.data(), sizeof(int64_t) * (B.n_comp + 1), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.tile_meta, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, st));
@@ -296,8 +331,8 @@ void sym_blocks_apply(Solver &s, const double *r, double *y) {
   k_sym_tiles<<<(unsigned)B.n_tiles, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.rowpart,
                                                          B.colpart);
   MTS_LAUNCH_CHECK();
-  k_sym_reduce<<<(unsigned)((s.nl + 255) / 256), 256, 0, s.stream>>>(B.off, B.tile_base, B.n_comp, s.nl, B.idx,
-                                                                    B.rowpart, B.colpart, y);
+  k_sym_reduce<<<(unsigned)B.n_rows, 256, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
+                                                        B.rowpart, B.colpart, y);
   MTS_LAUNCH_CHECK();
 }
 

@@ -320,35 +320,6 @@ __global__ void k_fe_correct_ring(int64_t n_ring, const int32_t *ring, int dim, 
   }
 }
 
-// Final FE update U = V + Y^FE lambda with Y^FE = (-M^-1 G_F^T, -dt/2 M^-1 G_F^T, 0)
-// (Eq. 50 with the link problem of Eq. 47b at beta = 0).
-__global__ void k_fe_correct(int64_t nfe, int dim, int nen, const uint8_t *nact, const uint8_t *bc,
-                             const int32_t *f2c_ptr, const int32_t *f2c, const double *cw, const double *lam,
-                             const double *mF, const double *ut, const double *vt, const double *at, double hdt,
-                             double *uF, double *vF, double *aF) {
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nfe || !nact[n]) return;
-  double tl[3] = {0.0, 0.0, 0.0};
-  if (f2c_ptr)
-    for (int t = f2c_ptr[n]; t < f2c_ptr[n + 1]; t++) {
-      int64_t q = f2c[t] / nen;
-      int a = f2c[t] % nen;
-      for (int d = 0; d < dim; d++) tl[d] += cw[q * nen + a] * lam[q * dim + d];
-    }
-  for (int d = 0; d < dim; d++) {
-    int64_t t = n * dim + d;
-    uF[t] = ut[t];
-    if (bc[t]) {
-      vF[t] = vt[t];
-      aF[t] = at[t];
-    } else {
-      double g = tl[d] / mF[n];
-      aF[t] = at[t] - g;
-      vF[t] = vt[t] - hdt * g;
-    }
-  }
-}
-
 inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 MeshGeo mesh_geo(const Solver &s) {

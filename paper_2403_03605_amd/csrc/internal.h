@@ -166,6 +166,8 @@ struct Solver {
     double *packed = nullptr;       // n_tiles * 4096
     double *rowpart = nullptr, *colpart = nullptr;  // n_tiles * 64
     double *work = nullptr;         // n_max * n_max
+    int64_t n_rows = 0;             // block rows over all components
+    int32_t *row_comp = nullptr, *row_block = nullptr;
   } sym;
   double *tmpA = nullptr, *tmpB = nullptr, *pinv = nullptr;
   std::vector<int32_t> h_cn;
