@@ -152,7 +152,10 @@ mts_status mts_read_bonds(mts_solver *s, int64_t *host_row_ptr, int32_t *host_co
 
 mts_status mts_query(mts_solver *s, mts_info *out);
 
-/* Per-kernel HIP-event timing (on the solver's stream) while enabled. */
+/* HIP-event timing on the solver's stream while enabled.  MTS_KT_PD_SUBSTEP:
+ * one event pair brackets the m back-to-back substep launches of a macro step
+ * and *launches counts the substeps; the other groups count one launch group
+ * (FE free step, multiplier solve, link re-run) per macro step. */
 mts_status mts_profile(mts_solver *s, int32_t enable);
 mts_status mts_kernel_time(mts_solver *s, int32_t kernel, int64_t *launches, double *total_ms);
 

@@ -836,10 +836,13 @@ orc_solver *orc_create(const orc_problem *p) {
     for (int64_t i = 0; i < N; i++) s->cidx[i] = -1;
     s->cel = xcalloc((size_t)s->nc, sizeof(int64_t));
     s->cw = xcalloc((size_t)(s->nc * s->nen), sizeof(double));
-    s->H = xcalloc((size_t)(s->nl * s->nl), sizeof(double));
-    s->L = xcalloc((size_t)(s->nl * s->nl), sizeof(double));
+    const int full = !p->setup_only;
+    if (full) {
+      s->H = xcalloc((size_t)(s->nl * s->nl), sizeof(double));
+      s->L = xcalloc((size_t)(s->nl * s->nl), sizeof(double));
+    }
     s->lam0 = xcalloc((size_t)s->nl, sizeof(double));
-    if (!s->cn || !s->cel || !s->cw || !s->H || !s->L || !s->lam0) { orc_destroy(s); return NULL; }
+    if (!s->cn || !s->cel || !s->cw || (full && (!s->H || !s->L)) || !s->lam0) { orc_destroy(s); return NULL; }
     int64_t q = 0;
     double h = p->fe_h;
     for (int64_t i = 0; i < N; i++) {
@@ -861,16 +864,18 @@ orc_solver *orc_create(const orc_problem *p) {
       for (int a = 0; a < s->nen; a++) s->cw[q * s->nen + a] = shape(dim, a, xi); /* G_F row: N_a(x_p) */
       q++;
     }
-    double Rr = (double)(p->m - 1) * s->delta;
-    double Rr2 = Rr * Rr;
-    for (int64_t i = 0; i < N; i++)
-      for (int64_t c = 0; c < s->nc; c++)
-        if (dist2(dim, s->x + s->cn[c] * dim, s->x + i * dim) <= Rr2) {
-          s->region[i] = 1;
-          s->nregion++;
-          break;
-        }
-    if (build_y(s)) { orc_destroy(s); return NULL; }
+    if (full) {
+      double Rr = (double)(p->m - 1) * s->delta;
+      double Rr2 = Rr * Rr;
+      for (int64_t i = 0; i < N; i++)
+        for (int64_t c = 0; c < s->nc; c++)
+          if (dist2(dim, s->x + s->cn[c] * dim, s->x + i * dim) <= Rr2) {
+            s->region[i] = 1;
+            s->nregion++;
+            break;
+          }
+      if (build_y(s)) { orc_destroy(s); return NULL; }
+    }
   }
   /* initial accelerations a0 = M^-1 (P - K u0) with u0 = 0 (reading R15) */
   for (int64_t i = 0; i < N; i++)
@@ -1041,6 +1046,10 @@ out:
 }
 
 int orc_advance(orc_solver *s, int64_t n) {
+  if (s->p.setup_only) {
+    set_err("setup-only oracle instance cannot advance");
+    return -1;
+  }
   for (int64_t k = 0; k < n; k++)
     if (macro_step(s)) return -1;
   return 0;

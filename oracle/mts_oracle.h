@@ -32,6 +32,9 @@ typedef struct {
   double cracks[8][3];        /* horizontal segments: y, x_start, x_end */
   double E, rho, G0, thickness, s_crit, l_over_delta;
   double traction, vel_bc, dt_pd;
+  int32_t setup_only;         /* 1: weights, masses, FE mesh and constraint set only
+                                 (no link region, no unit-load responses, no stepping);
+                                 for checks of large runs against the constraint set */
 } orc_problem;
 
 typedef struct {

@@ -34,6 +34,7 @@ class _Problem(C.Structure):
         ("E", C.c_double), ("rho", C.c_double), ("G0", C.c_double),
         ("thickness", C.c_double), ("s_crit", C.c_double), ("l_over_delta", C.c_double),
         ("traction", C.c_double), ("vel_bc", C.c_double), ("dt_pd", C.c_double),
+        ("setup_only", C.c_int32),
     ]
 
 
@@ -121,7 +122,7 @@ _WEIGHT = {"cubic": 0, "linear": 1, "constant": 2}
 _KERNEL = {"pmb": 0, "exp": 1}
 
 
-def make_problem(inst: dict):
+def make_problem(inst: dict, setup_only: bool = False):
     pos = np.ascontiguousarray(inst["pos"], dtype=np.float64)
     p = _Problem()
     dim = int(inst["dim"])
@@ -153,16 +154,19 @@ def make_problem(inst: dict):
     for k in ("E", "rho", "G0", "thickness", "l_over_delta", "traction", "vel_bc", "dt_pd"):
         setattr(p, k, float(inst.get(k, 0.0)))
     p.s_crit = float(inst.get("s_crit", 0.0))
+    p.setup_only = 1 if setup_only else 0
     return p, pos
 
 
 class Oracle:
     """One oracle solve of an instance dict (from mts_inputs)."""
 
-    def __init__(self, inst: dict):
+    def __init__(self, inst: dict, setup_only: bool = False):
+        """setup_only: build weights, masses, FE mesh and the constraint set but
+        not the unit-load responses (for checks of large runs); cannot advance."""
         self.lib = _L()
         self.inst = inst
-        self._p, self._pos = make_problem(inst)
+        self._p, self._pos = make_problem(inst, setup_only)
         self.h = self.lib.orc_create(C.byref(self._p))
         if not self.h:
             raise RuntimeError("oracle create failed: " + self.lib.orc_last_error().decode())

@@ -15,33 +15,40 @@ namespace {
 
 constexpr int NB = 64;
 
-// Invert the kb x kb pivot block A[k0:k0+kb, k0:k0+kb] in LDS (Gauss-Jordan).
+// Invert the kb x kb pivot block A[k0:k0+kb, k0:k0+kb] in LDS (Gauss-Jordan),
+// padded to 64 x 64 with the identity (whose inverse is itself).  Thread t
+// owns column t % 64 and rows 16 (t / 64) .. 16 (t / 64) + 15.
 __global__ __launch_bounds__(256) void k_pivot_inverse(const double *A, int64_t n, int64_t k0, int kb,
                                                       double *pinv) {
   __shared__ double M[NB][NB + 1];
   __shared__ double rowp[NB], colp[NB];
-  for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
-    int r = t / kb, c = t % kb;
-    M[r][c] = A[(k0 + r) * n + k0 + c];
+  const int c = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * 16;
+  for (int q = 0; q < 16; q++) {
+    const int r = r0 + q;
+    M[r][c] = (r < kb && c < kb) ? A[(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int p = 0; p < kb; p++) {
-    double d = 1.0 / M[p][p];
-    __syncthreads();
-    for (int t = threadIdx.x; t < kb; t += blockDim.x) {
-      rowp[t] = (t == p) ? d : M[p][t] * d;
-      colp[t] = M[t][p];
+  for (int p = 0; p < NB; p++) {
+    const double d = 1.0 / M[p][p];
+    if (threadIdx.x < NB) {
+      rowp[c] = (c == p) ? d : M[p][c] * d;
+      colp[c] = M[c][p];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
-      int r = t / kb, c = t % kb;
-      if (r == p) M[r][c] = rowp[c];
-      else if (c == p) M[r][c] = -colp[r] * d;
-      else M[r][c] = M[r][c] - colp[r] * rowp[c];
+    for (int q = 0; q < 16; q++) {
+      const int r = r0 + q;
+      double v;
+      if (r == p) v = rowp[c];
+      else if (c == p) v = -colp[r] * d;
+      else v = M[r][c] - colp[r] * rowp[c];
+      M[r][c] = v;
     }
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) pinv[t] = M[t / kb][t % kb];
+  for (int q = 0; q < 16; q++) {
+    const int r = r0 + q;
+    if (r < kb && c < kb) pinv[r * kb + c] = M[r][c];
+  }
 }
 
 // C[i][t] = A[i][k0+t] (0 on the pivot rows);  R[t][j] = (Pinv A[K,:])[t][j], R[:,K] = Pinv.
@@ -87,40 +94,51 @@ __global__ void k_write_panels(double *A, int64_t n, int64_t k0, int kb, const d
   }
 }
 
-// A -= C R over the whole matrix; 64x64 output tile per workgroup, 4x4 per thread.
+// A -= C R over the whole matrix: a rank-kb update, kb <= 64, on the FP64
+// matrix cores.  64 x 64 output tile per workgroup; wave w owns rows
+// [16 w, 16 w + 16) of the tile as four 16 x 16 MFMA tiles, accumulating onto
+// the loaded A with the negated C operand.  Operand layout of
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator register g of lane l is row 4 g + l / 16, column l % 16.
 __global__ __launch_bounds__(256) void k_rank_update(double *A, int64_t n, int kb, const double *C,
                                                      const double *R) {
   __shared__ double Cs[NB][NB + 1];
   __shared__ double Rs[NB][NB + 1];
-  int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
   for (int t = threadIdx.x; t < 64 * NB; t += 256) {
-    int r = t / NB, c = t % NB;
-    int64_t i = i0 + r;
-    Cs[r][c] = (i < n && c < kb) ? C[i * kb + c] : 0.0;
-    int rr = t / 64, cc = t % 64;
-    int64_t j = j0 + cc;
-    Rs[rr][cc] = (rr < kb && j < n) ? R[(int64_t)rr * n + j] : 0.0;
+    const int r = t / NB, c = t % NB;
+    const int64_t i = i0 + r;
+    Cs[r][c] = (i < n && c < kb) ? -C[i * kb + c] : 0.0;
+    const int64_t j = j0 + c;
+    Rs[r][c] = (r < kb && j < n) ? R[(int64_t)r * n + j] : 0.0;
   }
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+      const int64_t i = i0 + 16 * w + 4 * g + lk, j = j0 + 16 * t + lr;
+      acc[t][g] = (i < n && j < n) ? A[i * n + j] : 0.0;
+    }
   __syncthreads();
-  double acc[4][4] = {};
-  for (int s = 0; s < kb; s++) {
-    double cv[4], rv[4];
-    for (int q = 0; q < 4; q++) {
-      cv[q] = Cs[ty * 4 + q][s];
-      rv[q] = Rs[s][tx * 4 + q];
-    }
-    for (int a = 0; a < 4; a++)
-      for (int b = 0; b < 4; b++) acc[a][b] += cv[a] * rv[b];
-  }
-  for (int a = 0; a < 4; a++) {
-    int64_t i = i0 + ty * 4 + a;
-    if (i >= n) continue;
-    for (int b = 0; b < 4; b++) {
-      int64_t j = j0 + tx * 4 + b;
-      if (j < n) A[i * n + j] -= acc[a][b];
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const double a = Cs[16 * w + lr][k0 + lk];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const double b = Rs[k0 + lk][16 * t + lr];
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
     }
   }
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+      const int64_t i = i0 + 16 * w + 4 * g + lk, j = j0 + 16 * t + lr;
+      if (i < n && j < n) A[i * n + j] = acc[t][g];
+    }
 }
 
 }  // namespace

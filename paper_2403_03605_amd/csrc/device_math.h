@@ -30,6 +30,17 @@ __device__ inline double alpha_of(const Params &P, const double *xp) {
   return t * t * t;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that XCD x runs one contiguous range of tiles: the
+// neighbour gathers of a tile then hit the L2 that already holds the tiles next
+// to it.  A bijection of [0, nb) for any nb.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int nb) {
+  const int x = b % kXcds, q = b / kXcds;
+  const int base = nb / kXcds, rem = nb % kXcds;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
 // Position of slot k of local row j in a sliced-ELL slice with L lanes per row.
 __device__ inline int64_t sell_slot(int64_t slot_off, int j, int k, int L) {
   return slot_off + (int64_t)(k / L) * WAVE + j * L + (k % L);

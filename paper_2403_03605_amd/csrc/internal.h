@@ -194,13 +194,17 @@ struct Solver {
   // profiling
   bool profiling = false;
   hipEvent_t ev_start[MTS_KT_COUNT]{}, ev_stop[MTS_KT_COUNT]{};
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[MTS_KT_COUNT];
+  struct EvPair {
+    hipEvent_t e0, e1;
+    int launches;  // back-to-back launches between the two events
+  };
+  std::vector<EvPair> ev_pending[MTS_KT_COUNT];
   int64_t kt_count[MTS_KT_COUNT]{};
   double kt_ms[MTS_KT_COUNT]{};
   std::vector<hipEvent_t> ev_pool;
 
   void prof_begin(int k, hipEvent_t *e0);
-  void prof_end(int k, hipEvent_t e0);
+  void prof_end(int k, hipEvent_t e0, int launches = 1);
   void prof_collect();
 };
 

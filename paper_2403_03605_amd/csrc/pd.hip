@@ -79,21 +79,24 @@ struct SubstepArgs {
   int breaking;
 };
 
+struct SubstepEntry {
+  SubstepArgs A;
+  Params P;
+  int32_t first_block;
+};
+
 // One wavefront = one slice of 64/L consecutive nodes; the L lanes of a node
 // take every L-th slot of its family, their partial sums are combined by a
 // fixed butterfly (deterministic, no atomics).  Bond states of one iteration of
 // the slice form one 64-bit word owned by the wavefront.
 template <int DIM, int L, bool MX>
-__global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) {
+__device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
   // formed in FP64; the accumulated value is the acceleration (coefficient
   // pre-divided by the node mass).  Integration stays FP64.
   using R = typename std::conditional<MX, float, double>::type;
   constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
-  // wave-uniform slice index: offsets and state words come through scalar loads
-  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / WAVE) + (threadIdx.x >> 6)));
-  if (slice >= A.n_slices) return;  // uniform per wavefront
   const int64_t N = A.N;
   const int jl = lane / L, l = lane % L;
   const int64_t i = slice * S + jl;
@@ -245,6 +248,30 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) 
   }
 }
 
+// One solver: slice = renumbered workgroup * 4 + wavefront (wave-uniform, so
+// offsets and state words come through scalar loads).
+template <int DIM, int L, bool MX>
+__global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) {
+  const int64_t slice = __builtin_amdgcn_readfirstlane(
+      (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+  if (slice >= A.n_slices) return;  // uniform per wavefront
+  substep_body<DIM, L, MX>(A, P, slice);
+}
+
+// Several solvers in one launch: workgroup b (after renumbering) belongs to
+// solver blk_req[b], whose slices start at its entry's first_block.
+template <int DIM, int L, bool MX>
+__global__ __launch_bounds__(kBlock) void k_pd_substep_batch(const SubstepEntry *tab, const int32_t *blk_req) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int r = __builtin_amdgcn_readfirstlane(blk_req[b]);
+  const SubstepArgs A = tab[r].A;
+  const Params P = tab[r].P;
+  const int64_t slice = __builtin_amdgcn_readfirstlane(
+      (int)((b - tab[r].first_block) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+  if (slice >= A.n_slices) return;
+  substep_body<DIM, L, MX>(A, P, slice);
+}
+
 // Link problem (Eq. 48b / eq. unit): linear, no breaking, bond states of the
 // last rebuild.  NRHS right-hand sides share one pass over the bond data.
 //  kColor = false: one RHS, load (j/m) lambda_m at every constraint node.
@@ -270,12 +297,16 @@ struct LinkArgs {
   double lfac;
 };
 
+struct LinkEntry {
+  LinkArgs A;
+  Params P;
+  int32_t first_block;
+};
+
 template <int DIM, int NRHS, bool kColor, int L>
-__global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
+__device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, const int64_t slice) {
   constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / WAVE) + (threadIdx.x >> 6)));
-  if (slice >= A.n_slices) return;
   if (A.slice_layer[slice] > A.jmax) return;  // uniform per wavefront
   const int jl = lane / L, l = lane % L;
   const int64_t r = slice * S + jl;
@@ -351,6 +382,26 @@ __global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
       A.v[tix] = vn;
       A.u_out[tix] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
     }
+}
+
+template <int DIM, int NRHS, bool kColor, int L>
+__global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
+  const int64_t slice = __builtin_amdgcn_readfirstlane(
+      (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+  if (slice >= A.n_slices) return;
+  link_body<DIM, NRHS, kColor, L>(A, P, slice);
+}
+
+template <int DIM, int L>
+__global__ __launch_bounds__(kBlock) void k_link_substep_batch(const LinkEntry *tab, const int32_t *blk_req) {
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int r = __builtin_amdgcn_readfirstlane(blk_req[b]);
+  const LinkArgs A = tab[r].A;
+  const Params P = tab[r].P;
+  const int64_t slice = __builtin_amdgcn_readfirstlane(
+      (int)((b - tab[r].first_block) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+  if (slice >= A.n_slices) return;
+  link_body<DIM, 1, false, L>(A, P, slice);
 }
 
 __global__ void k_zero_region(int64_t n_rows, const int32_t *rows, int64_t N, int dim, int nrhs, double *u0,
@@ -442,8 +493,6 @@ void pd_substep(Solver &s, int j) {
   A.damage = (j == s.m) ? s.damage : nullptr;
   A.breaking = s.breaking ? 1 : 0;
   unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
-  hipEvent_t e0 = nullptr;
-  s.prof_begin(MTS_KT_PD_SUBSTEP, &e0);
   const int L = s.sell.L;
 #define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
 #define MTS_SUBL(D, MX)                                                                        \
@@ -460,7 +509,6 @@ void pd_substep(Solver &s, int j) {
 #undef MTS_SUBL
 #undef MTS_SUB
   MTS_LAUNCH_CHECK();
-  s.prof_end(MTS_KT_PD_SUBSTEP, e0);
   s.cur ^= 1;
   s.pd_steps++;
 }

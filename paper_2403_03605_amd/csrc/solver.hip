@@ -58,7 +58,7 @@ void Solver::prof_begin(int k, hipEvent_t *e0) {
   (void)k;
 }
 
-void Solver::prof_end(int k, hipEvent_t e0) {
+void Solver::prof_end(int k, hipEvent_t e0, int launches) {
   if (!profiling || !e0) return;
   hipEvent_t e;
   if (!ev_pool.empty()) {
@@ -68,19 +68,19 @@ void Solver::prof_end(int k, hipEvent_t e0) {
     MTS_HIP(hipEventCreate(&e));
   }
   MTS_HIP(hipEventRecord(e, stream));
-  ev_pending[k].push_back({e0, e});
+  ev_pending[k].push_back({e0, e, launches});
 }
 
 void Solver::prof_collect() {
   for (int k = 0; k < MTS_KT_COUNT; k++) {
     for (auto &pr : ev_pending[k]) {
-      MTS_HIP(hipEventSynchronize(pr.second));
+      MTS_HIP(hipEventSynchronize(pr.e1));
       float ms = 0.f;
-      MTS_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      MTS_HIP(hipEventElapsedTime(&ms, pr.e0, pr.e1));
       kt_ms[k] += ms;
-      kt_count[k]++;
-      ev_pool.push_back(pr.first);
-      ev_pool.push_back(pr.second);
+      kt_count[k] += pr.launches;
+      ev_pool.push_back(pr.e0);
+      ev_pool.push_back(pr.e1);
     }
     ev_pending[k].clear();
   }
@@ -309,7 +309,13 @@ void advance_impl(Solver &s, int64_t n) {
       fe_free_step(s);
       s.prof_end(MTS_KT_FE, e0);
     }
-    for (int j = 1; j <= s.m; j++) pd_substep(s, j);
+    {
+      // the m substep launches run back to back; one event pair brackets them
+      hipEvent_t e0 = nullptr;
+      s.prof_begin(MTS_KT_PD_SUBSTEP, &e0);
+      for (int j = 1; j <= s.m; j++) pd_substep(s, j);
+      s.prof_end(MTS_KT_PD_SUBSTEP, e0, s.m);
+    }
     int slot = -1;
     if (track) {
       slot = (int)(s.macro_steps & 1);
@@ -638,8 +644,8 @@ void mts_destroy(mts_solver *h) {
   (void)hipStreamSynchronize(s.stream);
   for (int k = 0; k < MTS_KT_COUNT; k++)
     for (auto &pr : s.ev_pending[k]) {
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+      (void)hipEventDestroy(pr.e0);
+      (void)hipEventDestroy(pr.e1);
     }
   for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : s.flag_event)
