@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed macro steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default=None,
+                    help="override the workload's precision (same seeded instance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
@@ -127,7 +129,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    inst = mi.config(args.config)
+    inst = mi.config(args.config) if args.precision is None else mi.config(args.config, precision=args.precision)
+    if args.precision is not None:
+        inst["name"] += f" ({args.precision})"
     K = args.steps if args.steps is not None else inst["n_macro"]
     W = args.warmup
     stream = torch.cuda.Stream()

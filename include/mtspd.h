@@ -165,6 +165,70 @@ void mts_destroy(mts_solver *s);
 const char *mts_status_str(mts_status st);
 const char *mts_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Serving pool: independent solves of one dimension and precision resident in
+ * device memory together, admitted against a byte budget and advanced together
+ * (continuous batching).  One pool step advances every running request by one
+ * macro step of Algorithm 1; the PD substeps of all requests run as one batched
+ * launch per substep index, and the per-step work is replayed from HIP graphs
+ * while the set of running requests does not change.  A request's results equal
+ * those of the same request running alone in a pool (same lane count, same
+ * arithmetic order).
+ * Threads: mts_pool_submit may run on one other thread concurrently with the
+ * other pool calls (it builds the request on a stream of its own); all other
+ * pool calls must come from one thread.
+ * ------------------------------------------------------------------------- */
+enum { MTS_REQ_ACTIVE = 1, MTS_REQ_DONE = 2 };
+
+typedef struct mts_pool mts_pool;
+
+typedef struct mts_pool_info {
+  int64_t budget_bytes, used_bytes;  /* device bytes charged to running and unreleased requests */
+  int64_t ticks, graph_captures, graph_replays;
+  int32_t n_running, n_ready, max_slots, lanes;
+} mts_pool_info;
+
+/* budget_bytes: device bytes the pool may hold (requests are charged their
+ * mts_plan estimate while being built, then what they actually allocated);
+ * max_slots: most requests admitted at once; dim, precision: of every request;
+ * use_graphs: replay pool steps from HIP graphs; hip_stream: the stream pool
+ * steps run on (caller-owned; NULL: the pool creates a non-blocking stream of
+ * its own -- graphs cannot be captured on the null stream).
+ * Errors: MTS_EINVAL, MTS_EDEVICE. */
+mts_status mts_pool_create(int64_t budget_bytes, int32_t max_slots, int32_t dim, int32_t precision,
+                           int32_t use_graphs, void *hip_stream, mts_pool **out);
+
+/* Build a request (synchronous; may run concurrently with mts_pool_step on one
+ * other thread) that will run n_macro macro steps; it joins the running set at
+ * the next pool step.  *id identifies it.  Errors: MTS_EAGAIN (no slot or not
+ * enough budget now: submit again after a release), MTS_ETOOBIG (the estimate
+ * exceeds the whole budget), MTS_EINVAL (bad description, or dim/precision
+ * differ from the pool's), MTS_ENOMEM, MTS_EDEVICE. */
+mts_status mts_pool_submit(mts_pool *pool, const mts_problem *p, int64_t n_macro, uint64_t *id);
+
+/* Enqueue one pool step.  *n_active: requests still running afterwards;
+ * host_done_ids[0 .. min(*n_done, cap)): requests whose last step this was
+ * (their results can be read once the stream reaches that point; the read
+ * calls wait for it). */
+mts_status mts_pool_step(mts_pool *pool, int32_t *n_active, uint64_t *host_done_ids, int32_t cap,
+                         int32_t *n_done);
+
+/* State (MTS_REQ_ACTIVE or MTS_REQ_DONE), macro steps enqueued and, when info
+ * is not NULL, the request's mts_query record.  Any output may be NULL. */
+mts_status mts_pool_poll(mts_pool *pool, uint64_t id, int32_t *state, int64_t *macro_done, mts_info *info);
+
+/* mts_read for a finished request (waits for its last step only).
+ * MTS_ESTATE if it has not finished. */
+mts_status mts_pool_read(mts_pool *pool, uint64_t id, int32_t what, double *host_out, int64_t cap, int64_t *n);
+
+/* Free a finished request's device memory and return its budget. */
+mts_status mts_pool_release(mts_pool *pool, uint64_t id);
+
+mts_status mts_pool_query(mts_pool *pool, mts_pool_info *out);
+
+/* Waits for the pool stream, frees every request.  Accepts NULL. */
+void mts_pool_destroy(mts_pool *pool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -216,3 +216,30 @@ def serving_stream(n_requests: int = 256, rate: float = 20.0, seed: int = SERVIN
         out.append(dict(arrival=t, nx=nx, notch=a, crack_y=yc, traction=T, m=m, seed=pseed,
                         t_end=t_end))
     return out
+
+
+def serving_instance(req: Dict, precision: str = "mixed") -> Dict:
+    """The plate solve of one serving request.
+
+    Notch length and height are snapped to the FE node lines (spacing 4 dx) and
+    clamped so that the PD strip [a - 10 mm, a + 40 mm] x [y_c - 10 mm, y_c + 10 mm]
+    stays at least one element inside the plate.  The PD step follows the
+    400 x 160 workload (6e-9 s at dx = 0.125 mm, m = 10) scaled with dx and 1/m,
+    which keeps the same fraction of the PD and FE stability bounds; the request
+    runs ceil(t_end / (m dt)) macro steps.  Returns the instance with
+    "n_macro" and "bond_updates_per_macro" left to the caller (the latter needs
+    the bond count)."""
+    nx, m = int(req["nx"]), int(req["m"])
+    dx = 0.05 / nx
+    fe_h = 4.0 * dx
+    a = round(req["notch"] / fe_h) * fe_h
+    a = min(max(a, 0.01 + fe_h), 0.06 - fe_h)
+    yc = round(req["crack_y"] / fe_h) * fe_h
+    yc = min(max(yc, 0.01 + fe_h), 0.03 - fe_h)
+    dt = 6.0e-9 * (dx / 0.125e-3) * (10.0 / m)
+    n_macro = int(math.ceil(req["t_end"] / (m * dt) - 1e-9))
+    inst = plate2d(nx, m, n_macro * m, dt, perturb=1e-6, seed=int(req["seed"]) & 0x7FFFFFFFFFFFFFFF,
+                   precision=precision, traction=float(req["traction"]), notch=a, crack_y=yc,
+                   name=f"serve {nx}x{2 * nx // 5} m={m}")
+    inst["n_macro"] = n_macro
+    return inst

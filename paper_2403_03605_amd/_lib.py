@@ -16,6 +16,7 @@ FP64, MIXED = 0, 1
 PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, DAMAGE, LAMBDA, PD_ALPHA, PD_MASS, FE_MASS, FE_X, \
     CONSTRAINT_NODES, H = range(14)
 KT_PD_SUBSTEP, KT_LINK, KT_FE, KT_LAMBDA = range(4)
+REQ_ACTIVE, REQ_DONE = 1, 2
 WEIGHT = {"cubic": 0, "linear": 1, "constant": 2}
 KERNEL = {"pmb": 0, "exp": 1}
 
@@ -57,8 +58,16 @@ class PlanInfo(C.Structure):
                 ("n_constraints_estimate", C.c_int64), ("device_bytes_estimate", C.c_int64)]
 
 
+class PoolInfo(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("used_bytes", C.c_int64), ("ticks", C.c_int64),
+                ("graph_captures", C.c_int64), ("graph_replays", C.c_int64),
+                ("n_running", C.c_int32), ("n_ready", C.c_int32), ("max_slots", C.c_int32), ("lanes", C.c_int32)]
+
+
 EXPORTS = ["mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_write", "mts_read_bonds",
-           "mts_query", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error"]
+           "mts_query", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
+           "mts_pool_create", "mts_pool_submit", "mts_pool_step", "mts_pool_poll", "mts_pool_read",
+           "mts_pool_release", "mts_pool_query", "mts_pool_destroy"]
 
 _lib = None
 
@@ -87,8 +96,19 @@ def load():
     lib.mts_status_str.restype = C.c_char_p
     lib.mts_status_str.argtypes = [C.c_int]
     lib.mts_last_error.restype = C.c_char_p
+    lib.mts_pool_create.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                    P(C.c_void_p)]
+    lib.mts_pool_submit.argtypes = [C.c_void_p, P(Problem), C.c_int64, P(C.c_uint64)]
+    lib.mts_pool_step.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_uint64), C.c_int32, P(C.c_int32)]
+    lib.mts_pool_poll.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int64), P(Info)]
+    lib.mts_pool_read.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, P(C.c_double), C.c_int64, P(C.c_int64)]
+    lib.mts_pool_release.argtypes = [C.c_void_p, C.c_uint64]
+    lib.mts_pool_query.argtypes = [C.c_void_p, P(PoolInfo)]
+    lib.mts_pool_destroy.argtypes = [C.c_void_p]
+    lib.mts_pool_destroy.restype = None
     for f in ("mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_write", "mts_read_bonds",
-              "mts_query", "mts_profile", "mts_kernel_time"):
+              "mts_query", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
+              "mts_pool_step", "mts_pool_poll", "mts_pool_read", "mts_pool_release", "mts_pool_query"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -226,3 +246,70 @@ class Solver:
         ms = C.c_double()
         _check(self.lib.mts_kernel_time(self.h, kernel, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+class Pool:
+    """Serving pool (mts_pool_*): requests of one dimension and precision,
+    admitted against a device-memory budget and advanced together."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, dim: int = 2, precision: str = "mixed",
+                 use_graphs: bool = True, stream=None):
+        self.lib = load()
+        if stream is None:
+            stream = 0  # the pool creates a stream of its own
+        h = C.c_void_p()
+        _check(self.lib.mts_pool_create(int(budget_bytes), int(max_slots), int(dim),
+                                        MIXED if precision == "mixed" else FP64, 1 if use_graphs else 0,
+                                        C.c_void_p(int(stream)), C.byref(h)))
+        self.h = h
+        self.dim = dim
+        self._ids = (C.c_uint64 * 1024)()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mts_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, inst: dict, n_macro: int):
+        """Build the request; returns its id, or None when the pool is full now
+        (EAGAIN).  Raises MtsError otherwise."""
+        p, _pos = make_problem(inst)
+        rid = C.c_uint64()
+        st = self.lib.mts_pool_submit(self.h, C.byref(p), int(n_macro), C.byref(rid))
+        if st == EAGAIN:
+            return None
+        _check(st)
+        return rid.value
+
+    def step(self):
+        """One pool step; returns (running after it, ids of requests that finished)."""
+        na, nd = C.c_int32(), C.c_int32()
+        _check(self.lib.mts_pool_step(self.h, C.byref(na), self._ids, len(self._ids), C.byref(nd)))
+        return na.value, [self._ids[i] for i in range(min(nd.value, len(self._ids)))]
+
+    def poll(self, rid: int):
+        """(state, macro steps enqueued, the request's query record)"""
+        st, done, info = C.c_int32(), C.c_int64(), Info()
+        _check(self.lib.mts_pool_poll(self.h, C.c_uint64(rid), C.byref(st), C.byref(done), C.byref(info)))
+        return st.value, done.value, {k: getattr(info, k) for k, _ in Info._fields_}
+
+    def read(self, rid: int, what: int, size: int) -> np.ndarray:
+        out = np.zeros(max(size, 1), dtype=np.float64)
+        got = C.c_int64()
+        _check(self.lib.mts_pool_read(self.h, C.c_uint64(rid), what, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                      out.size, C.byref(got)))
+        out = out[:got.value]
+        if what in (PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, FE_X, LAMBDA):
+            out = out.reshape(-1, self.dim)
+        return out
+
+    def release(self, rid: int):
+        _check(self.lib.mts_pool_release(self.h, C.c_uint64(rid)))
+
+    def query(self) -> dict:
+        o = PoolInfo()
+        _check(self.lib.mts_pool_query(self.h, C.byref(o)))
+        return {k: getattr(o, k) for k, _ in PoolInfo._fields_}

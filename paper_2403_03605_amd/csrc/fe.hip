@@ -18,8 +18,6 @@ struct FeTables {
   double detJ;
 };
 
-__constant__ FeTables c_fe;
-
 __device__ inline double nat(int dim, int a, int c) {
   // local node a natural coordinate along axis c: Q4 (-1,-1),(1,-1),(1,1),(-1,1); Hex8 adds z.
   const int q4[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
@@ -123,7 +121,7 @@ __global__ void k_fe_gp_alpha(Params P, MeshGeo G, int64_t ne, int ngp, double *
 // (element, local node) list is in ascending element order.
 __global__ void k_fe_node_setup(Params P, MeshGeo G, int64_t nfe, int nen, int ngp, const int32_t *n2e_ptr,
                                 const int32_t *n2e, const double *gpa, const uint8_t *eact, double T,
-                                double dom_hi_y, double thick, double *mF, double *PF, uint8_t *nact) {
+                                double dom_hi_y, double thick, double *mF, double *PF, uint8_t *nact, const FeTables *tab) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nfe) return;
   int dim = P.dim;
@@ -135,7 +133,7 @@ __global__ void k_fe_node_setup(Params P, MeshGeo G, int64_t nfe, int nen, int n
     int a = n2e[t] % nen;
     if (!eact[e]) continue;
     act = 1;
-    for (int g = 0; g < ngp; g++) m += gpa[e * ngp + g] * P.rho * c_fe.N[g][a] * c_fe.detJ * thick;
+    for (int g = 0; g < ngp; g++) m += gpa[e * ngp + g] * P.rho * tab->N[g][a] * tab->detJ * thick;
   }
   if (T != 0.0) {
     for (int t = n2e_ptr[n]; t < n2e_ptr[n + 1]; t++) {
@@ -194,7 +192,7 @@ __global__ void k_fe_predict(int64_t nfe, int dim, const uint8_t *nact, const ui
 // Element force f_e = sum_gp alpha B^T D B u_e detJ t (engineering shear strains).
 template <int DIM>
 __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *eact, const double *gpa,
-                                const double *u, double thick, double *fe_buf) {
+                                const double *u, double thick, const FeTables *__restrict__ tab, double *fe_buf) {
   constexpr int NEN = DIM == 2 ? 4 : 8;
   constexpr int NSTR = DIM == 2 ? 3 : 6;
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +207,7 @@ __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *
     double eps[NSTR], sig[NSTR];
     for (int r = 0; r < NSTR; r++) eps[r] = 0.0;
     for (int a = 0; a < NEN; a++) {
-      const double *dN = c_fe.dN[g][a];
+      const double *dN = tab->dN[g][a];
       const double *uu = ue + a * DIM;
       if (DIM == 2) {
         eps[0] += dN[0] * uu[0];
@@ -226,11 +224,11 @@ __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *
     }
     for (int r = 0; r < NSTR; r++) {
       sig[r] = 0.0;
-      for (int c = 0; c < NSTR; c++) sig[r] += c_fe.D[r][c] * eps[c];
+      for (int c = 0; c < NSTR; c++) sig[r] += tab->D[r][c] * eps[c];
     }
-    double scale = al * c_fe.detJ * thick;
+    double scale = al * tab->detJ * thick;
     for (int a = 0; a < NEN; a++) {
-      const double *dN = c_fe.dN[g][a];
+      const double *dN = tab->dN[g][a];
       double *f = fe + a * DIM;
       if (DIM == 2) {
         f[0] += scale * (dN[0] * sig[0] + dN[1] * sig[2]);
@@ -441,17 +439,16 @@ void fe_setup(Solver &s) {
   FeTables *tab = ar.alloc<FeTables>(1);
   k_fe_tables<<<1, 1, 0, st>>>(dim, h, p.E, dim == 2 ? 1.0 / 3.0 : 0.25, tab);
   MTS_LAUNCH_CHECK();
-  MTS_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_fe), tab, sizeof(FeTables), 0, hipMemcpyDeviceToDevice, st));
+  s.fe_tab = tab;  // per solver: solvers of different mesh sizes coexist
   MeshGeo G = mesh_geo(s);
   k_fe_gp_alpha<<<nb(s.ne), 256, 0, st>>>(s.prm, G, s.ne, s.ngp, s.gpa, s.eact);
   MTS_LAUNCH_CHECK();
   k_fe_node_setup<<<nb(nfe), 256, 0, st>>>(s.prm, G, nfe, nen, s.ngp, s.n2e_ptr, s.n2e, s.gpa, s.eact, p.traction,
-                                           p.dom_hi[1], p.thickness, s.mF, s.PF, s.nact);
+                                           p.dom_hi[1], p.thickness, s.mF, s.PF, s.nact, tab);
   MTS_LAUNCH_CHECK();
   k_fe_init<<<nb(nfe), 256, 0, st>>>(nfe, dim, s.nact, s.bc, s.PF, s.mF, p.vel_bc, s.vF, s.aF);
   MTS_LAUNCH_CHECK();
   MTS_HIP(hipStreamSynchronize(st));
-  ar.release(tab);
 }
 
 void fe_free_step(Solver &s) {
@@ -461,9 +458,11 @@ void fe_free_step(Solver &s) {
                                         s.aF, s.ut);
   MTS_LAUNCH_CHECK();
   if (s.dim == 2)
-    k_fe_elem_force<2><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness, s.fe_buf);
+    k_fe_elem_force<2><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness,
+                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
   else
-    k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness, s.fe_buf);
+    k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness,
+                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
   MTS_LAUNCH_CHECK();
   k_fe_gather_free<<<nb(nfe), 256, 0, st>>>(nfe, s.dim, s.nen, s.n2e_ptr, s.n2e, s.eact, s.nact, s.bc, s.fe_buf,
                                             s.PF, s.mF, s.vF, s.aF, s.prm.hdtF, s.p.vel_bc, s.at, s.vt, s.f2c_ptr,

@@ -139,6 +139,7 @@ struct Solver {
   double *xF = nullptr, *mF = nullptr, *PF = nullptr;
   double *uF = nullptr, *vF = nullptr, *aF = nullptr;
   double *ut = nullptr, *vt = nullptr, *at = nullptr, *fe_buf = nullptr;
+  void *fe_tab = nullptr;        // element tables (shape functions, derivatives, Hooke), device
   std::vector<int32_t> h_conn;
   std::vector<uint8_t> h_bc;
 
@@ -189,6 +190,7 @@ struct Solver {
   int pending_slot = 0;
 
   bool verbose = false;
+  int force_lanes = 0;             // lanes per row of the full-lattice bond layout (0: pick_lanes)
   double t_create0 = 0.0;
 
   // profiling
@@ -219,6 +221,12 @@ void pd_setup(Solver &s);
 void pd_predict_all(Solver &s);
 void pd_substep(Solver &s, int j);
 void pd_damage(Solver &s);
+// batched substeps over several solvers of one form and lane count (pd.hip)
+size_t substep_entry_size();
+int64_t substep_blocks(const Solver &s);
+void substep_entry_fill(Solver &s, int j, int cur, int32_t first_block, void *dst);
+void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const int32_t *dev_blk_req,
+                          int64_t nblocks, hipStream_t st);
 // FE kernels (fe.hip)
 void fe_setup(Solver &s);
 void fe_free_step(Solver &s);
@@ -232,6 +240,14 @@ void dense_spd_inverse(Solver &s, double *A, int64_t n);
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
 void sym_blocks_apply(Solver &s, const double *r, double *y);
+// solver construction and helpers shared with the serving pool (solver.hip)
+void create_impl(const mts_problem *pin, void *stream, Solver *s);
+mts_status fail_from_exception();
+void set_error(const char *fmt, ...);
+void check_finite(Solver &s);
+void resolve_pending(Solver &s);
+mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n);
+void query_impl(Solver &s, mts_info *o);
 // progress log on stderr when MTS_VERBOSE is set
 void vlog(const Solver &s, const char *fmt, ...);
 // scans (neighbors.hip)

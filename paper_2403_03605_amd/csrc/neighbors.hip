@@ -235,7 +235,7 @@ void build_neighbors(Solver &s) {
 
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
-  build_sell(s, s.sell, rows, nullptr, pick_lanes(N));
+  build_sell(s, s.sell, rows, nullptr, s.force_lanes ? s.force_lanes : pick_lanes(N));
 }
 
 }  // namespace mts

@@ -6,6 +6,7 @@
 // Equations: Eq. 2 (force), Eq. 3 (stretch), Eq. 4 (bond state), Eq. 5 (damage),
 // Eq. 38 with gamma = 1/2, beta = 0 (velocity Verlet), Eq. 48a/48b (free and
 // link problems), Eq. 17-18 and Eq. 34 (Arlequin weights of stiffness and mass).
+#include <cstring>
 #include <type_traits>
 
 #include "device_math.h"
@@ -126,21 +127,26 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   // results is used (state words, indices and coefficients first, then the
   // neighbour gathers), so a wavefront waits on two memory round trips per
   // chunk instead of three per slot.
+  // Software pipeline over chunks of TM iterations: the state words, indices
+  // and coefficients of chunk t0 + TM are requested right after the neighbour
+  // gathers of chunk t0, so the slot stream stays in flight while chunk t0 is
+  // gathered and evaluated.  The slot arrays carry kSpareIters (>= TM) spare
+  // iterations past the last slice, so every such load is in bounds; slots past
+  // T are masked out.
   constexpr int TM = 4;
-  for (int t0 = 0; t0 < T; t0 += TM) {
-    uint64_t word[TM];
-    int64_t c[TM];
-    R cf[TM];
-    // The slot arrays carry TM spare iterations past the last slice, so these
-    // loads are always in bounds; slots past T are masked out afterwards.
+  static_assert(kSpareIters >= TM, "spare iterations must cover one chunk");
+  uint64_t word[TM];
+  int64_t c[TM];
+  R cf[TM];
 #pragma unroll
-    for (int q = 0; q < TM; q++) {
-      const int64_t pos = so + (int64_t)(t0 + q) * WAVE + lane;
-      word[q] = A.mask[wo + t0 + q];
-      c[q] = A.col[pos];
-      if constexpr (MX) cf[q] = A.coef32[pos];
-      else cf[q] = A.coef[pos];
-    }
+  for (int q = 0; q < TM; q++) {
+    const int64_t pos = so + (int64_t)q * WAVE + lane;
+    word[q] = A.mask[wo + q];
+    c[q] = A.col[pos];
+    if constexpr (MX) cf[q] = A.coef32[pos];
+    else cf[q] = A.coef[pos];
+  }
+  for (int t0 = 0; t0 < T; t0 += TM) {
 #pragma unroll
     for (int q = 0; q < TM; q++)
       if (t0 + q >= T) word[q] = 0ull;
@@ -151,6 +157,26 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
         xk[q][d] = A.x[d * N + c[q]];
         uk[q][d] = A.u_in[d * N + c[q]];
       }
+    uint64_t wnext[TM];
+    int64_t cnext[TM];
+    R fnext[TM];
+    if (t0 + TM < T) {  // wave-uniform
+#pragma unroll
+      for (int q = 0; q < TM; q++) {
+        const int64_t pos = so + (int64_t)(t0 + TM + q) * WAVE + lane;
+        wnext[q] = A.mask[wo + t0 + TM + q];
+        cnext[q] = A.col[pos];
+        if constexpr (MX) fnext[q] = A.coef32[pos];
+        else fnext[q] = A.coef[pos];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < TM; q++) {
+        wnext[q] = 0ull;
+        cnext[q] = 0;
+        fnext[q] = R(0);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < TM; q++) {
       bool bit = (word[q] >> lane) & 1ull;
@@ -214,6 +240,12 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
         const uint64_t nw = __ballot(bit);
         if (nw != word[q] && lane == 0) A.mask[wo + t0 + q] = nw;
       }
+    }
+#pragma unroll
+    for (int q = 0; q < TM; q++) {
+      word[q] = wnext[q];
+      c[q] = cnext[q];
+      cf[q] = fnext[q];
     }
   }
   for (int off = L / 2; off >= 1; off >>= 1) {
@@ -463,9 +495,9 @@ void pd_predict_all(Solver &s) {
   MTS_LAUNCH_CHECK();
 }
 
-// Substep j (1..m) of the free problem.  Reads u[cur^1] (predicted u_j), writes
-// the predicted u_{j+1} into u[cur]; afterwards cur flips.
-void pd_substep(Solver &s, int j) {
+// Arguments of substep j (1..m) with displacement buffers u[cur ^ 1] (predicted
+// u_j, read) and u[cur] (predicted u_{j+1}, written).
+static SubstepArgs substep_args(Solver &s, int j, int cur) {
   SubstepArgs A{};
   A.x = s.x;
   A.N = s.N;
@@ -480,8 +512,8 @@ void pd_substep(Solver &s, int j) {
   A.mask = s.sell.mask;
   A.mass = s.mass;
   A.P = s.P;
-  A.u_in = s.u[s.cur ^ 1];
-  A.u_out = s.u[s.cur];
+  A.u_in = s.u[cur ^ 1];
+  A.u_out = s.u[cur];
   A.v = s.v;
   A.a = s.a;
   A.cidx = s.nc ? s.cidx : nullptr;
@@ -492,25 +524,56 @@ void pd_substep(Solver &s, int j) {
   A.rp = s.rp;
   A.damage = (j == s.m) ? s.damage : nullptr;
   A.breaking = s.breaking ? 1 : 0;
-  unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
+  return A;
+}
+
+#define MTS_BY_LANES(L, MACRO, D, MX)  \
+  if (L == 1) MACRO(D, 1, MX);         \
+  else if (L == 2) MACRO(D, 2, MX);    \
+  else if (L == 4) MACRO(D, 4, MX);    \
+  else MACRO(D, 8, MX)
+#define MTS_BY_FORM(dim, mx, L, MACRO)                                   \
+  if (dim == 2) {                                                        \
+    if (mx) { MTS_BY_LANES(L, MACRO, 2, true); } else { MTS_BY_LANES(L, MACRO, 2, false); } \
+  } else {                                                               \
+    if (mx) { MTS_BY_LANES(L, MACRO, 3, true); } else { MTS_BY_LANES(L, MACRO, 3, false); } \
+  }
+
+// Substep j (1..m) of the free problem.  Reads u[cur^1] (predicted u_j), writes
+// the predicted u_{j+1} into u[cur]; afterwards cur flips.
+void pd_substep(Solver &s, int j) {
+  const SubstepArgs A = substep_args(s, j, s.cur);
+  const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   const int L = s.sell.L;
 #define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
-#define MTS_SUBL(D, MX)                                                                        \
-  if (L == 1) MTS_SUB(D, 1, MX);                                                              \
-  else if (L == 2) MTS_SUB(D, 2, MX);                                                         \
-  else if (L == 4) MTS_SUB(D, 4, MX);                                                         \
-  else MTS_SUB(D, 8, MX)
-  const bool mx = s.precision == MTS_MIXED;
-  if (s.dim == 2) {
-    if (mx) { MTS_SUBL(2, true); } else { MTS_SUBL(2, false); }
-  } else {
-    if (mx) { MTS_SUBL(3, true); } else { MTS_SUBL(3, false); }
-  }
-#undef MTS_SUBL
+  MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB);
 #undef MTS_SUB
   MTS_LAUNCH_CHECK();
   s.cur ^= 1;
   s.pd_steps++;
+}
+
+// ---- batched substeps over several solvers (serving pool) ----
+size_t substep_entry_size() { return sizeof(SubstepEntry); }
+
+int64_t substep_blocks(const Solver &s) { return (s.sell.n_slices * WAVE + kBlock - 1) / kBlock; }
+
+void substep_entry_fill(Solver &s, int j, int cur, int32_t first_block, void *dst) {
+  SubstepEntry e{};
+  e.A = substep_args(s, j, cur);
+  e.P = s.prm;
+  e.first_block = first_block;
+  std::memcpy(dst, &e, sizeof e);
+}
+
+void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const int32_t *dev_blk_req,
+                          int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return;
+  const SubstepEntry *tab = static_cast<const SubstepEntry *>(dev_tab);
+#define MTS_SUBB(D, LL, MX) k_pd_substep_batch<D, LL, MX><<<(unsigned)nblocks, kBlock, 0, st>>>(tab, dev_blk_req)
+  MTS_BY_FORM(dim, mixed, L, MTS_SUBB);
+#undef MTS_SUBB
+  MTS_LAUNCH_CHECK();
 }
 
 // ---- link runs (used by coupling.hip) ----

@@ -179,9 +179,23 @@ void derive_params(Solver &s) {
   P.rho = p.rho;
 }
 
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
 void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   validate(pin);
   s->verbose = std::getenv("MTS_VERBOSE") != nullptr;
+  const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
+  if (e) {  // tuning: lanes per row of the bond pass
+    const int L = std::atoi(e);
+    if (L == 1 || L == 2 || L == 4 || L == 8) s->force_lanes = L;
+  }
   s->t_create0 = now_s();
   s->p = *pin;
   const int dim = s->dim = pin->dim;
@@ -348,7 +362,6 @@ int64_t qsize(Solver &s, int what) {
   }
 }
 
-}  // namespace
 }  // namespace mts
 
 using namespace mts;
@@ -478,8 +491,14 @@ mts_status mts_sync(mts_solver *h) {
 
 mts_status mts_read(mts_solver *h, int32_t what, double *out, int64_t cap, int64_t *n) {
   if (!h || !out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  return read_impl(h->s, what, out, cap, n);
+}
+
+}  // extern "C"
+
+namespace mts {
+mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n) {
   try {
-    Solver &s = h->s;
     int64_t sz = qsize(s, what);
     if (sz < 0) throw ArgError{"quantity not available"};
     if (cap < sz) throw ArgError{"output capacity too small"};
@@ -520,6 +539,9 @@ mts_status mts_read(mts_solver *h, int32_t what, double *out, int64_t cap, int64
     return fail_from_exception();
   }
 }
+}  // namespace mts
+
+extern "C" {
 
 mts_status mts_write(mts_solver *h, int32_t what, const double *in, int64_t n) {
   if (!h || !in) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
@@ -587,7 +609,13 @@ mts_status mts_read_bonds(mts_solver *h, int64_t *row_ptr, int32_t *col, uint8_t
 
 mts_status mts_query(mts_solver *h, mts_info *o) {
   if (!h || !o) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
-  Solver &s = h->s;
+  query_impl(h->s, o);
+  return MTS_OK;
+}
+
+}  // extern "C"
+
+void mts::query_impl(Solver &s, mts_info *o) {
   std::memset(o, 0, sizeof *o);
   o->delta = s.prm.delta;
   o->volume = s.prm.V;
@@ -608,8 +636,9 @@ mts_status mts_query(mts_solver *h, mts_info *o) {
   o->device_bytes = (int64_t)s.arena.bytes;
   o->dim = s.dim;
   o->precision = s.precision;
-  return MTS_OK;
 }
+
+extern "C" {
 
 mts_status mts_profile(mts_solver *h, int32_t enable) {
   if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);

@@ -1,0 +1,160 @@
+"""Serving pool (continuous batching) on the GPU, through the C-ABI.
+
+A request's result must not depend on what else runs in the pool: the same
+requests run alone and in a mix (joining at different pool steps, with and
+without graph replay) give bit-identical displacements and damage.  The
+batched substep path is also checked against the FP64 oracle (relative L2 of
+the displacement, the mixed form's bound) and against a plain solver.
+"""
+import numpy as np
+import pytest
+
+import mts_inputs as mi
+from oracle import Oracle
+import oracle.oracle as O
+
+pytestmark = pytest.mark.gpu
+
+BIG = 64 << 30
+
+
+@pytest.fixture(scope="module")
+def mts():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_03605_amd as m
+    m.load()
+    return m
+
+
+def _requests():
+    """Four requests of uneven size and step ratio (the serving recipe, short runs)."""
+    raw = [dict(nx=100, notch=0.045, crack_y=0.018, traction=1.5e6, m=4, seed=101, t_end=2.0e-6),
+           dict(nx=140, notch=0.030, crack_y=0.022, traction=0.8e6, m=8, seed=102, t_end=2.0e-6),
+           dict(nx=160, notch=0.055, crack_y=0.020, traction=2.0e6, m=10, seed=103, t_end=2.4e-6),
+           dict(nx=120, notch=0.040, crack_y=0.015, traction=1.2e6, m=10, seed=104, t_end=1.6e-6)]
+    return [mi.serving_instance(r) for r in raw]
+
+
+def _drain(pool, ids_expected):
+    out = {}
+    while len(out) < len(ids_expected):
+        _, done = pool.step()
+        for rid in done:
+            out[rid] = True
+    return out
+
+
+def _read(mts, pool, rid, inst):
+    n = inst["pos"].shape[0]
+    return pool.read(rid, mts.PD_U, 2 * n), pool.read(rid, mts.DAMAGE, n)
+
+
+def _alone(mts, inst, graphs=True):
+    pool = mts.Pool(BIG, max_slots=4, use_graphs=graphs)
+    rid = pool.submit(inst, inst["n_macro"])
+    _drain(pool, [rid])
+    u, phi = _read(mts, pool, rid, inst)
+    info = pool.query()
+    pool.release(rid)
+    pool.close()
+    return u, phi, info
+
+
+def test_alone_equals_mix(mts):
+    insts = _requests()
+    alone = [_alone(mts, i) for i in insts]
+    assert all(a[2]["graph_replays"] > 0 for a in alone)
+    pool = mts.Pool(BIG, max_slots=8, use_graphs=True)
+    ids = [pool.submit(insts[0], insts[0]["n_macro"]), pool.submit(insts[1], insts[1]["n_macro"])]
+    done = {}
+    for _ in range(3):
+        for rid in pool.step()[1]:
+            done[rid] = True
+    ids.append(pool.submit(insts[2], insts[2]["n_macro"]))
+    for _ in range(2):
+        for rid in pool.step()[1]:
+            done[rid] = True
+    ids.append(pool.submit(insts[3], insts[3]["n_macro"]))
+    while len(done) < 4:
+        for rid in pool.step()[1]:
+            done[rid] = True
+    info = pool.query()
+    print("mix pool", info)
+    for k, rid in enumerate(ids):
+        u, phi = _read(mts, pool, rid, insts[k])
+        assert np.array_equal(u, alone[k][0]), k
+        assert np.array_equal(phi, alone[k][1]), k
+        assert np.abs(u).max() > 0
+        pool.release(rid)
+    pool.close()
+
+
+def test_graphs_equal_eager(mts):
+    inst = _requests()[2]
+    ug, pg, ig = _alone(mts, inst, graphs=True)
+    ue, pe, ie = _alone(mts, inst, graphs=False)
+    assert ig["graph_replays"] > 0 and ie["graph_replays"] == 0
+    assert np.array_equal(ug, ue)
+    assert np.array_equal(pg, pe)
+
+
+def _rel_l2(g, w):
+    return np.sqrt(((g - w) ** 2).sum()) / max(np.sqrt((w ** 2).sum()), 1e-300)
+
+
+def test_pool_against_oracle_and_solver(mts):
+    """Batched substep path vs the FP64 oracle (mixed-form bound) and vs a plain
+    solver of the same request (different lane count, so FP32 sums differ in
+    order only)."""
+    inst = _requests()[0]
+    u, phi, _ = _alone(mts, inst)
+    o = Oracle(inst)
+    o.advance(inst["n_macro"])
+    assert o.info()["n_broken"] == 0
+    uo = o.get(O.PD_U)
+    e = _rel_l2(u, uo)
+    print("pool vs oracle rel L2", e)
+    assert e <= 1e-4
+    s = mts.Solver(inst)
+    s.advance(inst["n_macro"])
+    us = s.read(mts.PD_U)
+    e2 = _rel_l2(u, us)
+    print("pool vs plain solver rel L2", e2)
+    assert e2 <= 1e-5
+    s.close()
+
+
+def test_admission_by_budget(mts):
+    insts = _requests()
+    est = mts.plan(insts[2])["device_bytes_estimate"]
+    with pytest.raises(mts.MtsError):
+        mts.Pool(est // 2, max_slots=4).submit(insts[2], 1)   # ETOOBIG
+    pool = mts.Pool(int(est * 1.5), max_slots=4)
+    a = pool.submit(insts[2], 2)
+    assert a is not None
+    assert pool.submit(insts[2], 2) is None  # EAGAIN: budget held by the first
+    _drain(pool, [a])
+    pool.release(a)
+    b = pool.submit(insts[2], 2)
+    assert b is not None
+    _drain(pool, [b])
+    pool.release(b)
+    assert pool.query()["used_bytes"] == 0
+    pool.close()
+
+
+def test_serve_loop(mts):
+    """Threaded admission + stepping over a short compressed stream; every result
+    equals the request run alone."""
+    from paper_2403_03605_amd.serving import serve
+    insts = _requests()
+    reqs = [{"arrival": 0.02 * k, "inst": i} for k, i in enumerate(insts)]
+    out = serve(reqs, BIG, max_slots=8, keep_results=True)
+    print({k: v for k, v in out.items() if k not in ("results", "latencies_s")})
+    assert out["n_requests"] == 4 and out["p99_s"] > 0
+    for k, inst in enumerate(insts):
+        u, phi, _ = _alone(mts, inst)
+        assert np.array_equal(out["results"][k]["u"], u)
+        assert np.array_equal(out["results"][k]["damage"], phi)
