@@ -91,6 +91,34 @@ def cpu_baseline(inst, seconds=15.0):
                       f"pure-PD mode (bond pass with breaking + Verlet), plain C FP64, 1 thread, {dt:.1f} s"}
 
 
+def serve_main(args, torch, mts, log):
+    """Serving form: the seeded stream of plate solves (sizes 100x40 .. 800x320,
+    m in {4, 8, 10}, mixed precision) with Poisson arrivals at 20 per second,
+    admitted by device-memory budget and advanced together in the pool."""
+    from paper_2403_03605_amd.serving import serve, stream_requests
+    reqs = stream_requests(args.serve_requests)
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(args.serve_budget_gib * (1 << 30)) if args.serve_budget_gib > 0 else int(0.9 * free)
+    log(f"serving {len(reqs)} requests, budget {budget / 2**30:.1f} GiB")
+    out = serve(reqs, budget, max_slots=64, use_graphs=not args.serve_no_graphs,
+                log=lambda m: log(m), builders=args.serve_builders)
+    sizes = {}
+    for r in reqs:
+        sizes[f"{r['nx']}x{r['ny']}"] = sizes.get(f"{r['nx']}x{r['ny']}", 0) + 1
+    line = {
+        "metric": "served p99 latency (s), with p50 and aggregate PD bond-updates/s",
+        "value": out["p99_s"], "unit": "s", "n_gpus": 1, "steps": out["pool_steps"], "warmup": 0,
+        "ms_per_step": out["span_s"] * 1e3 / max(out["pool_steps"], 1), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 bond math / f64 integration", "data": "synthetic",
+        "config": {"workload": f"serving stream: {len(reqs)} plate solves, Poisson 20/s, 10 us of physical time each",
+                   "budget_bytes": budget, "graphs": not args.serve_no_graphs,
+                   "builders": args.serve_builders},
+        "serving": {k: v for k, v in out.items() if k != "latencies_s"},
+        "request_sizes": sizes,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +132,12 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving stream (Poisson arrivals of plate solves) through the pool instead")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0, help="pool budget (0: 90%% of free HBM)")
+    ap.add_argument("--serve-no-graphs", action="store_true")
+    ap.add_argument("--serve-builders", type=int, default=4, help="threads that build arrived requests")
     ap.add_argument("--profile-steps", type=int, default=100, help="macro steps of the event-timed pass")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -129,6 +163,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.serve:
+        return serve_main(args, torch, mts, log)
     inst = mi.config(args.config) if args.precision is None else mi.config(args.config, precision=args.precision)
     if args.precision is not None:
         inst["name"] += f" ({args.precision})"

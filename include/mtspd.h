@@ -174,9 +174,9 @@ const char *mts_last_error(void);
  * while the set of running requests does not change.  A request's results equal
  * those of the same request running alone in a pool (same lane count, same
  * arithmetic order).
- * Threads: mts_pool_submit may run on one other thread concurrently with the
- * other pool calls (it builds the request on a stream of its own); all other
- * pool calls must come from one thread.
+ * Threads: mts_pool_submit may run on other threads (several at once)
+ * concurrently with the other pool calls (each call builds its request on a
+ * stream of its own); all other pool calls must come from one thread.
  * ------------------------------------------------------------------------- */
 enum { MTS_REQ_ACTIVE = 1, MTS_REQ_DONE = 2 };
 
@@ -198,8 +198,8 @@ typedef struct mts_pool_info {
 mts_status mts_pool_create(int64_t budget_bytes, int32_t max_slots, int32_t dim, int32_t precision,
                            int32_t use_graphs, void *hip_stream, mts_pool **out);
 
-/* Build a request (synchronous; may run concurrently with mts_pool_step on one
- * other thread) that will run n_macro macro steps; it joins the running set at
+/* Build a request (synchronous; may run concurrently with mts_pool_step and
+ * with other submits on other threads) that will run n_macro macro steps; it joins the running set at
  * the next pool step.  *id identifies it.  Errors: MTS_EAGAIN (no slot or not
  * enough budget now: submit again after a release), MTS_ETOOBIG (the estimate
  * exceeds the whole budget), MTS_EINVAL (bad description, or dim/precision

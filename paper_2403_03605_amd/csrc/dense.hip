@@ -1,9 +1,17 @@
 // Dense FP64 linear algebra for the multiplier system of Eq. 49: each diagonal
 // block of the symmetric positive-definite matrix H (one per connected
-// component of the coupling graph) is inverted once per (re)build by blocked
-// in-place Gauss-Jordan elimination (no pivoting, SPD) and stored as its
-// lower-triangle 64 x 64 tiles; every macro step applies the inverse with a
-// tile-parallel symmetric GEMV whose partial sums are combined in a fixed order.
+// component of the coupling graph) is inverted once per (re)build and stored
+// as its lower-triangle 64 x 64 tiles; every macro step applies the inverse
+// with a tile-parallel symmetric GEMV whose partial sums are combined in a
+// fixed order.
+//
+// Inversion: the symmetric sweep operator, one 64-wide pivot block at a time,
+// directly on the packed lower tiles.  Sweeping pivot block K of a symmetric A
+// with P = A_KK^-1:
+//   A_IJ <- A_IJ - A_IK P A_KJ   (I, J != K),
+//   A_IK <- A_IK P,  A_KJ <- P A_KJ,  A_KK <- -P,
+// keeps A symmetric, so only the lower tiles are touched; sweeping every block
+// leaves -A^-1.  The rank-64 updates run on the FP64 matrix cores.
 #include "internal.h"
 
 #include <algorithm>
@@ -13,189 +21,204 @@ namespace mts {
 
 namespace {
 
-constexpr int NB = 64;
+constexpr int TS = 64;  // tile side
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Invert the kb x kb pivot block A[k0:k0+kb, k0:k0+kb] in LDS (Gauss-Jordan),
-// padded to 64 x 64 with the identity (whose inverse is itself).  Thread t
-// owns column t % 64 and rows 16 (t / 64) .. 16 (t / 64) + 15.
-__global__ __launch_bounds__(256) void k_pivot_inverse(const double *A, int64_t n, int64_t k0, int kb,
-                                                      double *pinv) {
-  __shared__ double M[NB][NB + 1];
-  __shared__ double rowp[NB], colp[NB];
-  const int c = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * 16;
-  for (int q = 0; q < 16; q++) {
-    const int r = r0 + q;
-    M[r][c] = (r < kb && c < kb) ? A[(k0 + r) * n + k0 + c] : (r == c ? 1.0 : 0.0);
+__device__ inline int64_t tile_row(int64_t tile) {
+  int64_t I = (int64_t)((sqrt(8.0 * (double)tile + 1.0) - 1.0) / 2.0);
+  while (I * (I + 1) / 2 > tile) I--;
+  while ((I + 1) * (I + 2) / 2 <= tile) I++;
+  return I;
+}
+
+__device__ inline int64_t tile_index(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
+
+// packed[tile (I, J), J <= I][r][c] = H[idx[64 I + r]][idx[64 J + c]] (0 outside)
+__global__ void k_pack_lower(const double *H, int64_t nl, const int32_t *idx, int64_t n, int64_t T, double *packed) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T * (T + 1) / 2 * TS * TS) return;
+  const int64_t tile = t / (TS * TS);
+  const int e = (int)(t % (TS * TS));
+  const int64_t I = tile_row(tile), J = tile - I * (I + 1) / 2;
+  const int64_t i = I * TS + e / TS, j = J * TS + e % TS;
+  packed[t] = (i < n && j < n) ? H[(int64_t)idx[i] * nl + idx[j]] : 0.0;
+}
+
+// P = inverse of the diagonal tile (k, k) (symmetric part), its rows/columns
+// past n padded with the identity.  Gauss-Jordan without pivoting (SPD); thread t keeps the 4 x 4
+// sub-block rows 4 (t / 16) .., columns 4 (t % 16) .. in registers, and the
+// pivot row and column pass through LDS (double-buffered: one barrier a step).
+__global__ __launch_bounds__(256) void k_tile_inverse(const double *packed, int64_t k, int64_t n, double *P) {
+  __shared__ double rowp[2][TS], colp[2][TS];
+  const int t = threadIdx.x, r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
+  const double *D = packed + tile_index(k, k) * TS * TS;
+  const int kb = (int)std::min<int64_t>(TS, n - k * TS);
+  double M[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int r = r0 + a, c = c0 + b;
+      M[a][b] = (r < kb && c < kb) ? D[r * TS + c] : (r == c ? 1.0 : 0.0);
+    }
+  for (int p = 0; p < TS; p++) {
+    const int buf = p & 1;
+    // (constant register indices only: a runtime index would move M to scratch)
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (r0 + a == p)
+#pragma unroll
+        for (int b = 0; b < 4; b++) rowp[buf][c0 + b] = M[a][b];
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+      if (c0 + b == p)
+#pragma unroll
+        for (int a = 0; a < 4; a++) colp[buf][r0 + a] = M[a][b];
+    __syncthreads();
+    const double d = 1.0 / rowp[buf][p];
+    double rs[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++) rs[b] = rowp[buf][c0 + b] * d;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int r = r0 + a;
+      const double cp = colp[buf][r];
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int c = c0 + b;
+        if (r == p) M[a][b] = (c == p) ? d : rs[b];
+        else if (c == p) M[a][b] = -cp * d;
+        else M[a][b] = M[a][b] - cp * rs[b];
+      }
+    }
   }
+  // P is symmetric up to rounding; storing its symmetric part keeps the sweep
+  // exactly symmetric, which the lower-tile storage relies on.
+  __shared__ double S[TS][TS + 1];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) S[r0 + a][c0 + b] = M[a][b];
   __syncthreads();
-  for (int p = 0; p < NB; p++) {
-    const double d = 1.0 / M[p][p];
-    if (threadIdx.x < NB) {
-      rowp[c] = (c == p) ? d : M[p][c] * d;
-      colp[c] = M[c][p];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int r = r0 + a, c = c0 + b;
+      P[r * TS + c] = 0.5 * (S[r][c] + S[c][r]);
     }
-    __syncthreads();
-    for (int q = 0; q < 16; q++) {
-      const int r = r0 + q;
-      double v;
-      if (r == p) v = rowp[c];
-      else if (c == p) v = -colp[r] * d;
-      else v = M[r][c] - colp[r] * rowp[c];
-      M[r][c] = v;
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < 16; q++) {
-    const int r = r0 + q;
-    if (r < kb && c < kb) pinv[r * kb + c] = M[r][c];
+}
+
+// Load a 64 x 64 tile (row-major source, optionally transposed) into LDS.
+__device__ inline void load_tile(double (*dst)[TS + 1], const double *src, bool transpose) {
+  for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+    const int r = e / TS, c = e % TS;
+    if (transpose) dst[c][r] = src[e];
+    else dst[r][c] = src[e];
   }
 }
 
-// C[i][t] = A[i][k0+t] (0 on the pivot rows);  R[t][j] = (Pinv A[K,:])[t][j], R[:,K] = Pinv.
-__global__ void k_panels(const double *A, int64_t n, int64_t k0, int kb, const double *pinv, double *C,
-                         double *R) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t total = n * kb;
-  if (idx >= total) return;
-  // C part: idx -> (i, t)
-  {
-    int64_t i = idx / kb;
-    int t = (int)(idx % kb);
-    bool inK = i >= k0 && i < k0 + kb;
-    C[i * kb + t] = inK ? 0.0 : A[i * n + k0 + t];
-  }
-  // R part: idx -> (t, j)
-  {
-    int t = (int)(idx / n);
-    int64_t j = idx % n;
-    double r;
-    if (j >= k0 && j < k0 + kb) {
-      r = pinv[t * kb + (j - k0)];
-    } else {
-      r = 0.0;
-      for (int s = 0; s < kb; s++) r += pinv[t * kb + s] * A[(k0 + s) * n + j];
+// acc (wave w's 16 rows, 4 column tiles) += sign * X[16 w .., :] * Y where
+// Y[kk][col] = Ycol(col, kk) (ycol_major) or Y[kk][col] (row-major).
+template <bool YT>
+__device__ inline void mfma_rows(d4 acc[4], const double (*X)[TS + 1], const double (*Y)[TS + 1], double sign) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k0 = 0; k0 < TS; k0 += 4) {
+    const double a = sign * X[16 * w + lr][k0 + lk];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const double b = YT ? Y[16 * t + lr][k0 + lk] : Y[k0 + lk][16 * t + lr];
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
     }
-    R[(int64_t)t * n + j] = r;
   }
 }
 
-__global__ void k_write_panels(double *A, int64_t n, int64_t k0, int kb, const double *R) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * kb) return;
-  {
-    int t = (int)(idx / n);
-    int64_t j = idx % n;
-    A[(k0 + t) * n + j] = R[(int64_t)t * n + j];
-  }
-  {
-    int64_t i = idx / kb;
-    int t = (int)(idx % kb);
-    if (!(i >= k0 && i < k0 + kb)) A[i * n + k0 + t] = 0.0;
-  }
+// Panel of pivot block k: V_I = A_Ik (from tile (I, k) or the transpose of
+// tile (k, I)) and W_I = V_I P, one workgroup per tile row I.
+__global__ __launch_bounds__(256) void k_sweep_panel(const double *packed, int64_t k, const double *P, double *V,
+                                                    double *W) {
+  __shared__ double Vs[TS][TS + 1], Ps[TS][TS + 1];
+  const int64_t I = blockIdx.x;
+  const bool below = I >= k;
+  load_tile(Vs, packed + (below ? tile_index(I, k) : tile_index(k, I)) * TS * TS, !below);
+  load_tile(Ps, P, false);
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  mfma_rows<false>(acc, Vs, Ps, 1.0);
+  double *Vo = V + I * TS * TS, *Wo = W + I * TS * TS;
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+      const int r = 16 * w + 4 * g + lk, c = 16 * t + lr;
+      Wo[r * TS + c] = acc[t][g];
+      Vo[r * TS + c] = Vs[r][c];
+    }
 }
 
-// A -= C R over the whole matrix: a rank-kb update, kb <= 64, on the FP64
-// matrix cores.  64 x 64 output tile per workgroup; wave w owns rows
-// [16 w, 16 w + 16) of the tile as four 16 x 16 MFMA tiles, accumulating onto
-// the loaded A with the negated C operand.  Operand layout of
-// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-// accumulator register g of lane l is row 4 g + l / 16, column l % 16.
-__global__ __launch_bounds__(256) void k_rank_update(double *A, int64_t n, int kb, const double *C,
-                                                     const double *R) {
-  __shared__ double Cs[NB][NB + 1];
-  __shared__ double Rs[NB][NB + 1];
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  for (int t = threadIdx.x; t < 64 * NB; t += 256) {
-    const int r = t / NB, c = t % NB;
-    const int64_t i = i0 + r;
-    Cs[r][c] = (i < n && c < kb) ? -C[i * kb + c] : 0.0;
-    const int64_t j = j0 + c;
-    Rs[r][c] = (r < kb && j < n) ? R[(int64_t)r * n + j] : 0.0;
+// Sweep of pivot block k over every lower tile (one workgroup per tile).
+// Interior tiles: A_IJ -= W_I V_J^T on the matrix cores with the operands read
+// straight from the (cache-resident) panels: lane group lk of a wavefront
+// supplies the reduction indices 16 lk .. 16 lk + 15 (a permutation of the
+// 64-term sums, so each lane reads contiguous 128-byte runs), no LDS.
+__global__ __launch_bounds__(256) void k_sweep_update(double *packed, int64_t k, const double *P, const double *V,
+                                                     const double *W) {
+  const int64_t tile = blockIdx.x;
+  const int64_t I = tile_row(tile), J = tile - I * (I + 1) / 2;
+  double *A = packed + tile * TS * TS;
+  if (I == k || J == k) {
+    // pivot row / column / diagonal: -P, W_I, or W_J^T
+    const double *src = (I == k && J == k) ? P : (J == k ? W + I * TS * TS : W + J * TS * TS);
+    const double sg = (I == k && J == k) ? -1.0 : 1.0;
+    const bool tr = I == k && J != k;
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+      const int r = e / TS, c = e % TS;
+      A[e] = sg * (tr ? src[c * TS + r] : src[e]);
+    }
+    return;
   }
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  typedef double d4 __attribute__((ext_vector_type(4)));
   d4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
-    for (int g = 0; g < 4; g++) {
-      const int64_t i = i0 + 16 * w + 4 * g + lk, j = j0 + 16 * t + lr;
-      acc[t][g] = (i < n && j < n) ? A[i * n + j] : 0.0;
-    }
-  __syncthreads();
-  for (int k0 = 0; k0 < NB; k0 += 4) {
-    const double a = Cs[16 * w + lr][k0 + lk];
+    for (int g = 0; g < 4; g++) acc[t][g] = A[(16 * w + 4 * g + lk) * TS + 16 * t + lr];
+  const double2 *wrow = reinterpret_cast<const double2 *>(W + I * TS * TS + (16 * w + lr) * TS + 16 * lk);
+  double a[16];
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const double b = Rs[k0 + lk][16 * t + lr];
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+  for (int q = 0; q < 8; q++) {
+    const double2 v = wrow[q];
+    a[2 * q] = -v.x;
+    a[2 * q + 1] = -v.y;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const double2 *vrow = reinterpret_cast<const double2 *>(V + J * TS * TS + (16 * t + lr) * TS + 16 * lk);
+    double b[16];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const double2 v = vrow[q];
+      b[2 * q] = v.x;
+      b[2 * q + 1] = v.y;
     }
+#pragma unroll
+    for (int s2 = 0; s2 < 16; s2++) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], b[s2], acc[t], 0, 0, 0);
   }
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
-    for (int g = 0; g < 4; g++) {
-      const int64_t i = i0 + 16 * w + 4 * g + lk, j = j0 + 16 * t + lr;
-      if (i < n && j < n) A[i * n + j] = acc[t][g];
-    }
+    for (int g = 0; g < 4; g++) A[(16 * w + 4 * g + lk) * TS + 16 * t + lr] = acc[t][g];
 }
 
-}  // namespace
-
-void dense_spd_inverse(Solver &s, double *A, int64_t n) {
-  hipStream_t st = s.stream;
-  if (n <= 0) return;
-  if (!s.tmpA) {  // sized for the largest block this solver will ever invert
-    const int64_t cap = std::max<int64_t>(n, s.sym.n_max);
-    s.tmpA = s.arena.alloc<double>((size_t)cap * NB);
-    s.tmpB = s.arena.alloc<double>((size_t)cap * NB);
-    s.pinv = s.arena.alloc<double>((size_t)NB * NB);
-  }
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    int kb = (int)std::min<int64_t>(NB, n - k0);
-    k_pivot_inverse<<<1, 256, 0, st>>>(A, n, k0, kb, s.pinv);
-    MTS_LAUNCH_CHECK();
-    int64_t tot = n * kb;
-    k_panels<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(A, n, k0, kb, s.pinv, s.tmpA, s.tmpB);
-    MTS_LAUNCH_CHECK();
-    k_write_panels<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(A, n, k0, kb, s.tmpB);
-    MTS_LAUNCH_CHECK();
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-    k_rank_update<<<grid, 256, 0, st>>>(A, n, kb, s.tmpA, s.tmpB);
-    MTS_LAUNCH_CHECK();
-  }
-}
-
-
-// ---------------------------------------------------------------------------
-// Block-diagonal inverse in packed lower-triangle tiles
-// ---------------------------------------------------------------------------
-namespace {
-
-constexpr int TS = 64;  // tile side
-
-// work[i][j] = H[idx[i]][idx[j]] for one component
-__global__ void k_gather_block(const double *H, int64_t nl, const int32_t *idx, int64_t n, double *work) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * n) return;
-  int64_t i = t / n, j = t % n;
-  work[t] = H[(int64_t)idx[i] * nl + idx[j]];
-}
-
-// packed[tile (I, J), J <= I][r][c] = work[64 I + r][64 J + c] (0 outside)
-__global__ void k_pack_tiles(const double *work, int64_t n, int64_t T, double *packed) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t ntile = T * (T + 1) / 2;
-  if (t >= ntile * TS * TS) return;
-  int64_t tile = t / (TS * TS);
-  int e = (int)(t % (TS * TS));
-  int64_t I = (int64_t)((sqrt(8.0 * (double)tile + 1.0) - 1.0) / 2.0);
-  while (I * (I + 1) / 2 > tile) I--;
-  while ((I + 1) * (I + 2) / 2 <= tile) I++;
-  int64_t J = tile - I * (I + 1) / 2;
-  int64_t i = I * TS + e / TS, j = J * TS + e % TS;
-  packed[t] = (i < n && j < n) ? work[i * n + j] : 0.0;
+__global__ void k_negate(double *a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = -a[i];
 }
 
 // One workgroup per tile: row partial A_IJ x_J (for block row I) and, off the
@@ -301,7 +324,12 @@ void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps)
   B.packed = ar.alloc<double>((size_t)B.n_tiles * TS * TS);
   B.rowpart = ar.alloc<double>((size_t)B.n_tiles * TS);
   B.colpart = ar.alloc<double>((size_t)B.n_tiles * TS);
-  B.work = ar.alloc<double>((size_t)B.n_max * B.n_max);
+  {
+    const int64_t Tm = (B.n_max + TS - 1) / TS;
+    B.pv = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * TS);
+    B.pw = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * TS);
+    B.pinv = ar.alloc<double>((size_t)TS * TS);
+  }
   std::vector<int32_t> rc, rb;
   for (int64_t c = 0; c < B.n_comp; c++) {
     int64_t T = (B.h_off[c + 1] - B.h_off[c] + TS - 1) / TS;
@@ -323,20 +351,28 @@ void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps)
   MTS_HIP(hipStreamSynchronize(st));
 }
 
-// Invert every component block of H (already assembled in s.H) and pack it.
+// Invert every component block of H (assembled in s.H) in packed lower tiles.
 void sym_blocks_build(Solver &s) {
   auto &B = s.sym;
   hipStream_t st = s.stream;
-  std::vector<int64_t> tbase(B.n_comp + 1, 0);
+  int64_t tb = 0;
   for (int64_t c = 0; c < B.n_comp; c++) {
-    int64_t n = B.h_off[c + 1] - B.h_off[c];
-    int64_t T = (n + TS - 1) / TS;
-    tbase[c + 1] = tbase[c] + T * (T + 1) / 2;
-    k_gather_block<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(s.H, s.nl, B.idx + B.h_off[c], n, B.work);
+    const int64_t n = B.h_off[c + 1] - B.h_off[c];
+    const int64_t T = (n + TS - 1) / TS, ntile = T * (T + 1) / 2;
+    double *pk = B.packed + tb * TS * TS;
+    tb += ntile;
+    k_pack_lower<<<(unsigned)((ntile * TS * TS + 255) / 256), 256, 0, st>>>(s.H, s.nl, B.idx + B.h_off[c], n, T, pk);
     MTS_LAUNCH_CHECK();
-    dense_spd_inverse(s, B.work, n);
-    int64_t ne = T * (T + 1) / 2 * TS * TS;
-    k_pack_tiles<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(B.work, n, T, B.packed + tbase[c] * TS * TS);
+    for (int64_t k = 0; k < T; k++) {
+      k_tile_inverse<<<1, 256, 0, st>>>(pk, k, n, B.pinv);
+      MTS_LAUNCH_CHECK();
+      k_sweep_panel<<<(unsigned)T, 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw);
+      MTS_LAUNCH_CHECK();
+      k_sweep_update<<<(unsigned)ntile, 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw);
+      MTS_LAUNCH_CHECK();
+    }
+    // the sweep leaves -H^-1
+    k_negate<<<(unsigned)((ntile * TS * TS + 255) / 256), 256, 0, st>>>(pk, ntile * TS * TS);
     MTS_LAUNCH_CHECK();
     vlog(s, "coupling: block %lld of %lld inverted (%lld dofs)", (long long)(c + 1), (long long)B.n_comp,
          (long long)n);

@@ -166,11 +166,11 @@ struct Solver {
     int64_t *tile_base = nullptr;   // per component: first tile
     double *packed = nullptr;       // n_tiles * 4096
     double *rowpart = nullptr, *colpart = nullptr;  // n_tiles * 64
-    double *work = nullptr;         // n_max * n_max
+    double *pv = nullptr, *pw = nullptr;  // sweep panels, one 64 x 64 tile per tile row
+    double *pinv = nullptr;         // inverse of the current pivot tile
     int64_t n_rows = 0;             // block rows over all components
     int32_t *row_comp = nullptr, *row_block = nullptr;
   } sym;
-  double *tmpA = nullptr, *tmpB = nullptr, *pinv = nullptr;
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;
   Sell rsell;                    // link region rows
@@ -236,7 +236,6 @@ void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);
 void coupling_solve_and_correct(Solver &s);
 // dense linear algebra (dense.hip)
-void dense_spd_inverse(Solver &s, double *A, int64_t n);
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
 void sym_blocks_apply(Solver &s, const double *r, double *y);

@@ -14,8 +14,9 @@
 // from HIP graphs, one per phase and parity of the pool step (every per-step
 // alternation of a request -- displacement buffer, state snapshot slot -- has
 // period two).  Requests join and leave between pool steps: a request created
-// (on the caller's thread, on a separate stream) while others run is admitted at
-// the next step, and a finished request leaves the set at once.
+// (on a caller's thread, on a separate stream) while others run is admitted at
+// the next step, and a finished request leaves the set at once.  Several
+// requests may be built at once, each on a stream of its own.
 #include <algorithm>
 #include <condition_variable>
 #include <cstring>
@@ -69,7 +70,6 @@ using namespace mts;
 
 struct mts_pool {
   hipStream_t stream = nullptr;   // pool steps
-  hipStream_t setup_st = nullptr; // request construction
   hipStream_t read_st = nullptr;  // reads of finished requests
   bool own_stream = false;
   int dim = 2, precision = MTS_MIXED, lanes = 4;
@@ -350,7 +350,6 @@ mts_status mts_pool_create(int64_t budget_bytes, int32_t max_slots, int32_t dim,
       MTS_HIP(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
       P->own_stream = true;
     }
-    MTS_HIP(hipStreamCreateWithFlags(&P->setup_st, hipStreamNonBlocking));
     MTS_HIP(hipStreamCreateWithFlags(&P->read_st, hipStreamNonBlocking));
     for (auto &e : P->ev_a) MTS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     *out = P;
@@ -368,8 +367,8 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
   if (p->dim != P->dim || p->precision != P->precision)
     return (set_error("request dim/precision differ from the pool's"), MTS_EINVAL);
   mts_plan_info plan{};
-  mts_status st = mts_plan(p, &plan);
-  if (st != MTS_OK) return st;
+  const mts_status pst = mts_plan(p, &plan);
+  if (pst != MTS_OK) return pst;
   const int64_t est = plan.device_bytes_estimate;
   {
     std::unique_lock<std::mutex> lk(P->mu);
@@ -389,20 +388,31 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
   Req *r = new Req();
   r->n_macro = n_macro;
   r->charged = est;
+  hipStream_t st = nullptr;  // per call, so that concurrent submits build in parallel
   try {
+    MTS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     r->s = new Solver();
     r->s->force_lanes = P->lanes;
-    create_impl(p, P->setup_st, r->s);
+    create_impl(p, st, r->s);  // ends with a synchronisation of st
+    r->s->stream = P->stream;
+    MTS_HIP(hipStreamDestroy(st));
+    st = nullptr;
     MTS_HIP(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
     r->tracked = p->mode == MTS_COUPLED && p->m >= 2;
   } catch (...) {
-    st = fail_from_exception();
+    const mts_status err = fail_from_exception();
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      if (r->s) r->s->stream = P->stream;
+      (void)hipStreamDestroy(st);
+    }
     destroy_solver(r->s);
     delete r;
     std::lock_guard<std::mutex> lk(P->mu);
     P->used -= est;
     P->creating--;
-    return st;
+    P->cv.notify_all();
+    return err;
   }
   std::lock_guard<std::mutex> lk(P->mu);
   const int64_t actual = (int64_t)r->s->arena.bytes;
@@ -506,7 +516,6 @@ void mts_pool_destroy(mts_pool *P) {
   if (P->blk_req) (void)hipFree(P->blk_req);
   for (auto &e : P->ev_a)
     if (e) (void)hipEventDestroy(e);
-  if (P->setup_st) (void)hipStreamDestroy(P->setup_st);
   if (P->own_stream) (void)hipStreamDestroy(P->stream);
   if (P->read_st) (void)hipStreamDestroy(P->read_st);
   delete P;

@@ -1,10 +1,10 @@
 """Request loop over the serving pool (continuous batching).
 
-Requests arrive on their own clock (Poisson arrivals, seconds); an admission
-thread builds each arrived request into the pool as soon as a slot and device
-memory are free (mts_pool_submit runs the neighbour build and the unit-load
-responses on a stream of its own), while the main thread keeps issuing pool
-steps that advance every running request by one macro step.  Finished requests
+Requests arrive on their own clock (Poisson arrivals, seconds); a few builder
+threads take arrived requests in order and build each into the pool as soon as
+a slot and device memory are free (mts_pool_submit runs the neighbour build and
+the unit-load responses on a stream of its own), while the main thread keeps
+issuing pool steps that advance every running request by one macro step.  Finished requests
 are read back (damage and displacement) and released, which frees budget for
 waiting arrivals.  Latency is completion minus arrival.
 """
@@ -20,7 +20,7 @@ from . import _lib
 
 
 def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_graphs: bool = True,
-          stream=None, keep_results: bool = False, log=None) -> Dict:
+          stream=None, keep_results: bool = False, log=None, builders: int = 4) -> Dict:
     """Run `requests` (dicts with "arrival" in seconds and "inst", an instance
     dict with "n_macro") through a pool.
 
@@ -41,9 +41,18 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
     work = [0.0] * n  # bond-updates of each request (directed slots x PD substeps)
     t0 = time.perf_counter()
 
+    next_k = [0]
+
     def admission():
+        """One of `builders` threads: take the next request in arrival order,
+        wait for its arrival, build it into the pool (retrying while full)."""
         try:
-            for k in order:
+            while True:
+                with lock:
+                    if next_k[0] >= n:
+                        return
+                    k = order[next_k[0]]
+                    next_k[0] += 1
                 r = requests[k]
                 delay = t0 + r["arrival"] - time.perf_counter()
                 if delay > 0:
@@ -62,8 +71,9 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
         except Exception as e:  # surfaced by the main loop
             errors.append(e)
 
-    th = threading.Thread(target=admission, daemon=True)
-    th.start()
+    threads = [threading.Thread(target=admission, daemon=True) for _ in range(max(1, builders))]
+    for th in threads:
+        th.start()
     finished = 0
     steps = 0
     while finished < n:
@@ -91,7 +101,8 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
                 log(f"request {k} ({inst['name']}) done: latency {t_done[k] - requests[k]['arrival']:.3f} s")
         if na == 0 and not done:
             time.sleep(0.0005)
-    th.join()
+    for th in threads:
+        th.join()
     info = pool.query()
     pool.close()
     arr = np.array([requests[k]["arrival"] for k in range(n)])
