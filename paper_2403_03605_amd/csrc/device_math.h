@@ -46,11 +46,11 @@ __device__ inline int64_t sell_slot(int64_t slot_off, int j, int k, int L) {
   return slot_off + (int64_t)(k / L) * WAVE + j * L + (k % L);
 }
 
-// Bond state of slot k of node i in the full-lattice layout.
-__device__ inline bool full_bit(const int64_t *word_off, const uint64_t *mask, int L, int64_t i, int k) {
+// Bond state of slot k of row r in the full-lattice layout.
+__device__ inline bool full_bit(const int64_t *word_off, const uint64_t *mask, int L, int64_t r, int k) {
   const int S = WAVE / L;
-  const int64_t s = i / S;
-  const int j = (int)(i % S);
+  const int64_t s = r / S;
+  const int j = (int)(r % S);
   return (mask[word_off[s] + k / L] >> (j * L + (k % L))) & 1ull;
 }
 

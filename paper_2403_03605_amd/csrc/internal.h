@@ -79,7 +79,8 @@ struct Sell {
   int64_t n_rows = 0, n_slices = 0, n_slots = 0, n_words = 0;
   int L = 1;
   int T = 0;                     // iterations per slice (same for every slice)
-  int32_t *rows = nullptr;       // row -> node id (identity for the full lattice)
+  int32_t *rows = nullptr;       // row -> node id
+  int32_t *row_of = nullptr;     // node -> row (full layout in tile order; nullptr: identity)
   int32_t *width = nullptr;      // per slice, slots per row rounded up to a multiple of L
   int64_t *slot_off = nullptr;   // per slice, in slots (multiple of 64)
   int64_t *word_off = nullptr;   // per slice, in mask words
@@ -88,12 +89,18 @@ struct Sell {
   double *coef = nullptr;        // n_slots: w_ik c(|xi_ik|) V_i V_k (0 on padding)
   int32_t *slice_layer = nullptr; // link region: smallest h with a row within h horizons of a constraint
   float *coef32 = nullptr;       // mixed form: coef / m_i in single precision
+  // full layout only: index and coefficient of each slot interleaved for the
+  // bond pass, one load per slot (FP64: 3 dwords {col, coef}; mixed: 2 dwords
+  // {col, coef32})
+  uint32_t *slots = nullptr;
 };
 
-// Lanes per row: enough wavefronts to cover the chip several times over.
-inline int pick_lanes(int64_t rows) {
+// Lanes per row: enough wavefronts to cover the chip, with as few lanes per row
+// as that allows (fewer partial sums to combine); 3D rows are four times longer.
+inline int pick_lanes(int64_t rows, int dim = 2) {
+  const int64_t target = dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000;
   int L = 1;
-  while (L < 8 && rows * L < ((int64_t)1 << 19)) L *= 2;
+  while (L < 8 && rows * L < target) L *= 2;
   return L;
 }
 
@@ -116,9 +123,12 @@ struct Solver {
   double *x = nullptr;           // SoA dim*N
   float *xf = nullptr;           // SoA dim*N, positions minus the PD box origin (mixed)
   double *alpha = nullptr, *mass = nullptr, *P = nullptr;
-  double *u[2] = {nullptr, nullptr};
+  // Node records [x (dim), u (dim)] (AoS, one 16-byte-aligned record per node):
+  // the bond pass gathers a neighbour's position and displacement with
+  // 16-byte loads.  Double-buffered predicted displacement; x never changes.
+  double *xu[2] = {nullptr, nullptr};
   double *v = nullptr, *a = nullptr;
-  int cur = 0;                   // u[cur] = current displacement, u[cur^1] = predicted next
+  int cur = 0;                   // xu[cur]: current displacement, xu[cur^1]: predicted next
   int32_t *rp = nullptr;         // canonical CSR, N+1
   int32_t *csr_col = nullptr;    // nnz
   int64_t nnz = 0;
@@ -191,6 +201,8 @@ struct Solver {
 
   bool verbose = false;
   int force_lanes = 0;             // lanes per row of the full-lattice bond layout (0: pick_lanes)
+  bool tiled = true;               // full layout rows in spatial tile order
+  int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
   double t_create0 = 0.0;
 
   // profiling
@@ -215,6 +227,7 @@ void build_neighbors(Solver &s);
 void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full, int L);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 void sell_coefficients(Solver &s, Sell &out);
+void sell_pack_slots(Solver &s, Sell &out);
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
 // PD kernels (pd.hip)
 void pd_setup(Solver &s);

@@ -76,7 +76,7 @@ __global__ void k_sell_fill(const int32_t *rows, int64_t n_rows, int64_t n_slice
 __global__ void k_sell_mask(const int32_t *rows, int64_t n_rows, int64_t n_slices, const int32_t *rp,
                             const int32_t *csr_col, int L, const int32_t *width, const int64_t *word_off,
                             uint64_t *mask, const double *x, int64_t N, int dim, Cracks cr,
-                            const uint64_t *src_mask, const int64_t *src_word_off, int src_L) {
+                            const uint64_t *src_mask, const int64_t *src_word_off, int src_L, const int32_t *src_row_of) {
   int64_t s = blockIdx.y;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_slices || t >= width[s] / L) return;
@@ -92,7 +92,7 @@ __global__ void k_sell_mask(const int32_t *rows, int64_t n_rows, int64_t n_slice
     if (k >= len) continue;
     bool intact;
     if (src_mask) {
-      intact = full_bit(src_word_off, src_mask, src_L, i, k);
+      intact = full_bit(src_word_off, src_mask, src_L, src_row_of ? src_row_of[i] : i, k);
     } else {
       int64_t c = csr_col[rp[i] + k];
       intact = !(dim == 2 && crosses_crack(x, N, i, c, cr));
@@ -139,20 +139,22 @@ __global__ void k_sell_coef(const int32_t *rows, int64_t n_rows, int64_t n_slice
 }
 
 __global__ void k_mask_to_csr(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask, int L,
-                              uint8_t *out) {
+                              const int32_t *row_of, uint8_t *out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   int len = rp[i + 1] - rp[i];
-  for (int k = 0; k < len; k++) out[rp[i] + k] = (uint8_t)full_bit(word_off, mask, L, i, k);
+  const int64_t r = row_of ? row_of[i] : i;
+  for (int k = 0; k < len; k++) out[rp[i] + k] = (uint8_t)full_bit(word_off, mask, L, r, k);
 }
 
 __global__ void k_damage(int64_t N, const int32_t *rp, const int64_t *word_off, const uint64_t *mask, int L,
-                         double *phi) {
+                         const int32_t *row_of, double *phi) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   int len = rp[i + 1] - rp[i];
+  const int64_t r = row_of ? row_of[i] : i;
   int cnt = 0;
-  for (int k = 0; k < len; k++) cnt += (int)full_bit(word_off, mask, L, i, k);
+  for (int k = 0; k < len; k++) cnt += (int)full_bit(word_off, mask, L, r, k);
   phi[i] = len > 0 ? 1.0 - (double)cnt / (double)len : 0.0;  // Eq. 5, uniform nodal volumes
 }
 
@@ -215,7 +217,8 @@ void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, con
     if (maxt > 0) {
       dim3 grid((unsigned)((maxt + 63) / 64), (unsigned)ns);
       k_sell_mask<<<grid, 64, 0, st>>>(out.rows, out.n_rows, ns, s.rp, s.csr_col, L, out.width, out.word_off,
-                                       out.mask, s.x, s.N, s.dim, cr, src_mask_full, s.sell.word_off, s.sell.L);
+                                       out.mask, s.x, s.N, s.dim, cr, src_mask_full, s.sell.word_off, s.sell.L,
+                                       s.sell.row_of);
       MTS_LAUNCH_CHECK();
     }
   }
@@ -234,7 +237,7 @@ void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full) {
   dim3 grid((unsigned)((maxt + 63) / 64), (unsigned)out.n_slices);
   k_sell_mask<<<grid, 64, 0, s.stream>>>(out.rows, out.n_rows, out.n_slices, s.rp, s.csr_col, out.L, out.width,
                                           out.word_off, out.mask, s.x, s.N, s.dim, cr, src_mask_full,
-                                          s.sell.word_off, s.sell.L);
+                                          s.sell.word_off, s.sell.L, s.sell.row_of);
   MTS_LAUNCH_CHECK();
 }
 
@@ -256,14 +259,41 @@ void sell_coefficients(Solver &s, Sell &out) {
   MTS_LAUNCH_CHECK();
 }
 
+namespace {
+__global__ void k_pack_slots(int64_t n, const int32_t *col, const double *coef, const float *coef32,
+                             uint32_t *slots) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (coef32) {
+    slots[2 * p] = (uint32_t)col[p];
+    slots[2 * p + 1] = __float_as_uint(coef32[p]);
+  } else {
+    const uint64_t b = (uint64_t)__double_as_longlong(coef[p]);
+    slots[3 * p] = (uint32_t)col[p];
+    slots[3 * p + 1] = (uint32_t)b;
+    slots[3 * p + 2] = (uint32_t)(b >> 32);
+  }
+}
+}  // namespace
+
+void sell_pack_slots(Solver &s, Sell &out) {
+  const bool mixed = s.precision == MTS_MIXED;
+  const int64_t n = out.n_slots + kSpareIters * WAVE;
+  if (!out.slots) out.slots = s.arena.alloc<uint32_t>((size_t)n * (mixed ? 2 : 3));
+  k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, out.col, out.coef, mixed ? out.coef32 : nullptr,
+                                                          out.slots);
+  MTS_LAUNCH_CHECK();
+}
+
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out) {
   k_mask_to_csr<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, s.sell.L,
-                                                            dev_out);
+                                                            s.sell.row_of, dev_out);
   MTS_LAUNCH_CHECK();
 }
 
 void pd_damage(Solver &s) {
-  k_damage<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, s.sell.L, s.damage);
+  k_damage<<<blocks_for(s.N), kThreads, 0, s.stream>>>(s.N, s.rp, s.sell.word_off, s.sell.mask, s.sell.L,
+                                                       s.sell.row_of, s.damage);
   MTS_LAUNCH_CHECK();
 }
 

@@ -233,9 +233,43 @@ void build_neighbors(Solver &s) {
                   (void *)items, (void *)rowlen, (void *)rp64})
     ar.release(q);
 
+  // Rows of the bond layout in spatial tile order (32 x 8 nodes in 2D,
+  // 8 x 8 x 4 in 3D, ascending id inside a tile): a workgroup's rows and
+  // their neighbours then form a compact patch, which keeps the neighbour
+  // gathers of consecutive workgroups in the same L2.
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
-  build_sell(s, s.sell, rows, nullptr, s.force_lanes ? s.force_lanes : pick_lanes(N));
+  if (s.tiled && s.p.dx > 0.0) {
+    double lo[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; a++) {
+      lo[a] = s.pos[a];
+      for (int64_t i = 0; i < N; i++) lo[a] = std::min(lo[a], s.pos[(size_t)i * dim + a]);
+    }
+    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {8.0, 8.0, 4.0};
+    const double *ext = dim == 2 ? ext2 : ext3;
+    std::vector<int64_t> key(N);
+    int64_t nt[3] = {1, 1, 1};
+    std::vector<int64_t> tc((size_t)N * 3);
+    for (int64_t i = 0; i < N; i++)
+      for (int a = 0; a < dim; a++) {
+        const int64_t t = (int64_t)std::floor((s.pos[(size_t)i * dim + a] - lo[a]) / (ext[a] * s.p.dx));
+        tc[(size_t)i * 3 + a] = std::max<int64_t>(t, 0);
+        nt[a] = std::max(nt[a], tc[(size_t)i * 3 + a] + 1);
+      }
+    for (int64_t i = 0; i < N; i++)
+      key[i] = (tc[(size_t)i * 3 + 2] * nt[1] + tc[(size_t)i * 3 + 1]) * nt[0] + tc[(size_t)i * 3 + 0];
+    std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    std::vector<int32_t> row_of(N);
+    for (int64_t r = 0; r < N; r++) row_of[rows[r]] = (int32_t)r;
+    s.sell.row_of = ar.alloc<int32_t>(N);
+    MTS_HIP(hipMemcpyAsync(s.sell.row_of, row_of.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
+  build_sell(s, s.sell, rows, nullptr, s.force_lanes ? s.force_lanes : pick_lanes(N, dim));
+  // the bond pass addresses its arrays with 32-bit byte offsets
+  const uint64_t lim = (uint64_t)1 << 32;
+  if ((uint64_t)(s.sell.n_slots + (int64_t)kSpareIters * WAVE) * 8 >= lim || (uint64_t)N * 2 * dim * 8 >= lim)
+    throw ArgError{"problem too large for one solver (bond or node arrays beyond 4 GiB)"};
 }
 
 }  // namespace mts

@@ -46,29 +46,29 @@ __global__ void k_init_accel(int64_t N, int dim, const double *Pf, const double 
   for (int d = 0; d < dim; d++) a[d * N + i] = (Pf ? Pf[d * N + i] : 0.0) / mass[i];
 }
 
-__global__ void k_predict(int64_t N, int dim, double dt, double hdt2, const double *u, const double *v,
-                          const double *a, double *up) {
+// predicted displacement (u part of the next node records)
+__global__ void k_predict(int64_t N, int dim, double dt, double hdt2, const double *xu, const double *v,
+                          const double *a, double *xu_next) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   for (int d = 0; d < dim; d++) {
-    int64_t t = d * N + i;
-    up[t] = (u[t] + dt * v[t]) + hdt2 * a[t];
+    int64_t t = d * N + i, q = i * 2 * dim + dim + d;
+    xu_next[q] = (xu[q] + dt * v[t]) + hdt2 * a[t];
   }
 }
 
 struct SubstepArgs {
   const double *x;
+  const int32_t *rows;  // row -> node (rows in spatial tile order)
   int64_t N, n_slices;
   int T;
   const int32_t *width;
   const int64_t *slot_off, *word_off;
-  const int32_t *col;
-  const double *coef;
-  const float *coef32;
+  const uint32_t *slots;  // interleaved {col, coef} per slot
   uint64_t *mask;
   const double *mass, *P;
-  const double *u_in;   // u_j (predicted)
-  double *u_out;        // u_{j+1} predicted
+  const double *xu_in;  // node records [x, u_j (predicted)]
+  double *xu_out;       // node records, u part <- u_{j+1} predicted
   double *v, *a;
   const int32_t *cidx;
   const double *lam0;
@@ -90,7 +90,15 @@ struct SubstepEntry {
 // take every L-th slot of its family, their partial sums are combined by a
 // fixed butterfly (deterministic, no atomics).  Bond states of one iteration of
 // the slice form one 64-bit word owned by the wavefront.
-template <int DIM, int L, bool MX>
+// Load through a uniform base pointer and a 32-bit byte offset (global loads
+// with a scalar base: one address register per lane).  Offsets stay below 2^32
+// for every array of a solver (checked when the layout is built).
+template <class T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <int DIM, int L, bool MX, int TM, bool PIPE>
 __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
   // formed in FP64; the accumulated value is the acceleration (coefficient
@@ -99,26 +107,40 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t N = A.N;
+  const uint32_t N8 = (uint32_t)N * 8u;  // byte stride of one component
   const int jl = lane / L, l = lane % L;
-  const int64_t i = slice * S + jl;
-  const bool valid = i < N;
-  const int64_t ii = valid ? i : 0;
+  const int64_t row = slice * S + jl;
+  const bool valid = row < N;
+  const int64_t i = valid ? A.rows[row] : 0;
+  const uint32_t i8 = (uint32_t)i * 8u;
   const int T = A.T;
-  const int64_t wo = slice * T, so = wo * WAVE;
+  const int64_t wo = slice * T;
+  const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;  // slot index of (iteration 0, this lane)
+  constexpr uint32_t RB = 16u * DIM;  // bytes of one node record
   double xi_[DIM], ui_[DIM];
-  for (int d = 0; d < DIM; d++) {
-    xi_[d] = A.x[d * N + ii];
-    ui_[d] = A.u_in[d * N + ii];
+  {
+    double rec[2 * DIM];
+#pragma unroll
+    for (int h = 0; h < DIM; h++) {
+      const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), (uint32_t)i * RB + 16u * h);
+      rec[2 * h] = v2.x;
+      rec[2 * h + 1] = v2.y;
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      xi_[d] = rec[d];
+      ui_[d] = rec[DIM + d];
+    }
   }
   // node data of the corrector, fetched up front so it shares the first round trip
   double v_o[DIM], a_o[DIM], p_o[DIM];
   for (int d = 0; d < DIM; d++) {
-    v_o[d] = A.v[d * N + ii];
-    a_o[d] = A.a[d * N + ii];
-    p_o[d] = A.P ? A.P[d * N + ii] : 0.0;
+    v_o[d] = ld32(A.v, i8 + d * N8);
+    a_o[d] = ld32(A.a, i8 + d * N8);
+    p_o[d] = A.P ? ld32(A.P, i8 + d * N8) : 0.0;
   }
-  const int32_t q_i = A.cidx ? A.cidx[ii] : -1;
-  const double m_i = A.mass[ii];
+  const int32_t q_i = A.cidx ? ld32(A.cidx, (uint32_t)i * 4u) : -1;
+  const double m_i = ld32(A.mass, i8);
   R F[DIM];
   for (int d = 0; d < DIM; d++) F[d] = R(0);
   int n_intact = 0;
@@ -126,57 +148,58 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   // Chunks of TM iterations: every load of a chunk is issued before any of its
   // results is used (state words, indices and coefficients first, then the
   // neighbour gathers), so a wavefront waits on two memory round trips per
-  // chunk instead of three per slot.
-  // Software pipeline over chunks of TM iterations: the state words, indices
-  // and coefficients of chunk t0 + TM are requested right after the neighbour
+  // chunk instead of three per slot.  With PIPE the state words, indices and
+  // coefficients of chunk t0 + TM are requested right after the neighbour
   // gathers of chunk t0, so the slot stream stays in flight while chunk t0 is
   // gathered and evaluated.  The slot arrays carry kSpareIters (>= TM) spare
   // iterations past the last slice, so every such load is in bounds; slots past
   // T are masked out.
-  constexpr int TM = 4;
   static_assert(kSpareIters >= TM, "spare iterations must cover one chunk");
   uint64_t word[TM];
-  int64_t c[TM];
+  uint32_t c8[TM];  // neighbour record byte offset
   R cf[TM];
+  auto load_slots = [&](int t, uint64_t *w, uint32_t *cc, R *ff) {
 #pragma unroll
-  for (int q = 0; q < TM; q++) {
-    const int64_t pos = so + (int64_t)q * WAVE + lane;
-    word[q] = A.mask[wo + q];
-    c[q] = A.col[pos];
-    if constexpr (MX) cf[q] = A.coef32[pos];
-    else cf[q] = A.coef[pos];
-  }
+    for (int q = 0; q < TM; q++) {
+      const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
+      w[q] = A.mask[wo + t + q];
+      if constexpr (MX) {
+        const uint2 v = ld32(reinterpret_cast<const uint2 *>(A.slots), pos * 8u);
+        cc[q] = v.x * RB;
+        ff[q] = __uint_as_float(v.y);
+      } else {
+        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);
+        cc[q] = v.x * RB;
+        ff[q] = __longlong_as_double((long long)(((uint64_t)v.z << 32) | v.y));
+      }
+    }
+  };
+  load_slots(0, word, c8, cf);
   for (int t0 = 0; t0 < T; t0 += TM) {
+    if (!PIPE && t0 > 0) load_slots(t0, word, c8, cf);
 #pragma unroll
     for (int q = 0; q < TM; q++)
       if (t0 + q >= T) word[q] = 0ull;
     double xk[TM][DIM], uk[TM][DIM];
 #pragma unroll
-    for (int q = 0; q < TM; q++)
+    for (int q = 0; q < TM; q++) {
+      double rec[2 * DIM];
+#pragma unroll
+      for (int h = 0; h < DIM; h++) {
+        const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), c8[q] + 16u * h);
+        rec[2 * h] = v2.x;
+        rec[2 * h + 1] = v2.y;
+      }
+#pragma unroll
       for (int d = 0; d < DIM; d++) {
-        xk[q][d] = A.x[d * N + c[q]];
-        uk[q][d] = A.u_in[d * N + c[q]];
-      }
-    uint64_t wnext[TM];
-    int64_t cnext[TM];
-    R fnext[TM];
-    if (t0 + TM < T) {  // wave-uniform
-#pragma unroll
-      for (int q = 0; q < TM; q++) {
-        const int64_t pos = so + (int64_t)(t0 + TM + q) * WAVE + lane;
-        wnext[q] = A.mask[wo + t0 + TM + q];
-        cnext[q] = A.col[pos];
-        if constexpr (MX) fnext[q] = A.coef32[pos];
-        else fnext[q] = A.coef[pos];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < TM; q++) {
-        wnext[q] = 0ull;
-        cnext[q] = 0;
-        fnext[q] = R(0);
+        xk[q][d] = rec[d];
+        uk[q][d] = rec[DIM + d];
       }
     }
+    uint64_t wnext[TM];
+    uint32_t cnext[TM];
+    R fnext[TM];
+    if (PIPE && t0 + TM < T) load_slots(t0 + TM, wnext, cnext, fnext);  // wave-uniform
 #pragma unroll
     for (int q = 0; q < TM; q++) {
       bool bit = (word[q] >> lane) & 1ull;
@@ -241,11 +264,13 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
         if (nw != word[q] && lane == 0) A.mask[wo + t0 + q] = nw;
       }
     }
+    if (PIPE) {
 #pragma unroll
-    for (int q = 0; q < TM; q++) {
-      word[q] = wnext[q];
-      c[q] = cnext[q];
-      cf[q] = fnext[q];
+      for (int q = 0; q < TM; q++) {
+        word[q] = wnext[q];
+        c8[q] = cnext[q];
+        cf[q] = fnext[q];
+      }
     }
   }
   for (int off = L / 2; off >= 1; off >>= 1) {
@@ -272,7 +297,7 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
     const double vn = v_o[d] + P.hdtP * (a_o[d] + an);
     A.a[tix] = an;
     A.v[tix] = vn;
-    A.u_out[tix] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
+    A.xu_out[(int64_t)i * 2 * DIM + DIM + d] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
   }
   if (A.damage && l == 0) {
     const int fam = A.rp[i + 1] - A.rp[i];
@@ -282,12 +307,12 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
 
 // One solver: slice = renumbered workgroup * 4 + wavefront (wave-uniform, so
 // offsets and state words come through scalar loads).
-template <int DIM, int L, bool MX>
+template <int DIM, int L, bool MX, int TM, bool PIPE>
 __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) {
   const int64_t slice = __builtin_amdgcn_readfirstlane(
       (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;  // uniform per wavefront
-  substep_body<DIM, L, MX>(A, P, slice);
+  substep_body<DIM, L, MX, TM, PIPE>(A, P, slice);
 }
 
 // Several solvers in one launch: workgroup b (after renumbering) belongs to
@@ -301,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep_batch(const SubstepEntry 
   const int64_t slice = __builtin_amdgcn_readfirstlane(
       (int)((b - tab[r].first_block) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;
-  substep_body<DIM, L, MX>(A, P, slice);
+  substep_body<DIM, L, MX, 4, true>(A, P, slice);
 }
 
 // Link problem (Eq. 48b / eq. unit): linear, no breaking, bond states of the
@@ -451,22 +476,23 @@ __global__ void k_zero_region(int64_t n_rows, const int32_t *rows, int64_t N, in
     }
 }
 
-// U = V + W on the link region, then the predictor for the next substep.
+// U = V + W on the link region, then the predictor for the next substep
+// (displacements in the u part of the node records).
 __global__ void k_add_link(int64_t n_rows, const int32_t *rows, int64_t N, int dim, double dt, double hdt2,
-                           const double *Wu, const double *Wv, const double *Wa, double *u, double *v, double *a,
-                           double *u_pred) {
+                           const double *Wu, const double *Wv, const double *Wa, double *xu, double *v, double *a,
+                           double *xu_pred) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_rows) return;
   int64_t i = rows[r];
   for (int d = 0; d < dim; d++) {
-    int64_t t = d * N + i;
-    double un = u[t] + Wu[t];
+    int64_t t = d * N + i, q = i * 2 * dim + dim + d;
+    double un = xu[q] + Wu[t];
     double vn = v[t] + Wv[t];
     double an = a[t] + Wa[t];
-    u[t] = un;
+    xu[q] = un;
     v[t] = vn;
     a[t] = an;
-    u_pred[t] = (un + dt * vn) + hdt2 * an;
+    xu_pred[q] = (un + dt * vn) + hdt2 * an;
   }
 }
 
@@ -487,11 +513,12 @@ void pd_setup(Solver &s) {
   k_init_accel<<<nblk(N), 256, 0, st>>>(N, s.dim, s.P, s.mass, s.a);
   MTS_LAUNCH_CHECK();
   sell_coefficients(s, s.sell);
+  sell_pack_slots(s, s.sell);
 }
 
 void pd_predict_all(Solver &s) {
-  k_predict<<<nblk(s.N), 256, 0, s.stream>>>(s.N, s.dim, s.prm.dtP, s.prm.hdt2P, s.u[s.cur], s.v, s.a,
-                                             s.u[s.cur ^ 1]);
+  k_predict<<<nblk(s.N), 256, 0, s.stream>>>(s.N, s.dim, s.prm.dtP, s.prm.hdt2P, s.xu[s.cur], s.v, s.a,
+                                             s.xu[s.cur ^ 1]);
   MTS_LAUNCH_CHECK();
 }
 
@@ -500,20 +527,19 @@ void pd_predict_all(Solver &s) {
 static SubstepArgs substep_args(Solver &s, int j, int cur) {
   SubstepArgs A{};
   A.x = s.x;
+  A.rows = s.sell.rows;
   A.N = s.N;
   A.n_slices = s.sell.n_slices;
   A.T = s.sell.T;
   A.width = s.sell.width;
   A.slot_off = s.sell.slot_off;
   A.word_off = s.sell.word_off;
-  A.col = s.sell.col;
-  A.coef = s.sell.coef;
-  A.coef32 = s.sell.coef32;
+  A.slots = s.sell.slots;
   A.mask = s.sell.mask;
   A.mass = s.mass;
   A.P = s.P;
-  A.u_in = s.u[cur ^ 1];
-  A.u_out = s.u[cur];
+  A.xu_in = s.xu[cur ^ 1];
+  A.xu_out = s.xu[cur];
   A.v = s.v;
   A.a = s.a;
   A.cidx = s.nc ? s.cidx : nullptr;
@@ -545,9 +571,20 @@ void pd_substep(Solver &s, int j) {
   const SubstepArgs A = substep_args(s, j, s.cur);
   const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   const int L = s.sell.L;
-#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
-  MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB);
+  switch (s.pd_variant) {
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+    case 1: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
 #undef MTS_SUB
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 2, true><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+    case 2: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
+#undef MTS_SUB
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 2, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+    case 3: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
+#undef MTS_SUB
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4, true><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+    default: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
+#undef MTS_SUB
+  }
   MTS_LAUNCH_CHECK();
   s.cur ^= 1;
   s.pd_steps++;
@@ -643,8 +680,8 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
 void link_add(Solver &s, const double *Wu, const double *Wv, const double *Wa) {
   if (!s.rsell.n_rows) return;
   k_add_link<<<nblk(s.rsell.n_rows), 256, 0, s.stream>>>(s.rsell.n_rows, s.rsell.rows, s.N, s.dim, s.prm.dtP,
-                                                         s.prm.hdt2P, Wu, Wv, Wa, s.u[s.cur], s.v, s.a,
-                                                         s.u[s.cur ^ 1]);
+                                                         s.prm.hdt2P, Wu, Wv, Wa, s.xu[s.cur], s.v, s.a,
+                                                         s.xu[s.cur ^ 1]);
   MTS_LAUNCH_CHECK();
 }
 

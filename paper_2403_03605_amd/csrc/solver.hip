@@ -191,6 +191,8 @@ void set_error(const char *fmt, ...) {
 void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   validate(pin);
   s->verbose = std::getenv("MTS_VERBOSE") != nullptr;
+  if (const char *t = std::getenv("MTS_TILE")) s->tiled = std::atoi(t) != 0;  // tuning: tile-ordered rows
+  if (const char *t = std::getenv("MTS_PD_VARIANT")) s->pd_variant = std::atoi(t);  // tuning: loop shape
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
     const int L = std::atoi(e);
@@ -220,12 +222,20 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   }
   s->alpha = ar.alloc<double>(N);
   s->mass = ar.alloc<double>(N);
-  s->u[0] = ar.alloc<double>((size_t)dim * N);
-  s->u[1] = ar.alloc<double>((size_t)dim * N);
+  s->xu[0] = ar.alloc<double>((size_t)2 * dim * N);
+  s->xu[1] = ar.alloc<double>((size_t)2 * dim * N);
+  {
+    std::vector<double> rec((size_t)2 * dim * N, 0.0);
+    for (int64_t i = 0; i < N; i++)
+      for (int d = 0; d < dim; d++) rec[(size_t)i * 2 * dim + d] = s->pos[(size_t)i * dim + d];
+    for (double *q : s->xu)
+      MTS_HIP(hipMemcpyAsync(q, rec.data(), sizeof(double) * rec.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
   s->v = ar.alloc<double>((size_t)dim * N);
   s->a = ar.alloc<double>((size_t)dim * N);
   s->damage = ar.alloc<double>(N);
-  for (double *q : {s->u[0], s->u[1], s->v, s->a}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * dim * N, st));
+  for (double *q : {s->v, s->a}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * dim * N, st));
   MTS_HIP(hipMemsetAsync(s->damage, 0, sizeof(double) * N, st));
   s->region_flag = ar.alloc<int32_t>(1);
   MTS_HIP(hipMemsetAsync(s->region_flag, 0, sizeof(int32_t), st));
@@ -276,6 +286,19 @@ __global__ void k_aos_to_soa(const double *src, double *dst, int64_t N, int dim)
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   for (int d = 0; d < dim; d++) dst[(int64_t)d * N + i] = src[i * dim + d];
+}
+
+// displacement part of the node records <-> node-major vectors
+__global__ void k_xu_to_aos(const double *xu, double *dst, int64_t N, int dim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < dim; d++) dst[i * dim + d] = xu[i * 2 * dim + dim + d];
+}
+
+__global__ void k_aos_to_xu(const double *src, double *xu, int64_t N, int dim) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < dim; d++) xu[i * 2 * dim + dim + d] = src[i * dim + d];
 }
 
 __global__ void k_nonfinite(const double *a, int64_t n, int32_t *flag) {
@@ -509,9 +532,13 @@ mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t 
     double *tmp = nullptr;
     switch (what) {
       case MTS_PD_U: case MTS_PD_V: case MTS_PD_A: {
-        const double *soa = what == MTS_PD_U ? s.u[s.cur] : (what == MTS_PD_V ? s.v : s.a);
         tmp = s.arena.alloc<double>(sz);
-        k_soa_to_aos<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(soa, tmp, s.N, s.dim);
+        if (what == MTS_PD_U) {
+          k_xu_to_aos<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(s.xu[s.cur], tmp, s.N, s.dim);
+        } else {
+          const double *soa = what == MTS_PD_V ? s.v : s.a;
+          k_soa_to_aos<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(soa, tmp, s.N, s.dim);
+        }
         MTS_LAUNCH_CHECK();
         src = tmp;
         break;
@@ -552,8 +579,12 @@ mts_status mts_write(mts_solver *h, int32_t what, const double *in, int64_t n) {
       if (n != s.N * s.dim) throw ArgError{"size mismatch"};
       double *tmp = s.arena.alloc<double>(n);
       MTS_HIP(hipMemcpyAsync(tmp, in, sizeof(double) * n, hipMemcpyHostToDevice, st));
-      double *dst = what == MTS_PD_U ? s.u[s.cur] : (what == MTS_PD_V ? s.v : s.a);
-      k_aos_to_soa<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(tmp, dst, s.N, s.dim);
+      if (what == MTS_PD_U) {
+        k_aos_to_xu<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(tmp, s.xu[s.cur], s.N, s.dim);
+      } else {
+        double *dst = what == MTS_PD_V ? s.v : s.a;
+        k_aos_to_soa<<<(unsigned)((s.N + 255) / 256), 256, 0, st>>>(tmp, dst, s.N, s.dim);
+      }
       MTS_LAUNCH_CHECK();
       pd_predict_all(s);
       MTS_HIP(hipStreamSynchronize(st));
