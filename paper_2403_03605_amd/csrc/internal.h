@@ -201,7 +201,7 @@ struct Solver {
 
   bool verbose = false;
   int force_lanes = 0;             // lanes per row of the full-lattice bond layout (0: pick_lanes)
-  bool tiled = true;               // full layout rows in spatial tile order
+  bool tiled = false;              // full layout rows in spatial tile order (measured no faster)
   int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
   double t_create0 = 0.0;
 
