@@ -2,14 +2,15 @@
 // admitted against a device-memory budget and advanced together.
 //
 // Every pool step is one macro step (Algorithm 1) of every active request:
-//  phase A  FE free steps (per request), the PD substeps of all requests as
+//  phase A  FE free steps (per request, on side streams), the PD substeps of all requests as
 //           one batched launch per substep index j (requests sorted by step
 //           ratio m, so substep j covers a prefix of them), then each coupled
 //           request saves its bond states and takes its rebuild flag;
 //  host     the rebuild checks of the previous pool step are resolved (the
 //           same one-step-behind pipeline as a single solver, so results are
 //           identical to running the request alone);
-//  phase B  multiplier solves and final updates (per request).
+//  phase B  multiplier solves and final updates (per request, spread over
+//           four side streams forked from and joined into the pool stream).
 // While the set of active requests is unchanged, phases A and B are replayed
 // from HIP graphs, one per phase and parity of the pool step (every per-step
 // alternation of a request -- displacement buffer, state snapshot slot -- has
@@ -94,6 +95,10 @@ struct mts_pool {
   bool dirty = true;
   int stable = 0;
   hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [phase][parity]
+  // per-request work (FE steps, multiplier solves) spread over side streams
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev[2] = {}, join_ev[2][kSide] = {};
   hipEvent_t ev_a[2] = {nullptr, nullptr};
   int64_t ticks = 0, captures = 0, replays = 0;
 };
@@ -170,10 +175,36 @@ void rebuild_tables(mts_pool *P) {
 
 inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Run fn(solver) for every running request, request k on side stream k % kSide,
+// between a fork from and a join into the pool stream (recorded in a capture
+// too, where it becomes parallel graph branches).
+template <class Fn>
+void on_side_streams(mts_pool *P, int phase, Fn fn) {
+  MTS_HIP(hipEventRecord(P->fork_ev[phase], P->stream));
+  for (auto st : P->side) MTS_HIP(hipStreamWaitEvent(st, P->fork_ev[phase], 0));
+  size_t k = 0;
+  for (Req *r : P->active) {
+    Solver &s = *r->s;
+    s.stream = P->side[k++ % mts_pool::kSide];
+    try {
+      fn(s);
+    } catch (...) {
+      s.stream = P->stream;
+      throw;
+    }
+    s.stream = P->stream;
+  }
+  for (int q = 0; q < mts_pool::kSide; q++) {
+    MTS_HIP(hipEventRecord(P->join_ev[phase][q], P->side[q]));
+    MTS_HIP(hipStreamWaitEvent(P->stream, P->join_ev[phase][q], 0));
+  }
+}
+
 void enqueue_phase_a(mts_pool *P, int par) {
   const size_t n = P->active.size();
-  for (Req *r : P->active)
-    if (r->s->p.mode == MTS_COUPLED) fe_free_step(*r->s);
+  on_side_streams(P, 0, [](Solver &s) {
+    if (s.p.mode == MTS_COUPLED) fe_free_step(s);
+  });
   const size_t esz = substep_entry_size();
   for (int j = 1; j <= P->max_m; j++) {
     const void *tab = static_cast<const unsigned char *>(P->tab[par]) + esz * (size_t)(j - 1) * n;
@@ -192,8 +223,9 @@ void enqueue_phase_a(mts_pool *P, int par) {
 }
 
 void enqueue_phase_b(mts_pool *P) {
-  for (Req *r : P->active)
-    if (r->s->p.mode == MTS_COUPLED) coupling_solve_and_correct(*r->s);
+  on_side_streams(P, 1, [](Solver &s) {
+    if (s.p.mode == MTS_COUPLED) coupling_solve_and_correct(s);
+  });
 }
 
 // Capture one phase into a graph.  No request is constructed on another thread
@@ -352,6 +384,10 @@ mts_status mts_pool_create(int64_t budget_bytes, int32_t max_slots, int32_t dim,
     }
     MTS_HIP(hipStreamCreateWithFlags(&P->read_st, hipStreamNonBlocking));
     for (auto &e : P->ev_a) MTS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &st : P->side) MTS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (auto &e : P->fork_ev) MTS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &ph : P->join_ev)
+      for (auto &e : ph) MTS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     *out = P;
     return MTS_OK;
   } catch (...) {
@@ -516,6 +552,16 @@ void mts_pool_destroy(mts_pool *P) {
   if (P->blk_req) (void)hipFree(P->blk_req);
   for (auto &e : P->ev_a)
     if (e) (void)hipEventDestroy(e);
+  for (auto &st : P->side)
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (auto &e : P->fork_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &ph : P->join_ev)
+    for (auto &e : ph)
+      if (e) (void)hipEventDestroy(e);
   if (P->own_stream) (void)hipStreamDestroy(P->stream);
   if (P->read_st) (void)hipStreamDestroy(P->read_st);
   delete P;

@@ -75,3 +75,38 @@ def test_plan_and_validation_on_host():
     h = C.c_void_p()
     assert lib.mts_create(None, None, C.byref(h)) == _lib.EINVAL
     assert h.value is None
+
+
+def _create_status(inst):
+    lib = _lib.load()
+    p, _pos = _lib.make_problem(inst)
+    h = C.c_void_p()
+    st = lib.mts_create(C.byref(p), None, C.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("bad", [
+    dict(m=0), dict(dt_pd=0.0), dict(horizon_factor=0.5), dict(dim=1),
+    dict(pos=np.zeros((0, 2))),                      # empty lattice
+])
+def test_create_rejects_bad_descriptions_before_device_use(bad):
+    """Degenerate or inconsistent descriptions are rejected with MTS_EINVAL by
+    host-side validation (no device call happens, so this runs on the CPU)."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    inst = dict(mi.config(0), **bad)
+    st, h = _create_status(inst)
+    assert st == _lib.EINVAL and not h
+    assert len(_lib.load().mts_last_error()) > 0
+
+
+def test_pool_rejects_bad_arguments_on_host():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    lib = _lib.load()
+    h = C.c_void_p()
+    for args in ((0, 4, 2, 1), (1 << 20, 0, 2, 1), (1 << 20, 4, 5, 1), (1 << 20, 4, 2, 7)):
+        assert lib.mts_pool_create(args[0], args[1], args[2], args[3], 1, None, C.byref(h)) == _lib.EINVAL
+        assert not h.value
+    lib.mts_pool_destroy(None)
+    assert lib.mts_pool_step(None, None, None, 0, None) == _lib.EINVAL

@@ -214,3 +214,53 @@ def test_breaking_states_3d(mts):
     diff = int((mug != muo).sum())
     print("3D broken", nb, "differing", diff)
     assert nb > 0 and diff <= max(2, nb // 100)
+
+
+@pytest.mark.parametrize("weight,kernel", [("linear", "pmb"), ("constant", "pmb"), ("cubic", "exp")])
+def test_coupled_weight_and_kernel_options(mts, weight, kernel):
+    """Linear and constant Arlequin weights and the exponential micromodulus
+    (Sec. 3.1-3.2 options): coupled trajectory within 1e-10 of the oracle
+    before the first break."""
+    inst = mi.plate2d(40, 4, 80, 4e-8, perturb=1e-6, seed=51, weight=weight, kernel=kernel,
+                      name=f"plate40 {weight} {kernel}")
+    s, o, worst = _run_pair(mts, inst, inst["n_macro"], 1e-10, check_every=4)
+    print(weight, kernel, "worst", worst)
+    assert np.abs(o.get(O.PD_U)).max() > 0
+
+
+def test_single_rate_coupling(mts):
+    """m = 1 (single-rate coupling, the limit the paper's MTS reduces to)."""
+    inst = mi.plate2d(40, 1, 40, 2e-8, perturb=1e-6, seed=52, name="plate40 m=1")
+    s, o, worst = _run_pair(mts, inst, inst["n_macro"], 1e-10, check_every=5)
+    print("m=1 worst", worst)
+
+
+def test_tiny_and_ragged_lattices(mts):
+    """Degenerate sizes: a lattice smaller than one wavefront slice and one whose
+    row count leaves a ragged last slice, in both precisions (pure PD)."""
+    for nx, prec in ((10, "fp64"), (10, "mixed"), (30, "fp64")):
+        inst = mi.plate2d(nx, 1, 20, 1e-7, perturb=1e-6, seed=53, mode="pure_pd", traction=1e6,
+                          precision=prec, name=f"pure{nx} {prec}")
+        print("case", inst["name"], inst["pos"].shape, flush=True)
+        s = mts.Solver(inst)
+        o = Oracle(inst)
+        s.advance(20)
+        o.advance(20)
+        assert o.info()["n_broken"] == 0
+        rp, col, mu = s.bonds()
+        rpo, colo, muo = o.bonds()
+        assert np.array_equal(col, colo) and np.array_equal(mu, muo)
+        g, w = s.read(mts.PD_U), o.get(O.PD_U)
+        if prec == "fp64":
+            assert _rel(g, w) <= 1e-10
+        else:
+            assert _rel_l2(g, w) <= 1e-4
+        s.close()
+
+
+def test_crack_off_node_line_rejected(mts):
+    inst = mi.config(0)
+    inst["cracks"] = [(0.0201, 0.0, 0.05)]
+    with pytest.raises(mts.MtsError) as e:
+        mts.Solver(inst)
+    assert e.value.status == 1  # MTS_EINVAL
