@@ -93,6 +93,11 @@ struct Sell {
   // bond pass, one load per slot (FP64: 3 dwords {col, coef}; mixed: 2 dwords
   // {col, coef32})
   uint32_t *slots = nullptr;
+  // Neighbour staging (2D full layout): workgroup w (4 slices) first copies
+  // the node records halo_ids[halo_off[w] .. halo_off[w + 1]) into LDS, and the
+  // index field of its slot records holds the position in that list.
+  int32_t *halo_off = nullptr, *halo_ids = nullptr;
+  int32_t halo_max = 0;  // 0: no staging
 };
 
 // Lanes per row: enough wavefronts to cover the chip, with as few lanes per row
@@ -201,8 +206,10 @@ struct Solver {
 
   bool verbose = false;
   int force_lanes = 0;             // lanes per row of the full-lattice bond layout (0: pick_lanes)
-  bool tiled = false;              // full layout rows in spatial tile order (measured no faster)
+  int tiled = -1;                  // full layout rows in spatial tile order (-1: in 2D only, where
+                                   // it shrinks the staged neighbour lists; it measured slower in 3D)
   int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
+  bool halo = true;                // stage neighbour records in LDS (2D) when they fit
   double t_create0 = 0.0;
 
   // profiling
@@ -227,7 +234,8 @@ void build_neighbors(Solver &s);
 void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full, int L);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 void sell_coefficients(Solver &s, Sell &out);
-void sell_pack_slots(Solver &s, Sell &out);
+void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col = nullptr);
+void sell_build_halo(Solver &s, Sell &out);
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
 // PD kernels (pd.hip)
 void pd_setup(Solver &s);

@@ -276,13 +276,62 @@ __global__ void k_pack_slots(int64_t n, const int32_t *col, const double *coef, 
 }
 }  // namespace
 
-void sell_pack_slots(Solver &s, Sell &out) {
+void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col) {
   const bool mixed = s.precision == MTS_MIXED;
   const int64_t n = out.n_slots + kSpareIters * WAVE;
   if (!out.slots) out.slots = s.arena.alloc<uint32_t>((size_t)n * (mixed ? 2 : 3));
-  k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, out.col, out.coef, mixed ? out.coef32 : nullptr,
-                                                          out.slots);
+  k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, dev_col ? dev_col : out.col, out.coef,
+                                                          mixed ? out.coef32 : nullptr, out.slots);
   MTS_LAUNCH_CHECK();
+}
+
+// Per-workgroup neighbour lists for LDS staging (host side, integer work only).
+// Workgroup w runs slices 4w .. 4w + 3; its list is the sorted set of every
+// node its slots name (padding slots name node 0).  Staging is used only when
+// every list fits kHaloMax records.
+void sell_build_halo(Solver &s, Sell &out) {
+  constexpr int kHaloMax = 2048;
+  out.halo_max = 0;
+  if (!out.n_slices) return;
+  hipStream_t st = s.stream;
+  const int64_t n = out.n_slots + kSpareIters * WAVE;
+  std::vector<int32_t> col(n);
+  MTS_HIP(hipMemcpyAsync(col.data(), out.col, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  const int64_t per_slice = (int64_t)out.T * WAVE;
+  const int64_t nwg = (out.n_slices + 3) / 4;
+  std::vector<int32_t> off(nwg + 1, 0), ids, pos_of(s.N, -1), local(n, 0);
+  std::vector<int64_t> stamp(s.N, -1);
+  std::vector<int32_t> set;
+  int hmax = 0;
+  for (int64_t w = 0; w < nwg; w++) {
+    const int64_t a = w * 4 * per_slice, b = std::min<int64_t>((w + 1) * 4 * per_slice, out.n_slots);
+    set.clear();
+    for (int64_t q = a; q < b; q++) {
+      const int32_t c = col[q];
+      if (stamp[c] != w) {
+        stamp[c] = w;
+        set.push_back(c);
+      }
+    }
+    std::sort(set.begin(), set.end());
+    hmax = std::max(hmax, (int)set.size());
+    if (hmax > kHaloMax) return;  // too spread out: gather from global memory instead
+    for (size_t h = 0; h < set.size(); h++) pos_of[set[h]] = (int32_t)h;
+    for (int64_t q = a; q < b; q++) local[q] = pos_of[col[q]];
+    ids.insert(ids.end(), set.begin(), set.end());
+    off[w + 1] = (int32_t)ids.size();
+  }
+  out.halo_off = s.arena.alloc<int32_t>(nwg + 1);
+  out.halo_ids = s.arena.alloc<int32_t>(std::max<size_t>(ids.size(), 1));
+  int32_t *dlocal = s.arena.alloc<int32_t>(n);
+  MTS_HIP(hipMemcpyAsync(out.halo_off, off.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(out.halo_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(dlocal, local.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  sell_pack_slots(s, out, dlocal);
+  MTS_HIP(hipStreamSynchronize(st));
+  s.arena.release(dlocal);
+  out.halo_max = hmax;
 }
 
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out) {

@@ -239,7 +239,7 @@ void build_neighbors(Solver &s) {
   // gathers of consecutive workgroups in the same L2.
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
-  if (s.tiled && s.p.dx > 0.0) {
+  if ((s.tiled < 0 ? dim == 2 : s.tiled != 0) && s.p.dx > 0.0) {
     double lo[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < dim; a++) {
       lo[a] = s.pos[a];

@@ -64,7 +64,8 @@ struct SubstepArgs {
   int T;
   const int32_t *width;
   const int64_t *slot_off, *word_off;
-  const uint32_t *slots;  // interleaved {col, coef} per slot
+  const uint32_t *slots;  // interleaved {col, coef} per slot (col: LDS list position when staged)
+  const int32_t *halo_off, *halo_ids;  // per-workgroup staged neighbour lists (or nullptr)
   uint64_t *mask;
   const double *mass, *P;
   const double *xu_in;  // node records [x, u_j (predicted)]
@@ -98,8 +99,9 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-template <int DIM, int L, bool MX, int TM, bool PIPE>
-__device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice) {
+template <int DIM, int L, bool MX, int TM, bool PIPE, bool HALO = false>
+__device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice,
+                                             const double2 *lds = nullptr) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
   // formed in FP64; the accumulated value is the acceleration (coefficient
   // pre-divided by the node mass).  Integration stays FP64.
@@ -186,7 +188,9 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
       double rec[2 * DIM];
 #pragma unroll
       for (int h = 0; h < DIM; h++) {
-        const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), c8[q] + 16u * h);
+        double2 v2;
+        if constexpr (HALO) v2 = lds[c8[q] / 16u + h];  // staged record
+        else v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), c8[q] + 16u * h);
         rec[2 * h] = v2.x;
         rec[2 * h + 1] = v2.y;
       }
@@ -313,6 +317,30 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) 
       (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;  // uniform per wavefront
   substep_body<DIM, L, MX, TM, PIPE>(A, P, slice);
+}
+
+// Copy workgroup wg's neighbour records into LDS (all threads; a barrier follows).
+template <int DIM>
+__device__ __forceinline__ void stage_halo(const SubstepArgs &A, int64_t wg, double2 *lds) {
+  const int h0 = A.halo_off[wg], nh = A.halo_off[wg + 1] - h0;
+  const double2 *src = reinterpret_cast<const double2 *>(A.xu_in);
+  for (int h = threadIdx.x; h < nh; h += kBlock) {
+    const uint32_t rb = (uint32_t)A.halo_ids[h0 + h] * (16u * DIM);
+#pragma unroll
+    for (int q = 0; q < DIM; q++) lds[h * DIM + q] = ld32(src, rb + 16u * q);
+  }
+}
+
+// One solver, neighbour records staged in LDS per workgroup (2D).
+template <int DIM, int L, bool MX>
+__global__ __launch_bounds__(kBlock) void k_pd_substep_halo(SubstepArgs A, Params P) {
+  extern __shared__ double2 lds[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  stage_halo<DIM>(A, b, lds);
+  __syncthreads();
+  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(b * (kBlock / WAVE) + (threadIdx.x >> 6)));
+  if (slice >= A.n_slices) return;  // after the barrier every wave of the group has staged
+  substep_body<DIM, L, MX, 4, true, true>(A, P, slice, lds);
 }
 
 // Several solvers in one launch: workgroup b (after renumbering) belongs to
@@ -514,6 +542,7 @@ void pd_setup(Solver &s) {
   MTS_LAUNCH_CHECK();
   sell_coefficients(s, s.sell);
   sell_pack_slots(s, s.sell);
+  if (s.halo && s.dim == 2) sell_build_halo(s, s.sell);
 }
 
 void pd_predict_all(Solver &s) {
@@ -535,6 +564,8 @@ static SubstepArgs substep_args(Solver &s, int j, int cur) {
   A.slot_off = s.sell.slot_off;
   A.word_off = s.sell.word_off;
   A.slots = s.sell.slots;
+  A.halo_off = s.sell.halo_max ? s.sell.halo_off : nullptr;
+  A.halo_ids = s.sell.halo_max ? s.sell.halo_ids : nullptr;
   A.mask = s.sell.mask;
   A.mass = s.mass;
   A.P = s.P;
@@ -571,6 +602,17 @@ void pd_substep(Solver &s, int j) {
   const SubstepArgs A = substep_args(s, j, s.cur);
   const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   const int L = s.sell.L;
+  if (s.sell.halo_max > 0 && s.dim == 2) {
+    const size_t shm = (size_t)s.sell.halo_max * 32;
+    const bool mx = s.precision == MTS_MIXED;
+#define MTS_SUBH(D, LL, MX) k_pd_substep_halo<D, LL, MX><<<grid, kBlock, shm, s.stream>>>(A, s.prm)
+    if (mx) { MTS_BY_LANES(L, MTS_SUBH, 2, true); } else { MTS_BY_LANES(L, MTS_SUBH, 2, false); }
+#undef MTS_SUBH
+    MTS_LAUNCH_CHECK();
+    s.cur ^= 1;
+    s.pd_steps++;
+    return;
+  }
   switch (s.pd_variant) {
 #define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
     case 1: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
@@ -607,6 +649,7 @@ void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const
                           int64_t nblocks, hipStream_t st) {
   if (nblocks <= 0) return;
   const SubstepEntry *tab = static_cast<const SubstepEntry *>(dev_tab);
+
 #define MTS_SUBB(D, LL, MX) k_pd_substep_batch<D, LL, MX><<<(unsigned)nblocks, kBlock, 0, st>>>(tab, dev_blk_req)
   MTS_BY_FORM(dim, mixed, L, MTS_SUBB);
 #undef MTS_SUBB

@@ -429,6 +429,8 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
     MTS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     r->s = new Solver();
     r->s->force_lanes = P->lanes;
+    r->s->halo = false;  // one batched kernel for every request: neighbour gathers from global memory
+    r->s->tiled = 0;
     create_impl(p, st, r->s);  // ends with a synchronisation of st
     r->s->stream = P->stream;
     MTS_HIP(hipStreamDestroy(st));

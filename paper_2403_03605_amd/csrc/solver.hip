@@ -191,8 +191,9 @@ void set_error(const char *fmt, ...) {
 void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   validate(pin);
   s->verbose = std::getenv("MTS_VERBOSE") != nullptr;
-  if (const char *t = std::getenv("MTS_TILE")) s->tiled = std::atoi(t) != 0;  // tuning: tile-ordered rows
+  if (const char *t = std::getenv("MTS_TILE")) s->tiled = std::atoi(t) != 0 ? 1 : 0;  // tuning: row order
   if (const char *t = std::getenv("MTS_PD_VARIANT")) s->pd_variant = std::atoi(t);  // tuning: loop shape
+  if (const char *t = std::getenv("MTS_HALO")) s->halo = std::atoi(t) != 0;          // tuning: LDS staging
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
     const int L = std::atoi(e);
