@@ -79,6 +79,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_03605_amd.build`")
+    try:  # torch (streams, device memory) brings the HIP runtime: load it first so there is one
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.POINTER
     lib.mts_plan.argtypes = [P(Problem), P(PlanInfo)]

@@ -18,10 +18,8 @@
 
 namespace mts {
 
-void link_zero(Solver &s, double *u0, double *u1, double *v, double *a, int nrhs);
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const double *lam,
-                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
-void link_add(Solver &s, const double *Wu, const double *Wv, const double *Wa);
+                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, bool add);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 
 namespace {
@@ -425,10 +423,9 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
       rc[b] = c < s.n_colors ? (int32_t)c : -1;
       rd[b] = b % dim;
     }
-    link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, s.nrhs);
-    int k = 0;
+    int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
     for (int j = 1; j <= s.m; j++) {
-      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, nullptr, s.ccolor, rc, rd, s.nrhs);
+      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, nullptr, s.ccolor, rc, rd, s.nrhs, false);
       k ^= 1;
     }
     MTS_HIP(hipMemcpyAsync(drc, rc, sizeof(rc), hipMemcpyHostToDevice, st));
@@ -438,8 +435,6 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     // the host arrays rc/rd are reused next iteration
     MTS_HIP(hipStreamSynchronize(st));
   }
-  // leave the W arrays zeroed for the per-step correction
-  link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, s.nrhs);
   dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
   k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
                                 s.p.fe_n[1], s.H);
@@ -460,21 +455,19 @@ void coupling_solve_and_correct(Solver &s) {
   s.prof_begin(MTS_KT_LAMBDA, &e0);
   k_rhs<<<nb(s.nc), 256, 0, st>>>(s.nc, s.dim, s.nen, s.cn, s.cel, s.conn, s.cw, s.vt, s.v, s.N, s.rhs);
   MTS_LAUNCH_CHECK();
-  sym_blocks_apply(s, s.rhs, s.lam);
+  sym_blocks_apply(s, s.rhs, s.lam, s.lam0);  // lambda_0 <- lambda_m for the next macro step too
   s.prof_end(MTS_KT_LAMBDA, e0);
   fe_correct(s);
   // PD: U = V + Y lambda_m by re-running the link problem with lambda_m
   hipEvent_t e1 = nullptr;
   s.prof_begin(MTS_KT_LINK, &e1);
-  link_zero(s, s.Wu[0], s.Wu[1], s.Wv, s.Wa, 1);
+  // m substeps from rest; the last one adds W_m into the PD state directly
   int k = 0;
   for (int j = 1; j <= s.m; j++) {
-    link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.lam, nullptr, nullptr, nullptr, 1);
+    link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.lam, nullptr, nullptr, nullptr, 1, j == s.m);
     k ^= 1;
   }
-  link_add(s, s.Wu[k ^ 1], s.Wv, s.Wa);
   s.prof_end(MTS_KT_LINK, e1);
-  MTS_HIP(hipMemcpyAsync(s.lam0, s.lam, sizeof(double) * s.nl, hipMemcpyDeviceToDevice, st));
 }
 
 }  // namespace mts

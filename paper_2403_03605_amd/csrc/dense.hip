@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const i
 __global__ __launch_bounds__(256) void k_sym_reduce(const int64_t *off, const int64_t *tile_base,
                                                     const int32_t *row_comp, const int32_t *row_block,
                                                     const int32_t *idx, const double *rowpart,
-                                                    const double *colpart, double *y) {
+                                                    const double *colpart, double *y, double *y2) {
   __shared__ double part[4][TS];
   const int64_t c = row_comp[blockIdx.x], I = row_block[blockIdx.x];
   const int64_t n = off[c + 1] - off[c], T = (n + TS - 1) / TS, tb = tile_base[c];
@@ -286,7 +286,10 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const int64_t *off, const in
   if (w == 0) {
     const int64_t i = I * TS + lane;
     const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-    if (i < n) y[idx[off[c] + i]] = tot;
+    if (i < n) {
+      y[idx[off[c] + i]] = tot;
+      if (y2) y2[idx[off[c] + i]] = tot;
+    }
   }
 }
 
@@ -379,14 +382,14 @@ void sym_blocks_build(Solver &s) {
   }
 }
 
-void sym_blocks_apply(Solver &s, const double *r, double *y) {
+void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   auto &B = s.sym;
   if (!B.n_tiles) return;
   k_sym_tiles<<<(unsigned)B.n_tiles, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.rowpart,
                                                          B.colpart);
   MTS_LAUNCH_CHECK();
   k_sym_reduce<<<(unsigned)B.n_rows, 256, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
-                                                        B.rowpart, B.colpart, y);
+                                                        B.rowpart, B.colpart, y, y2);
   MTS_LAUNCH_CHECK();
 }
 

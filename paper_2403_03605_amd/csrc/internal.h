@@ -259,13 +259,14 @@ void coupling_solve_and_correct(Solver &s);
 // dense linear algebra (dense.hip)
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
-void sym_blocks_apply(Solver &s, const double *r, double *y);
+void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2 = nullptr);
 // solver construction and helpers shared with the serving pool (solver.hip)
 void create_impl(const mts_problem *pin, void *stream, Solver *s);
 mts_status fail_from_exception();
 void set_error(const char *fmt, ...);
 void check_finite(Solver &s);
 void resolve_pending(Solver &s);
+void snapshot_states(Solver &s, int slot);
 mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n);
 void query_impl(Solver &s, mts_info *o);
 // progress log on stderr when MTS_VERBOSE is set

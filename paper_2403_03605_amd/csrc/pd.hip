@@ -380,6 +380,11 @@ struct LinkArgs {
   int32_t rhs_color[16];
   int32_t rhs_dir[16];
   double lfac;
+  int first;              // substep 1: the response starts from rest (inputs are exact zeros)
+  // last substep of the final update (one RHS): add W_m into the PD state
+  // (Eq. 50) and write the predictor, instead of storing W_m
+  int add;
+  double *Uxu, *Uxu_pred, *Uv, *Ua;
 };
 
 struct LinkEntry {
@@ -392,24 +397,38 @@ template <int DIM, int NRHS, bool kColor, int L>
 __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, const int64_t slice) {
   constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
-  if (A.slice_layer[slice] > A.jmax) return;  // uniform per wavefront
   const int jl = lane / L, l = lane % L;
   const int64_t r = slice * S + jl;
   const bool valid = r < A.n_rows;
   const int64_t N = A.N;
   const int64_t i = valid ? A.rows[r] : A.rows[0];
+  const int64_t stride = (int64_t)DIM * N;
+  if (A.slice_layer[slice] > A.jmax) {  // uniform per wavefront
+    // the response has not reached these rows yet: it is exactly zero
+    if (!valid) return;
+    for (int b = 0; b < NRHS; b++)
+      for (int d = 0; d < DIM; d++) {
+        if ((b * DIM + d) % L != l) continue;
+        const int64_t tix = b * stride + d * N + i;
+        A.u_out[tix] = 0.0;
+        if (A.first) {
+          A.v[tix] = 0.0;
+          A.a[tix] = 0.0;
+        }
+      }
+    return;
+  }
   const int T = A.T;
   const int64_t wo = slice * T, so = wo * WAVE;
-  const int64_t stride = (int64_t)DIM * N;
   double xi_[DIM], ui_[NRHS][DIM];
   for (int d = 0; d < DIM; d++) xi_[d] = A.x[d * N + i];
   for (int b = 0; b < NRHS; b++)
-    for (int d = 0; d < DIM; d++) ui_[b][d] = A.u_in[b * stride + d * N + i];
+    for (int d = 0; d < DIM; d++) ui_[b][d] = A.first ? 0.0 : A.u_in[b * stride + d * N + i];
   double F[NRHS][DIM];
   for (int b = 0; b < NRHS; b++)
     for (int d = 0; d < DIM; d++) F[b][d] = 0.0;
   constexpr int TM = NRHS == 1 ? 4 : 1;
-  for (int t0 = 0; t0 < T; t0 += TM) {
+  for (int t0 = 0; t0 < (A.first ? 0 : T); t0 += TM) {  // no bond forces from a response at rest
     bool bit[TM];
     int64_t c[TM];
     double cf[TM];
@@ -462,10 +481,25 @@ __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, co
         }
       }
       const double an = fl / m_i;
-      const double vn = A.v[tix] + P.hdtP * (A.a[tix] + an);
-      A.a[tix] = an;
-      A.v[tix] = vn;
-      A.u_out[tix] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
+      const double v0 = A.first ? 0.0 : A.v[tix], a0 = A.first ? 0.0 : A.a[tix];
+      const double vn = v0 + P.hdtP * (a0 + an);
+      const double un = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
+      if (!kColor && A.add) {
+        // U = V + W_m on this row (W_m's displacement is this substep's input,
+        // un the predictor beyond it), then the predictor for the next substep
+        const int64_t t = d * N + i, qx = i * 2 * DIM + DIM + d;
+        const double uu = A.Uxu[qx] + ui_[b][d];
+        const double vv = A.Uv[t] + vn;
+        const double aa = A.Ua[t] + an;
+        A.Uxu[qx] = uu;
+        A.Uv[t] = vv;
+        A.Ua[t] = aa;
+        A.Uxu_pred[qx] = (uu + P.dtP * vv) + P.hdt2P * aa;
+      } else {
+        A.a[tix] = an;
+        A.v[tix] = vn;
+        A.u_out[tix] = un;
+      }
     }
 }
 
@@ -489,40 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_link_substep_batch(const LinkEntry *
   link_body<DIM, 1, false, L>(A, P, slice);
 }
 
-__global__ void k_zero_region(int64_t n_rows, const int32_t *rows, int64_t N, int dim, int nrhs, double *u0,
-                              double *u1, double *v, double *a) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
-  int64_t i = rows[r];
-  for (int b = 0; b < nrhs; b++)
-    for (int d = 0; d < dim; d++) {
-      int64_t t = ((int64_t)b * dim + d) * N + i;
-      u0[t] = 0.0;
-      u1[t] = 0.0;
-      v[t] = 0.0;
-      a[t] = 0.0;
-    }
-}
 
-// U = V + W on the link region, then the predictor for the next substep
-// (displacements in the u part of the node records).
-__global__ void k_add_link(int64_t n_rows, const int32_t *rows, int64_t N, int dim, double dt, double hdt2,
-                           const double *Wu, const double *Wv, const double *Wa, double *xu, double *v, double *a,
-                           double *xu_pred) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
-  int64_t i = rows[r];
-  for (int d = 0; d < dim; d++) {
-    int64_t t = d * N + i, q = i * 2 * dim + dim + d;
-    double un = xu[q] + Wu[t];
-    double vn = v[t] + Wv[t];
-    double an = a[t] + Wa[t];
-    xu[q] = un;
-    v[t] = vn;
-    a[t] = an;
-    xu_pred[q] = (un + dt * vn) + hdt2 * an;
-  }
-}
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -657,12 +658,6 @@ void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const
 }
 
 // ---- link runs (used by coupling.hip) ----
-void link_zero(Solver &s, double *u0, double *u1, double *v, double *a, int nrhs) {
-  if (!s.rsell.n_rows) return;
-  k_zero_region<<<nblk(s.rsell.n_rows), 256, 0, s.stream>>>(s.rsell.n_rows, s.rsell.rows, s.N, s.dim, nrhs, u0, u1,
-                                                            v, a);
-  MTS_LAUNCH_CHECK();
-}
 
 template <int DIM, int NRHS, bool kColor>
 static void launch_link(Solver &s, LinkArgs &A) {
@@ -678,7 +673,7 @@ static void launch_link(Solver &s, LinkArgs &A) {
 
 // One link substep j over the region rows.  u_in/u_out/v/a: [nrhs][dim][N].
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const double *lam,
-                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs) {
+                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, bool add) {
   if (!s.rsell.n_rows) return;
   LinkArgs A{};
   A.x = s.x;
@@ -708,6 +703,14 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
     A.rhs_dir[b] = rhs_dir[b];
   }
   A.lfac = (double)j / (double)s.m;
+  A.first = j == 1 ? 1 : 0;
+  A.add = add ? 1 : 0;
+  if (add) {
+    A.Uxu = s.xu[s.cur];
+    A.Uxu_pred = s.xu[s.cur ^ 1];
+    A.Uv = s.v;
+    A.Ua = s.a;
+  }
   if (!ccolor) {
     if (s.dim == 2) launch_link<2, 1, false>(s, A);
     else launch_link<3, 1, false>(s, A);
@@ -720,12 +723,5 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
   }
 }
 
-void link_add(Solver &s, const double *Wu, const double *Wv, const double *Wa) {
-  if (!s.rsell.n_rows) return;
-  k_add_link<<<nblk(s.rsell.n_rows), 256, 0, s.stream>>>(s.rsell.n_rows, s.rsell.rows, s.N, s.dim, s.prm.dtP,
-                                                         s.prm.hdt2P, Wu, Wv, Wa, s.xu[s.cur], s.v, s.a,
-                                                         s.xu[s.cur ^ 1]);
-  MTS_LAUNCH_CHECK();
-}
 
 }  // namespace mts

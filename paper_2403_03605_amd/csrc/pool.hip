@@ -31,14 +31,7 @@
 namespace mts {
 namespace {
 
-__global__ void k_copy_words(const uint64_t *src, uint64_t *dst, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
 
-__global__ void k_clear_flag(int32_t *dev_flag) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) dev_flag[0] = 0;
-}
 
 struct Req {
   uint64_t id = 0;
@@ -173,8 +166,6 @@ void rebuild_tables(mts_pool *P) {
   P->stable = 0;
 }
 
-inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
-
 // Run fn(solver) for every running request, request k on side stream k % kSide,
 // between a fork from and a join into the pool stream (recorded in a capture
 // too, where it becomes parallel graph branches).
@@ -213,12 +204,7 @@ void enqueue_phase_a(mts_pool *P, int par) {
   for (Req *r : P->active) {
     if (!r->tracked) continue;
     Solver &s = *r->s;
-    const int slot = (int)(s.macro_steps & 1);
-    k_copy_words<<<nb(s.sell.n_words), 256, 0, P->stream>>>(s.sell.mask, s.mask_snap[slot], s.sell.n_words);
-    MTS_LAUNCH_CHECK();
-    MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
-    k_clear_flag<<<1, 64, 0, P->stream>>>(s.region_flag);  // a kernel, not a memset: graph-safe
-    MTS_LAUNCH_CHECK();
+    snapshot_states(s, (int)(s.macro_steps & 1));  // on s.stream == the pool stream
   }
 }
 

@@ -320,6 +320,23 @@ void check_finite(Solver &s) {
   if (h) s.unstable = true;
 }
 
+__global__ void k_snapshot(const uint64_t *mask, uint64_t *snap, int64_t n, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) snap[i] = mask[i];
+  if (i == 0) flag[0] = 0;
+}
+
+// Save the bond states of this macro step and move its rebuild flag to the
+// host (the copy is ordered before the kernel that clears the device flag; no
+// memset, so the sequence can be recorded into a graph).
+void snapshot_states(Solver &s, int slot) {
+  MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  const int64_t n = std::max<int64_t>(s.sell.n_words, 1);
+  k_snapshot<<<(unsigned)((n + 255) / 256), 256, 0, s.stream>>>(s.sell.mask, s.mask_snap[slot], s.sell.n_words,
+                                                               s.region_flag);
+  MTS_LAUNCH_CHECK();
+}
+
 // Algorithm 1, last step: the unit-load responses are rebuilt after a macro step
 // in which a bond inside their support broke.  The check for step k-1 is
 // resolved after step k's free problem has been enqueued (it does not use the
@@ -357,10 +374,7 @@ void advance_impl(Solver &s, int64_t n) {
     int slot = -1;
     if (track) {
       slot = (int)(s.macro_steps & 1);
-      MTS_HIP(hipMemcpyAsync(s.mask_snap[slot], s.sell.mask, sizeof(uint64_t) * s.sell.n_words,
-                             hipMemcpyDeviceToDevice, s.stream));
-      MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-      MTS_HIP(hipMemsetAsync(s.region_flag, 0, sizeof(int32_t), s.stream));
+      snapshot_states(s, slot);
       MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
     }
     resolve_pending(s);  // previous macro step's check
