@@ -93,7 +93,7 @@ struct Sell {
   // bond pass, one load per slot (FP64: 3 dwords {col, coef}; mixed: 2 dwords
   // {col, coef32})
   uint32_t *slots = nullptr;
-  // Neighbour staging (2D full layout): workgroup w (4 slices) first copies
+  // Neighbour staging (full layout): workgroup w (4 slices) first copies
   // the node records halo_ids[halo_off[w] .. halo_off[w + 1]) into LDS, and the
   // index field of its slot records holds the position in that list.
   int32_t *halo_off = nullptr, *halo_ids = nullptr;
@@ -206,10 +206,10 @@ struct Solver {
 
   bool verbose = false;
   int force_lanes = 0;             // lanes per row of the full-lattice bond layout (0: pick_lanes)
-  int tiled = -1;                  // full layout rows in spatial tile order (-1: in 2D only, where
-                                   // it shrinks the staged neighbour lists; it measured slower in 3D)
+  int tiled = 1;                   // full layout rows in spatial tile order (shrinks the staged
+                                   // neighbour lists of a workgroup)
   int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
-  bool halo = true;                // stage neighbour records in LDS (2D) when they fit
+  bool halo = true;                // stage neighbour records in LDS when they fit
   double t_create0 = 0.0;
 
   // profiling

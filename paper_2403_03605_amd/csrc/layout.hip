@@ -288,9 +288,9 @@ void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col) {
 // Per-workgroup neighbour lists for LDS staging (host side, integer work only).
 // Workgroup w runs slices 4w .. 4w + 3; its list is the sorted set of every
 // node its slots name (padding slots name node 0).  Staging is used only when
-// every list fits kHaloMax records.
+// every list fits 64 KiB of LDS.
 void sell_build_halo(Solver &s, Sell &out) {
-  constexpr int kHaloMax = 2048;
+  const int kHaloMax = 65536 / (16 * s.dim);  // records that fit 64 KiB of LDS
   out.halo_max = 0;
   if (!out.n_slices) return;
   hipStream_t st = s.stream;

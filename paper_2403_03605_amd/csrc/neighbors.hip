@@ -239,13 +239,14 @@ void build_neighbors(Solver &s) {
   // gathers of consecutive workgroups in the same L2.
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
-  if ((s.tiled < 0 ? dim == 2 : s.tiled != 0) && s.p.dx > 0.0) {
+  if (s.tiled != 0 && s.p.dx > 0.0) {
     double lo[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < dim; a++) {
       lo[a] = s.pos[a];
       for (int64_t i = 0; i < N; i++) lo[a] = std::min(lo[a], s.pos[(size_t)i * dim + a]);
     }
-    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {8.0, 8.0, 4.0};
+    // 3D tiles of 4 x 4 x 4 = 64 nodes: one workgroup at 4 lanes per row
+    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {4.0, 4.0, 4.0};
     const double *ext = dim == 2 ? ext2 : ext3;
     std::vector<int64_t> key(N);
     int64_t nt[3] = {1, 1, 1};
@@ -265,7 +266,11 @@ void build_neighbors(Solver &s) {
     MTS_HIP(hipMemcpyAsync(s.sell.row_of, row_of.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
     MTS_HIP(hipStreamSynchronize(st));
   }
-  build_sell(s, s.sell, rows, nullptr, s.force_lanes ? s.force_lanes : pick_lanes(N, dim));
+  // In 3D a workgroup at 4 lanes per row covers one 4 x 4 x 4 tile, whose
+  // staged neighbour records fit LDS.
+  int L = s.force_lanes ? s.force_lanes : pick_lanes(N, dim);
+  if (!s.force_lanes && dim == 3 && s.halo && s.tiled != 0) L = std::max(L, 4);
+  build_sell(s, s.sell, rows, nullptr, L);
   // the bond pass addresses its arrays with 32-bit byte offsets
   const uint64_t lim = (uint64_t)1 << 32;
   if ((uint64_t)(s.sell.n_slots + (int64_t)kSpareIters * WAVE) * 8 >= lim || (uint64_t)N * 2 * dim * 8 >= lim)

@@ -331,7 +331,7 @@ __device__ __forceinline__ void stage_halo(const SubstepArgs &A, int64_t wg, dou
   }
 }
 
-// One solver, neighbour records staged in LDS per workgroup (2D).
+// One solver, neighbour records staged in LDS per workgroup.
 template <int DIM, int L, bool MX>
 __global__ __launch_bounds__(kBlock) void k_pd_substep_halo(SubstepArgs A, Params P) {
   extern __shared__ double2 lds[];
@@ -543,7 +543,7 @@ void pd_setup(Solver &s) {
   MTS_LAUNCH_CHECK();
   sell_coefficients(s, s.sell);
   sell_pack_slots(s, s.sell);
-  if (s.halo && s.dim == 2) sell_build_halo(s, s.sell);
+  if (s.halo) sell_build_halo(s, s.sell);
 }
 
 void pd_predict_all(Solver &s) {
@@ -603,11 +603,10 @@ void pd_substep(Solver &s, int j) {
   const SubstepArgs A = substep_args(s, j, s.cur);
   const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   const int L = s.sell.L;
-  if (s.sell.halo_max > 0 && s.dim == 2) {
-    const size_t shm = (size_t)s.sell.halo_max * 32;
-    const bool mx = s.precision == MTS_MIXED;
+  if (s.sell.halo_max > 0) {
+    const size_t shm = (size_t)s.sell.halo_max * 16 * s.dim;
 #define MTS_SUBH(D, LL, MX) k_pd_substep_halo<D, LL, MX><<<grid, kBlock, shm, s.stream>>>(A, s.prm)
-    if (mx) { MTS_BY_LANES(L, MTS_SUBH, 2, true); } else { MTS_BY_LANES(L, MTS_SUBH, 2, false); }
+    MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUBH);
 #undef MTS_SUBH
     MTS_LAUNCH_CHECK();
     s.cur ^= 1;
