@@ -248,7 +248,7 @@ void coupling_setup(Solver &s) {
   for (int64_t i = 0; i < N; i++)
     if (reg[i]) rrows.push_back((int32_t)i);
   s.n_region = (int64_t)rrows.size();
-  build_sell(s, s.rsell, rrows, s.sell.mask, pick_lanes(s.n_region, s.dim));
+  build_sell(s, s.rsell, rrows, s.sell.mask, pick_lanes(s.n_region, s.dim, s.dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000));
   sell_coefficients(s, s.rsell);
   s.rsell.slice_layer = ar.alloc<int32_t>(s.rsell.n_slices);
   if (s.rsell.n_slices) {

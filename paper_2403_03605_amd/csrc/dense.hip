@@ -267,25 +267,28 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const i
 }
 
 // y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I).  One
-// workgroup per block row; wave w takes every 4th contribution and the four
+// workgroup per block row; wave w takes every kRedWaves-th contribution and the
 // wave sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_sym_reduce(const int64_t *off, const int64_t *tile_base,
-                                                    const int32_t *row_comp, const int32_t *row_block,
-                                                    const int32_t *idx, const double *rowpart,
-                                                    const double *colpart, double *y, double *y2) {
-  __shared__ double part[4][TS];
+constexpr int kRedWaves = 16;  // wavefronts per block row in the reduction
+
+__global__ __launch_bounds__(kRedWaves * 64) void k_sym_reduce(const int64_t *off, const int64_t *tile_base,
+                                                              const int32_t *row_comp, const int32_t *row_block,
+                                                              const int32_t *idx, const double *rowpart,
+                                                              const double *colpart, double *y, double *y2) {
+  __shared__ double part[kRedWaves][TS];
   const int64_t c = row_comp[blockIdx.x], I = row_block[blockIdx.x];
   const int64_t n = off[c + 1] - off[c], T = (n + TS - 1) / TS, tb = tile_base[c];
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
   double s = 0.0;
-  for (int64_t k = w; k < T; k += 4) {
+  for (int64_t k = w; k < T; k += kRedWaves) {
     s += k <= I ? rowpart[(tb + I * (I + 1) / 2 + k) * TS + lane] : colpart[(tb + k * (k + 1) / 2 + I) * TS + lane];
   }
   part[w][lane] = s;
   __syncthreads();
   if (w == 0) {
     const int64_t i = I * TS + lane;
-    const double tot = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    double tot = part[0][lane];
+    for (int q = 1; q < kRedWaves; q++) tot += part[q][lane];  // fixed order
     if (i < n) {
       y[idx[off[c] + i]] = tot;
       if (y2) y2[idx[off[c] + i]] = tot;
@@ -388,7 +391,7 @@ void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   k_sym_tiles<<<(unsigned)B.n_tiles, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.rowpart,
                                                          B.colpart);
   MTS_LAUNCH_CHECK();
-  k_sym_reduce<<<(unsigned)B.n_rows, 256, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
+  k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
                                                         B.rowpart, B.colpart, y, y2);
   MTS_LAUNCH_CHECK();
 }

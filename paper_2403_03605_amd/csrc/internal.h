@@ -102,8 +102,9 @@ struct Sell {
 
 // Lanes per row: enough wavefronts to cover the chip, with as few lanes per row
 // as that allows (fewer partial sums to combine); 3D rows are four times longer.
-inline int pick_lanes(int64_t rows, int dim = 2) {
-  const int64_t target = dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000;
+// `target` is the number of lanes of work to reach (0: the bond-pass default).
+inline int pick_lanes(int64_t rows, int dim = 2, int64_t target = 0) {
+  if (target <= 0) target = dim == 3 ? ((int64_t)1 << 18) : (int64_t)250000;
   int L = 1;
   while (L < 8 && rows * L < target) L *= 2;
   return L;
