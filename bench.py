@@ -96,7 +96,7 @@ def serve_main(args, torch, mts, log):
     m in {4, 8, 10}, mixed precision) with Poisson arrivals at 20 per second,
     admitted by device-memory budget and advanced together in the pool."""
     from paper_2403_03605_amd.serving import serve, stream_requests
-    reqs = stream_requests(args.serve_requests)
+    reqs = stream_requests(args.serve_requests, rate=args.serve_rate)
     free, _total = torch.cuda.mem_get_info()
     budget = int(args.serve_budget_gib * (1 << 30)) if args.serve_budget_gib > 0 else int(0.9 * free)
     log(f"serving {len(reqs)} requests, budget {budget / 2**30:.1f} GiB")
@@ -110,7 +110,8 @@ def serve_main(args, torch, mts, log):
         "value": out["p99_s"], "unit": "s", "n_gpus": 1, "steps": out["pool_steps"], "warmup": 0,
         "ms_per_step": out["span_s"] * 1e3 / max(out["pool_steps"], 1), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 bond math / f64 integration", "data": "synthetic",
-        "config": {"workload": f"serving stream: {len(reqs)} plate solves, Poisson 20/s, 10 us of physical time each",
+        "config": {"workload": f"serving stream: {len(reqs)} plate solves, Poisson {args.serve_rate:g}/s, "
+                               "10 us of physical time each",
                    "budget_bytes": budget, "graphs": not args.serve_no_graphs,
                    "builders": args.serve_builders},
         "serving": {k: v for k, v in out.items() if k != "latencies_s"},
@@ -135,6 +136,7 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="run the serving stream (Poisson arrivals of plate solves) through the pool instead")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0, help="pool budget (0: 90%% of free HBM)")
     ap.add_argument("--serve-no-graphs", action="store_true")
     ap.add_argument("--serve-builders", type=int, default=4, help="threads that build arrived requests")

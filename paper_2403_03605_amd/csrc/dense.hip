@@ -197,18 +197,27 @@ __global__ __launch_bounds__(256) void k_sweep_update(double *packed, int64_t k,
     a[2 * q] = -v.x;
     a[2 * q + 1] = -v.y;
   }
+  // two halves of the 16 reduction steps; inside a half the four accumulator
+  // chains are interleaved so consecutive MFMAs are independent
 #pragma unroll
-  for (int t = 0; t < 4; t++) {
-    const double2 *vrow = reinterpret_cast<const double2 *>(V + J * TS * TS + (16 * t + lr) * TS + 16 * lk);
-    double b[16];
+  for (int hh = 0; hh < 2; hh++) {
+    double b[4][8];
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const double2 v = vrow[q];
-      b[2 * q] = v.x;
-      b[2 * q + 1] = v.y;
+    for (int t = 0; t < 4; t++) {
+      const double2 *vrow =
+          reinterpret_cast<const double2 *>(V + J * TS * TS + (16 * t + lr) * TS + 16 * lk + 8 * hh);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const double2 v = vrow[q];
+        b[t][2 * q] = v.x;
+        b[t][2 * q + 1] = v.y;
+      }
     }
 #pragma unroll
-    for (int s2 = 0; s2 < 16; s2++) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], b[s2], acc[t], 0, 0, 0);
+    for (int s2 = 0; s2 < 8; s2++)
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 * hh + s2], b[t][s2], acc[t], 0, 0, 0);
   }
 #pragma unroll
   for (int t = 0; t < 4; t++)
