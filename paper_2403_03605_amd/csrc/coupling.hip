@@ -18,8 +18,10 @@
 
 namespace mts {
 
-void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const double *lam,
-                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, bool add);
+void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
+                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
+void link_records_init(Solver &s);
+void link_final_substep(Solver &s, int j, int k, bool add);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 
 namespace {
@@ -248,8 +250,10 @@ void coupling_setup(Solver &s) {
   for (int64_t i = 0; i < N; i++)
     if (reg[i]) rrows.push_back((int32_t)i);
   s.n_region = (int64_t)rrows.size();
-  build_sell(s, s.rsell, rrows, s.sell.mask, pick_lanes(s.n_region, s.dim, s.dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000));
+  build_sell(s, s.rsell, rrows, s.sell.mask,
+             s.region_lanes ? s.region_lanes : pick_lanes(s.n_region, s.dim, s.dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000));
   sell_coefficients(s, s.rsell);
+  sell_pack_slots(s, s.rsell, nullptr, true);  // the final update runs in FP64 in both forms
   s.rsell.slice_layer = ar.alloc<int32_t>(s.rsell.n_slices);
   if (s.rsell.n_slices) {
     k_slice_layer<<<nb(s.rsell.n_slices), 256, 0, st>>>(s.rsell.rows, s.rsell.n_rows, s.rsell.n_slices, s.rsell.L,
@@ -332,6 +336,8 @@ void coupling_setup(Solver &s) {
   s.Wv = ar.alloc<double>(wsz);
   s.Wa = ar.alloc<double>(wsz);
   for (double *q : {s.Wu[0], s.Wu[1], s.Wv, s.Wa}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
+  for (int k = 0; k < 2; k++) s.Wxu[k] = ar.alloc<double>((size_t)2 * dim * N);
+  link_records_init(s);
   s.lam = ar.alloc<double>(s.nl);
   s.lam0 = ar.alloc<double>(s.nl);
   s.rhs = ar.alloc<double>(s.nl);
@@ -425,7 +431,7 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     }
     int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
     for (int j = 1; j <= s.m; j++) {
-      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, nullptr, s.ccolor, rc, rd, s.nrhs, false);
+      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.ccolor, rc, rd, s.nrhs);
       k ^= 1;
     }
     MTS_HIP(hipMemcpyAsync(drc, rc, sizeof(rc), hipMemcpyHostToDevice, st));
@@ -450,6 +456,11 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
 }
 
 void coupling_solve_and_correct(Solver &s) {
+  coupling_lambda(s);
+  coupling_link(s);
+}
+
+void coupling_lambda(Solver &s) {
   hipStream_t st = s.stream;
   hipEvent_t e0 = nullptr;
   s.prof_begin(MTS_KT_LAMBDA, &e0);
@@ -458,13 +469,16 @@ void coupling_solve_and_correct(Solver &s) {
   sym_blocks_apply(s, s.rhs, s.lam, s.lam0);  // lambda_0 <- lambda_m for the next macro step too
   s.prof_end(MTS_KT_LAMBDA, e0);
   fe_correct(s);
+}
+
+void coupling_link(Solver &s) {
   // PD: U = V + Y lambda_m by re-running the link problem with lambda_m
   hipEvent_t e1 = nullptr;
   s.prof_begin(MTS_KT_LINK, &e1);
   // m substeps from rest; the last one adds W_m into the PD state directly
   int k = 0;
   for (int j = 1; j <= s.m; j++) {
-    link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.lam, nullptr, nullptr, nullptr, 1, j == s.m);
+    link_final_substep(s, j, k, j == s.m);
     k ^= 1;
   }
   s.prof_end(MTS_KT_LINK, e1);

@@ -54,7 +54,7 @@ struct DeviceArena {
 };
 
 constexpr int WAVE = 64;
-constexpr int kSpareIters = 4;  // zero iterations appended to every sliced-ELL array
+constexpr int kSpareIters = 16;  // zero iterations appended to every sliced-ELL array
 
 // Scalars of one problem, passed by value to kernels.
 struct Params {
@@ -93,11 +93,15 @@ struct Sell {
   // bond pass, one load per slot (FP64: 3 dwords {col, coef}; mixed: 2 dwords
   // {col, coef32})
   uint32_t *slots = nullptr;
-  // Neighbour staging (full layout): workgroup w (4 slices) first copies
-  // the node records halo_ids[halo_off[w] .. halo_off[w + 1]) into LDS, and the
-  // index field of its slot records holds the position in that list.
-  int32_t *halo_off = nullptr, *halo_ids = nullptr;
+  // Neighbour staging (full layout): workgroup w runs slices
+  // wg_start[w] .. wg_start[w + 1] - 1 (at most wg_waves, one spatial tile),
+  // first copies the node records halo_ids[halo_off[w] .. halo_off[w + 1])
+  // into LDS, and the offset field of its slot records points into that list.
+  int32_t *halo_off = nullptr, *halo_ids = nullptr, *wg_start = nullptr;
+  int64_t n_wg = 0;
   int32_t halo_max = 0;  // 0: no staging
+  int32_t wg_waves = 4;  // at most this many slices (wavefronts) per workgroup of the staged pass
+  std::vector<int64_t> h_tile;  // host: spatial tile of each row (empty: rows not tiled)
 };
 
 // Lanes per row: enough wavefronts to cover the chip, with as few lanes per row
@@ -191,6 +195,7 @@ struct Solver {
   int64_t n_region = 0;
   Sell rsell;                    // link region rows
   double *Wu[2] = {nullptr, nullptr};
+  double *Wxu[2] = {nullptr, nullptr};  // final-update response: node records [x, w], double-buffered
   double *Wv = nullptr, *Wa = nullptr; // dim*N (zero outside the region)
   int64_t n_colors = 0;
   int32_t *ccolor = nullptr;     // colour of each constraint
@@ -211,6 +216,8 @@ struct Solver {
                                    // neighbour lists of a workgroup)
   int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
   bool halo = true;                // stage neighbour records in LDS when they fit
+  int region_lanes = 0;            // lanes per row of the link region layout (0: automatic)
+  int halo_waves = 0;              // wavefronts per workgroup of the staged pass (0: 8 for 3D mixed, else 4)
   double t_create0 = 0.0;
 
   // profiling
@@ -235,7 +242,7 @@ void build_neighbors(Solver &s);
 void build_sell(Solver &s, Sell &out, const std::vector<int32_t> &rows_host, const uint64_t *src_mask_full, int L);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 void sell_coefficients(Solver &s, Sell &out);
-void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col = nullptr);
+void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col = nullptr, bool fp64 = false);
 void sell_build_halo(Solver &s, Sell &out);
 void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
 // PD kernels (pd.hip)
@@ -257,6 +264,8 @@ void fe_correct(Solver &s);
 void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);
 void coupling_solve_and_correct(Solver &s);
+void coupling_lambda(Solver &s);  // lambda_m and the FE correction
+void coupling_link(Solver &s);    // the PD correction (link re-run)
 // dense linear algebra (dense.hip)
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);

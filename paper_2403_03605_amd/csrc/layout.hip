@@ -260,37 +260,50 @@ void sell_coefficients(Solver &s, Sell &out) {
 }
 
 namespace {
-__global__ void k_pack_slots(int64_t n, const int32_t *col, const double *coef, const float *coef32,
+// Slot records {byte offset of the neighbour's node record, coefficient}
+// (FP64: coefficient first, then the offset); the
+// offset is col * rb (rb = bytes of one record), in the record array or, when
+// the records are staged, in the workgroup's LDS list.
+__global__ void k_pack_slots(int64_t n, const int32_t *col, uint32_t rb, const double *coef, const float *coef32,
                              uint32_t *slots) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
+  const uint32_t off = (uint32_t)col[p] * rb;
   if (coef32) {
-    slots[2 * p] = (uint32_t)col[p];
+    slots[2 * p] = off;
     slots[2 * p + 1] = __float_as_uint(coef32[p]);
   } else {
+    // coefficient first: it lands in an aligned register pair when loaded
     const uint64_t b = (uint64_t)__double_as_longlong(coef[p]);
-    slots[3 * p] = (uint32_t)col[p];
-    slots[3 * p + 1] = (uint32_t)b;
-    slots[3 * p + 2] = (uint32_t)(b >> 32);
+    slots[3 * p] = (uint32_t)b;
+    slots[3 * p + 1] = (uint32_t)(b >> 32);
+    slots[3 * p + 2] = off;
   }
 }
 }  // namespace
 
-void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col) {
-  const bool mixed = s.precision == MTS_MIXED;
+void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col, bool fp64) {
+  const bool mixed = !fp64 && s.precision == MTS_MIXED;
   const int64_t n = out.n_slots + kSpareIters * WAVE;
   if (!out.slots) out.slots = s.arena.alloc<uint32_t>((size_t)n * (mixed ? 2 : 3));
-  k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, dev_col ? dev_col : out.col, out.coef,
+  k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, dev_col ? dev_col : out.col, 16u * (uint32_t)s.dim, out.coef,
                                                           mixed ? out.coef32 : nullptr, out.slots);
   MTS_LAUNCH_CHECK();
 }
 
 // Per-workgroup neighbour lists for LDS staging (host side, integer work only).
-// Workgroup w runs slices 4w .. 4w + 3; its list is the sorted set of every
-// node its slots name (padding slots name node 0).  Staging is used only when
-// every list fits 64 KiB of LDS.
+// Workgroups take consecutive slices, at most G = wg_waves each, and a new one
+// starts where a slice's first row lies in another spatial tile, so that a
+// workgroup covers one tile.  Its list is the sorted set of every node its
+// slots name (padding slots name node 0).  Staging is used only when every
+// list fits the LDS share of one workgroup (64 KiB for 4 wavefronts, 80 KiB
+// for 8: two such workgroups per CU).
 void sell_build_halo(Solver &s, Sell &out) {
-  const int kHaloMax = 65536 / (16 * s.dim);  // records that fit 64 KiB of LDS
+  const int G = out.wg_waves;
+  int dev = 0, lds_max = 65536;
+  MTS_HIP(hipGetDevice(&dev));
+  MTS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const int kHaloMax = std::min(G == 8 ? 81920 : 65536, lds_max) / (16 * s.dim);  // records that fit
   out.halo_max = 0;
   if (!out.n_slices) return;
   hipStream_t st = s.stream;
@@ -299,13 +312,21 @@ void sell_build_halo(Solver &s, Sell &out) {
   MTS_HIP(hipMemcpyAsync(col.data(), out.col, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
   MTS_HIP(hipStreamSynchronize(st));
   const int64_t per_slice = (int64_t)out.T * WAVE;
-  const int64_t nwg = (out.n_slices + 3) / 4;
+  const int64_t S = WAVE / out.L;  // rows per slice
+  std::vector<int32_t> start{0};
+  for (int64_t sl = 1; sl < out.n_slices; sl++) {
+    const bool full = sl - start.back() == G;
+    const bool new_tile = !out.h_tile.empty() && out.h_tile[sl * S] != out.h_tile[start.back() * S];
+    if (full || new_tile) start.push_back((int32_t)sl);
+  }
+  start.push_back((int32_t)out.n_slices);
+  const int64_t nwg = (int64_t)start.size() - 1;
   std::vector<int32_t> off(nwg + 1, 0), ids, pos_of(s.N, -1), local(n, 0);
   std::vector<int64_t> stamp(s.N, -1);
   std::vector<int32_t> set;
   int hmax = 0;
   for (int64_t w = 0; w < nwg; w++) {
-    const int64_t a = w * 4 * per_slice, b = std::min<int64_t>((w + 1) * 4 * per_slice, out.n_slots);
+    const int64_t a = start[w] * per_slice, b = start[w + 1] * per_slice;
     set.clear();
     for (int64_t q = a; q < b; q++) {
       const int32_t c = col[q];
@@ -322,6 +343,9 @@ void sell_build_halo(Solver &s, Sell &out) {
     ids.insert(ids.end(), set.begin(), set.end());
     off[w + 1] = (int32_t)ids.size();
   }
+  out.n_wg = nwg;
+  out.wg_start = s.arena.alloc<int32_t>(nwg + 1);
+  MTS_HIP(hipMemcpyAsync(out.wg_start, start.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice, st));
   out.halo_off = s.arena.alloc<int32_t>(nwg + 1);
   out.halo_ids = s.arena.alloc<int32_t>(std::max<size_t>(ids.size(), 1));
   int32_t *dlocal = s.arena.alloc<int32_t>(n);

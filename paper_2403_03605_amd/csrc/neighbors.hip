@@ -234,9 +234,11 @@ void build_neighbors(Solver &s) {
     ar.release(q);
 
   // Rows of the bond layout in spatial tile order (32 x 8 nodes in 2D,
-  // 8 x 8 x 4 in 3D, ascending id inside a tile): a workgroup's rows and
-  // their neighbours then form a compact patch, which keeps the neighbour
-  // gathers of consecutive workgroups in the same L2.
+  // 8 x 4 x 4 or 4 x 4 x 4 in 3D, ascending id inside a tile): a workgroup's
+  // rows and their neighbours then form a compact patch, which keeps the
+  // neighbour gathers of consecutive workgroups in the same L2 and the staged
+  // neighbour lists short.
+  if (s.halo_waves == 0) s.halo_waves = (dim == 3 && s.precision == MTS_MIXED) ? 8 : 4;
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;
   if (s.tiled != 0 && s.p.dx > 0.0) {
@@ -245,8 +247,8 @@ void build_neighbors(Solver &s) {
       lo[a] = s.pos[a];
       for (int64_t i = 0; i < N; i++) lo[a] = std::min(lo[a], s.pos[(size_t)i * dim + a]);
     }
-    // 3D tiles of 4 x 4 x 4 = 64 nodes: one workgroup at 4 lanes per row
-    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {4.0, 4.0, 4.0};
+    // 3D tiles of 16 x halo_waves nodes: one workgroup at 4 lanes per row
+    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {s.halo_waves == 8 ? 8.0 : 4.0, 4.0, 4.0};
     const double *ext = dim == 2 ? ext2 : ext3;
     std::vector<int64_t> key(N);
     int64_t nt[3] = {1, 1, 1};
@@ -260,17 +262,20 @@ void build_neighbors(Solver &s) {
     for (int64_t i = 0; i < N; i++)
       key[i] = (tc[(size_t)i * 3 + 2] * nt[1] + tc[(size_t)i * 3 + 1]) * nt[0] + tc[(size_t)i * 3 + 0];
     std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    s.sell.h_tile.resize(N);
+    for (int64_t r = 0; r < N; r++) s.sell.h_tile[r] = key[rows[r]];
     std::vector<int32_t> row_of(N);
     for (int64_t r = 0; r < N; r++) row_of[rows[r]] = (int32_t)r;
     s.sell.row_of = ar.alloc<int32_t>(N);
     MTS_HIP(hipMemcpyAsync(s.sell.row_of, row_of.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, st));
     MTS_HIP(hipStreamSynchronize(st));
   }
-  // In 3D a workgroup at 4 lanes per row covers one 4 x 4 x 4 tile, whose
-  // staged neighbour records fit LDS.
+  // In 3D a workgroup at 4 lanes per row covers one tile, whose staged
+  // neighbour records fit LDS.
   int L = s.force_lanes ? s.force_lanes : pick_lanes(N, dim);
   if (!s.force_lanes && dim == 3 && s.halo && s.tiled != 0) L = std::max(L, 4);
   build_sell(s, s.sell, rows, nullptr, L);
+  s.sell.wg_waves = s.halo_waves;
   // the bond pass addresses its arrays with 32-bit byte offsets
   const uint64_t lim = (uint64_t)1 << 32;
   if ((uint64_t)(s.sell.n_slots + (int64_t)kSpareIters * WAVE) * 8 >= lim || (uint64_t)N * 2 * dim * 8 >= lim)

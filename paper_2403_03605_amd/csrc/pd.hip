@@ -64,8 +64,9 @@ struct SubstepArgs {
   int T;
   const int32_t *width;
   const int64_t *slot_off, *word_off;
-  const uint32_t *slots;  // interleaved {col, coef} per slot (col: LDS list position when staged)
+  const uint32_t *slots;  // per slot: record byte offset (LDS offset when staged) and coefficient
   const int32_t *halo_off, *halo_ids;  // per-workgroup staged neighbour lists (or nullptr)
+  const int32_t *wg_start;             // staged pass: first slice of each workgroup
   uint64_t *mask;
   const double *mass, *P;
   const double *xu_in;  // node records [x, u_j (predicted)]
@@ -99,7 +100,7 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-template <int DIM, int L, bool MX, int TM, bool PIPE, bool HALO = false>
+template <int DIM, int L, bool MX, int TM, bool HALO = false>
 __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice,
                                              const double2 *lds = nullptr) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
@@ -147,41 +148,43 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   for (int d = 0; d < DIM; d++) F[d] = R(0);
   int n_intact = 0;
   int broke = 0;
-  // Chunks of TM iterations: every load of a chunk is issued before any of its
-  // results is used (state words, indices and coefficients first, then the
-  // neighbour gathers), so a wavefront waits on two memory round trips per
-  // chunk instead of three per slot.  With PIPE the state words, indices and
-  // coefficients of chunk t0 + TM are requested right after the neighbour
-  // gathers of chunk t0, so the slot stream stays in flight while chunk t0 is
-  // gathered and evaluated.  The slot arrays carry kSpareIters (>= TM) spare
-  // iterations past the last slice, so every such load is in bounds; slots past
-  // T are masked out.
-  static_assert(kSpareIters >= TM, "spare iterations must cover one chunk");
-  uint64_t word[TM];
-  uint32_t c8[TM];  // neighbour record byte offset
-  R cf[TM];
-  auto load_slots = [&](int t, uint64_t *w, uint32_t *cc, R *ff) {
+  // Chunks of TM iterations, software-pipelined over two register sets: the
+  // state words and slot records of chunk t + TM are requested before chunk t
+  // is gathered and evaluated, and are only decoded when their own chunk runs,
+  // so their memory latency overlaps a whole chunk of work.  The slot arrays
+  // carry kSpareIters (>= 2 TM - 1) spare iterations past the last slice, so
+  // every such load is in bounds; slots past T are masked out.
+  static_assert(kSpareIters >= 2 * TM - 1, "spare iterations must cover the look-ahead chunk");
+  // The state word is the same in every lane.  Loading it through a lane-varying
+  // (zero) offset keeps it in vector registers, so the look-ahead load is not
+  // waited for at once to move it into scalar registers.
+  uint32_t zoff;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
+  const uint64_t lanebit = 1ull << lane;
+  struct Chunk {
+    uint64_t w[TM];       // bond-state words
+    uint32_t c[TM];       // neighbour record byte offset (in LDS when staged)
+    uint32_t f0[TM], f1[TM];  // coefficient bits (f1: high word, FP64 only)
+  };
+  auto load_chunk = [&](int t, Chunk &C) {
 #pragma unroll
     for (int q = 0; q < TM; q++) {
       const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
-      w[q] = A.mask[wo + t + q];
+      C.w[q] = ld32(static_cast<const uint64_t *>(A.mask), (uint32_t)(wo + t + q) * 8u + zoff);
       if constexpr (MX) {
         const uint2 v = ld32(reinterpret_cast<const uint2 *>(A.slots), pos * 8u);
-        cc[q] = v.x * RB;
-        ff[q] = __uint_as_float(v.y);
+        C.c[q] = v.x;
+        C.f0[q] = v.y;
+        C.f1[q] = 0u;
       } else {
-        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);
-        cc[q] = v.x * RB;
-        ff[q] = __longlong_as_double((long long)(((uint64_t)v.z << 32) | v.y));
+        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);  // {coef lo, coef hi, offset}
+        C.f0[q] = v.x;
+        C.f1[q] = v.y;
+        C.c[q] = v.z;
       }
     }
   };
-  load_slots(0, word, c8, cf);
-  for (int t0 = 0; t0 < T; t0 += TM) {
-    if (!PIPE && t0 > 0) load_slots(t0, word, c8, cf);
-#pragma unroll
-    for (int q = 0; q < TM; q++)
-      if (t0 + q >= T) word[q] = 0ull;
+  auto run_chunk = [&](int t0, const Chunk &C) {
     double xk[TM][DIM], uk[TM][DIM];
 #pragma unroll
     for (int q = 0; q < TM; q++) {
@@ -189,8 +192,8 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
 #pragma unroll
       for (int h = 0; h < DIM; h++) {
         double2 v2;
-        if constexpr (HALO) v2 = lds[c8[q] / 16u + h];  // staged record
-        else v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), c8[q] + 16u * h);
+        if constexpr (HALO) v2 = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(lds) + C.c[q] + 16u * h);
+        else v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), C.c[q] + 16u * h);
         rec[2 * h] = v2.x;
         rec[2 * h + 1] = v2.y;
       }
@@ -200,21 +203,21 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
         uk[q][d] = rec[DIM + d];
       }
     }
-    uint64_t wnext[TM];
-    uint32_t cnext[TM];
-    R fnext[TM];
-    if (PIPE && t0 + TM < T) load_slots(t0 + TM, wnext, cnext, fnext);  // wave-uniform
 #pragma unroll
     for (int q = 0; q < TM; q++) {
-      bool bit = (word[q] >> lane) & 1ull;
+      const bool live = t0 + q < T;  // wave-uniform
+      const uint64_t word = live ? C.w[q] : 0ull;
+      bool bit = (word & lanebit) != 0ull;
       if (bit) {
         if constexpr (!MX) {
+          const R cf = __longlong_as_double((long long)(((uint64_t)C.f1[q] << 32) | C.f0[q]));
           double xi[DIM], eta[DIM];
           for (int d = 0; d < DIM; d++) {
             xi[d] = xk[q][d] - xi_[d];
             eta[d] = uk[q][d] - ui_[d];
           }
           if (A.breaking) {
+            // squared lengths as the plain formula forms them (no contraction)
             double r2 = xi[0] * xi[0] + xi[1] * xi[1];
             double y0 = xi[0] + eta[0], y1 = xi[1] + eta[1];
             double y2 = y0 * y0 + y1 * y1;
@@ -229,53 +232,55 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
             }
           }
           if (bit) {
-            double xe = xi[0] * eta[0] + xi[1] * eta[1];
-            if (DIM == 3) xe = xe + xi[2] * eta[2];
-            const double tt = cf[q] * xe;  // Eq. 2 times V_i V_k, Arlequin-weighted
-            for (int d = 0; d < DIM; d++) F[d] += tt * xi[d];
+            double xe = __builtin_fma(xi[1], eta[1], xi[0] * eta[0]);
+            if (DIM == 3) xe = __builtin_fma(xi[2], eta[2], xe);
+            const double tt = cf * xe;  // Eq. 2 times V_i V_k, Arlequin-weighted
+            for (int d = 0; d < DIM; d++) F[d] = __builtin_fma(tt, xi[d], F[d]);
             n_intact++;
           }
         } else {
+          const R cf = __uint_as_float(C.f0[q]);
           float xi[DIM], eta[DIM];
           for (int d = 0; d < DIM; d++) {
             xi[d] = (float)(xk[q][d] - xi_[d]);
             eta[d] = (float)(uk[q][d] - ui_[d]);
           }
-          float xe = xi[0] * eta[0] + xi[1] * eta[1];
-          if (DIM == 3) xe = xe + xi[2] * eta[2];
+          float xe = __builtin_fmaf(xi[1], eta[1], xi[0] * eta[0]);
+          if (DIM == 3) xe = __builtin_fmaf(xi[2], eta[2], xe);
           if (A.breaking) {
             // |xi+eta|^2 - |xi|^2 = 2 xi.eta + eta.eta >= ((1+s_c)^2 - 1) |xi|^2
-            float r2 = xi[0] * xi[0] + xi[1] * xi[1];
-            float ee = eta[0] * eta[0] + eta[1] * eta[1];
+            float r2 = __builtin_fmaf(xi[1], xi[1], xi[0] * xi[0]);
+            float ee = __builtin_fmaf(eta[1], eta[1], eta[0] * eta[0]);
             if (DIM == 3) {
-              r2 = r2 + xi[2] * xi[2];
-              ee = ee + eta[2] * eta[2];
+              r2 = __builtin_fmaf(xi[2], xi[2], r2);
+              ee = __builtin_fmaf(eta[2], eta[2], ee);
             }
-            if (2.0f * xe + ee >= P.K2m1f * r2) {
+            if (__builtin_fmaf(2.0f, xe, ee) >= P.K2m1f * r2) {
               bit = false;
               broke = 1;
             }
           }
           if (bit) {
-            const float tt = cf[q] * xe;
-            for (int d = 0; d < DIM; d++) F[d] += tt * xi[d];
+            const float tt = cf * xe;
+            for (int d = 0; d < DIM; d++) F[d] = __builtin_fmaf(tt, xi[d], F[d]);
             n_intact++;
           }
         }
       }
-      if (t0 + q < T) {
+      if (live) {
         const uint64_t nw = __ballot(bit);
-        if (nw != word[q] && lane == 0) A.mask[wo + t0 + q] = nw;
+        if (nw != word && lane == 0) A.mask[wo + t0 + q] = nw;
       }
     }
-    if (PIPE) {
-#pragma unroll
-      for (int q = 0; q < TM; q++) {
-        word[q] = wnext[q];
-        c8[q] = cnext[q];
-        cf[q] = fnext[q];
-      }
-    }
+  };
+  Chunk C0, C1;
+  load_chunk(0, C0);
+  for (int t0 = 0; t0 < T; t0 += 2 * TM) {
+    load_chunk(t0 + TM, C1);
+    run_chunk(t0, C0);
+    if (t0 + TM >= T) break;
+    load_chunk(t0 + 2 * TM, C0);
+    run_chunk(t0 + TM, C1);
   }
   for (int off = L / 2; off >= 1; off >>= 1) {
     for (int d = 0; d < DIM; d++) F[d] += __shfl_xor(F[d], off, WAVE);
@@ -311,36 +316,40 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
 
 // One solver: slice = renumbered workgroup * 4 + wavefront (wave-uniform, so
 // offsets and state words come through scalar loads).
-template <int DIM, int L, bool MX, int TM, bool PIPE>
+template <int DIM, int L, bool MX, int TM>
 __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) {
   const int64_t slice = __builtin_amdgcn_readfirstlane(
       (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;  // uniform per wavefront
-  substep_body<DIM, L, MX, TM, PIPE>(A, P, slice);
+  substep_body<DIM, L, MX, TM>(A, P, slice);
 }
 
-// Copy workgroup wg's neighbour records into LDS (all threads; a barrier follows).
-template <int DIM>
+// Copy workgroup wg's neighbour records into LDS (all NT threads; a barrier follows).
+template <int DIM, int NT>
 __device__ __forceinline__ void stage_halo(const SubstepArgs &A, int64_t wg, double2 *lds) {
   const int h0 = A.halo_off[wg], nh = A.halo_off[wg + 1] - h0;
   const double2 *src = reinterpret_cast<const double2 *>(A.xu_in);
-  for (int h = threadIdx.x; h < nh; h += kBlock) {
+  for (int h = threadIdx.x; h < nh; h += NT) {
     const uint32_t rb = (uint32_t)A.halo_ids[h0 + h] * (16u * DIM);
 #pragma unroll
     for (int q = 0; q < DIM; q++) lds[h * DIM + q] = ld32(src, rb + 16u * q);
   }
 }
 
-// One solver, neighbour records staged in LDS per workgroup.
-template <int DIM, int L, bool MX>
-__global__ __launch_bounds__(kBlock) void k_pd_substep_halo(SubstepArgs A, Params P) {
+// One solver, neighbour records staged in LDS per workgroup of up to NW
+// wavefronts (consecutive slices of one spatial tile).  With NW = 8 the
+// register budget is held to four wavefronts per SIMD, so that two workgroups
+// share a CU.
+template <int DIM, int L, bool MX, int NW>
+__global__ __launch_bounds__(NW * 64, NW == 8 ? 4 : 1) void k_pd_substep_halo(SubstepArgs A, Params P) {
   extern __shared__ double2 lds[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  stage_halo<DIM>(A, b, lds);
+  stage_halo<DIM, NW * 64>(A, b, lds);
   __syncthreads();
-  const int64_t slice = __builtin_amdgcn_readfirstlane((int)(b * (kBlock / WAVE) + (threadIdx.x >> 6)));
-  if (slice >= A.n_slices) return;  // after the barrier every wave of the group has staged
-  substep_body<DIM, L, MX, 4, true, true>(A, P, slice, lds);
+  const int s0 = A.wg_start[b], w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (w >= A.wg_start[b + 1] - s0) return;  // after the barrier every wave of the group has staged
+  const int64_t slice = s0 + w;
+  substep_body<DIM, L, MX, 4, true>(A, P, slice, lds);
 }
 
 // Several solvers in one launch: workgroup b (after renumbering) belongs to
@@ -354,13 +363,15 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep_batch(const SubstepEntry 
   const int64_t slice = __builtin_amdgcn_readfirstlane(
       (int)((b - tab[r].first_block) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;
-  substep_body<DIM, L, MX, 4, true>(A, P, slice);
+  substep_body<DIM, L, MX, 4>(A, P, slice);
 }
 
 // Link problem (Eq. 48b / eq. unit): linear, no breaking, bond states of the
-// last rebuild.  NRHS right-hand sides share one pass over the bond data.
-//  kColor = false: one RHS, load (j/m) lambda_m at every constraint node.
-//  kColor = true : RHS b loads (j/m) e_dir(b) at every constraint node of color(b).
+// last rebuild, the response starting from rest at substep 1.
+//
+// Unit-load responses (setup and rebuild): NRHS right-hand sides share one pass
+// over the bond data; RHS b loads (j/m) e_dir(b) at every constraint node of
+// colour(b).
 struct LinkArgs {
   const double *x;
   int64_t N, n_rows, n_slices;
@@ -375,25 +386,14 @@ struct LinkArgs {
   const double *u_in;
   double *u_out, *v, *a;  // [NRHS][DIM][N]
   const int32_t *cidx;
-  const double *lam;      // kColor = false
-  const int32_t *ccolor;  // kColor = true: color of each constraint
+  const int32_t *ccolor;  // colour of each constraint
   int32_t rhs_color[16];
   int32_t rhs_dir[16];
   double lfac;
   int first;              // substep 1: the response starts from rest (inputs are exact zeros)
-  // last substep of the final update (one RHS): add W_m into the PD state
-  // (Eq. 50) and write the predictor, instead of storing W_m
-  int add;
-  double *Uxu, *Uxu_pred, *Uv, *Ua;
 };
 
-struct LinkEntry {
-  LinkArgs A;
-  Params P;
-  int32_t first_block;
-};
-
-template <int DIM, int NRHS, bool kColor, int L>
+template <int DIM, int NRHS, int L>
 __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, const int64_t slice) {
   constexpr int S = WAVE / L;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -427,39 +427,18 @@ __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, co
   double F[NRHS][DIM];
   for (int b = 0; b < NRHS; b++)
     for (int d = 0; d < DIM; d++) F[b][d] = 0.0;
-  constexpr int TM = NRHS == 1 ? 4 : 1;
-  for (int t0 = 0; t0 < (A.first ? 0 : T); t0 += TM) {  // no bond forces from a response at rest
-    bool bit[TM];
-    int64_t c[TM];
-    double cf[TM];
-#pragma unroll
-    for (int q = 0; q < TM; q++) {
-      const int64_t pos = so + (int64_t)(t0 + q) * WAVE + lane;
-      bit[q] = (A.mask[wo + t0 + q] >> lane) & 1ull;
-      c[q] = A.col[pos];
-      cf[q] = A.coef[pos];
-    }
-#pragma unroll
-    for (int q = 0; q < TM; q++)
-      if (t0 + q >= T) bit[q] = false;
-    double xk[TM][DIM], uk[TM][NRHS][DIM];
-#pragma unroll
-    for (int q = 0; q < TM; q++)
-      for (int d = 0; d < DIM; d++) {
-        xk[q][d] = A.x[d * N + c[q]];
-        for (int b = 0; b < NRHS; b++) uk[q][b][d] = A.u_in[b * stride + d * N + c[q]];
-      }
-#pragma unroll
-    for (int q = 0; q < TM; q++) {
-      if (!bit[q]) continue;
-      double xi[DIM];
-      for (int d = 0; d < DIM; d++) xi[d] = xk[q][d] - xi_[d];
-      for (int b = 0; b < NRHS; b++) {
-        double xe = xi[0] * (uk[q][b][0] - ui_[b][0]) + xi[1] * (uk[q][b][1] - ui_[b][1]);
-        if (DIM == 3) xe = xe + xi[2] * (uk[q][b][2] - ui_[b][2]);
-        const double tt = cf[q] * xe;
-        for (int d = 0; d < DIM; d++) F[b][d] += tt * xi[d];
-      }
+  for (int t = 0; t < (A.first ? 0 : T); t++) {  // no bond forces from a response at rest
+    const int64_t pos = so + (int64_t)t * WAVE + lane;
+    if (!((A.mask[wo + t] >> lane) & 1ull)) continue;
+    const int64_t c = A.col[pos];
+    const double cf = A.coef[pos];
+    double xi[DIM];
+    for (int d = 0; d < DIM; d++) xi[d] = A.x[d * N + c] - xi_[d];
+    for (int b = 0; b < NRHS; b++) {
+      double xe = xi[0] * (A.u_in[b * stride + c] - ui_[b][0]) + xi[1] * (A.u_in[b * stride + N + c] - ui_[b][1]);
+      if (DIM == 3) xe = xe + xi[2] * (A.u_in[b * stride + 2 * N + c] - ui_[b][2]);
+      const double tt = cf * xe;
+      for (int d = 0; d < DIM; d++) F[b][d] += tt * xi[d];
     }
   }
   for (int off = L / 2; off >= 1; off >>= 1)
@@ -473,57 +452,200 @@ __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, co
       if ((b * DIM + d) % L != l) continue;
       const int64_t tix = b * stride + d * N + i;
       double fl = F[b][d];
-      if (q >= 0) {
-        if (kColor) {
-          if (A.ccolor[q] == A.rhs_color[b] && d == A.rhs_dir[b]) fl = fl + A.lfac;
-        } else {
-          fl = fl + A.lfac * A.lam[q * DIM + d];
-        }
-      }
+      if (q >= 0 && A.ccolor[q] == A.rhs_color[b] && d == A.rhs_dir[b]) fl = fl + A.lfac;
       const double an = fl / m_i;
       const double v0 = A.first ? 0.0 : A.v[tix], a0 = A.first ? 0.0 : A.a[tix];
       const double vn = v0 + P.hdtP * (a0 + an);
-      const double un = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
-      if (!kColor && A.add) {
-        // U = V + W_m on this row (W_m's displacement is this substep's input,
-        // un the predictor beyond it), then the predictor for the next substep
-        const int64_t t = d * N + i, qx = i * 2 * DIM + DIM + d;
-        const double uu = A.Uxu[qx] + ui_[b][d];
-        const double vv = A.Uv[t] + vn;
-        const double aa = A.Ua[t] + an;
-        A.Uxu[qx] = uu;
-        A.Uv[t] = vv;
-        A.Ua[t] = aa;
-        A.Uxu_pred[qx] = (uu + P.dtP * vv) + P.hdt2P * aa;
-      } else {
-        A.a[tix] = an;
-        A.v[tix] = vn;
-        A.u_out[tix] = un;
-      }
+      A.a[tix] = an;
+      A.v[tix] = vn;
+      A.u_out[tix] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
     }
 }
 
-template <int DIM, int NRHS, bool kColor, int L>
+template <int DIM, int NRHS, int L>
 __global__ __launch_bounds__(kBlock) void k_link_substep(LinkArgs A, Params P) {
   const int64_t slice = __builtin_amdgcn_readfirstlane(
       (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;
-  link_body<DIM, NRHS, kColor, L>(A, P, slice);
+  link_body<DIM, NRHS, L>(A, P, slice);
 }
+
+// Final update of a macro step (Eq. 50): one right-hand side, the load
+// (j/m) lambda_m at every constraint node.  The response lives in node records
+// [x, w] (double-buffered like the free problem's) and the pass has the free
+// problem's shape: interleaved slot records {coefficient, record offset},
+// one 16-byte load per record half, chunks software-pipelined over two
+// register sets.  At the last substep the response is added into the PD state.
+struct Link1Args {
+  int64_t N, n_rows, n_slices;
+  int T;
+  const int32_t *rows, *slice_layer;
+  int jmax;               // rows farther than jmax horizons still hold exact zeros
+  const uint32_t *slots;  // per slot: {coef lo, coef hi, record byte offset}
+  const uint64_t *mask;
+  const double *mass;
+  const double *w_in;     // records [x, w_j]
+  double *w_out;          // records, w part <- w_{j+1}
+  double *v, *a;          // [DIM][N]
+  const int32_t *cidx;
+  const double *lam;
+  double lfac;
+  int first;              // substep 1: the response starts from rest
+  // last substep: add W_m into the PD state (its displacement is this
+  // substep's input) and write the next predictor, instead of storing W_m
+  int add;
+  double *Uxu, *Uxu_pred, *Uv, *Ua;
+};
 
 template <int DIM, int L>
-__global__ __launch_bounds__(kBlock) void k_link_substep_batch(const LinkEntry *tab, const int32_t *blk_req) {
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  const int r = __builtin_amdgcn_readfirstlane(blk_req[b]);
-  const LinkArgs A = tab[r].A;
-  const Params P = tab[r].P;
+__global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
+  constexpr int S = WAVE / L, TM = 4;
+  constexpr uint32_t RB = 16u * DIM;
+  static_assert(kSpareIters >= 2 * TM - 1, "spare iterations must cover the look-ahead chunk");
   const int64_t slice = __builtin_amdgcn_readfirstlane(
-      (int)((b - tab[r].first_block) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+      (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
   if (slice >= A.n_slices) return;
-  link_body<DIM, 1, false, L>(A, P, slice);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int jl = lane / L, l = lane % L;
+  const int64_t r = slice * S + jl;
+  const bool valid = r < A.n_rows;
+  const int64_t N = A.N;
+  const int64_t i = valid ? A.rows[r] : A.rows[0];
+  if (A.slice_layer[slice] > A.jmax) {  // uniform per wavefront: not reached yet, exactly zero
+    if (!valid) return;
+    for (int d = l; d < DIM; d += L) {
+      A.w_out[i * 2 * DIM + DIM + d] = 0.0;
+      if (A.first) {
+        A.v[d * N + i] = 0.0;
+        A.a[d * N + i] = 0.0;
+      }
+    }
+    return;
+  }
+  const int T = A.T;
+  const int64_t wo = slice * T;
+  const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;
+  double xi_[DIM], wi_[DIM];
+  {
+    double rec[2 * DIM];
+#pragma unroll
+    for (int h = 0; h < DIM; h++) {
+      const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.w_in), (uint32_t)i * RB + 16u * h);
+      rec[2 * h] = v2.x;
+      rec[2 * h + 1] = v2.y;
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+      xi_[d] = rec[d];
+      wi_[d] = A.first ? 0.0 : rec[DIM + d];
+    }
+  }
+  // node data of the epilogue, requested before the bond loop
+  const int32_t q = A.cidx[i];
+  const double m_i = A.mass[i];
+  double v0[DIM], a0[DIM], lq[DIM];
+  for (int d = 0; d < DIM; d++) {
+    v0[d] = A.first ? 0.0 : A.v[d * N + i];
+    a0[d] = A.first ? 0.0 : A.a[d * N + i];
+    lq[d] = q >= 0 ? A.lam[q * DIM + d] : 0.0;
+  }
+  double F[DIM];
+  for (int d = 0; d < DIM; d++) F[d] = 0.0;
+  if (!A.first) {  // no bond forces from a response at rest
+    uint32_t zoff;  // lane-varying zero: the state words stay in vector registers
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
+    const uint64_t lanebit = 1ull << lane;
+    struct Chunk {
+      uint64_t w[TM];
+      uint32_t c[TM], f0[TM], f1[TM];
+    };
+    auto load_chunk = [&](int t, Chunk &C) {
+#pragma unroll
+      for (int q = 0; q < TM; q++) {
+        const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
+        C.w[q] = ld32(A.mask, (uint32_t)(wo + t + q) * 8u + zoff);
+        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);
+        C.f0[q] = v.x;
+        C.f1[q] = v.y;
+        C.c[q] = v.z;
+      }
+    };
+    auto run_chunk = [&](int t0, const Chunk &C) {
+      double xk[TM][DIM], wk[TM][DIM];
+#pragma unroll
+      for (int q = 0; q < TM; q++) {
+        double rec[2 * DIM];
+#pragma unroll
+        for (int h = 0; h < DIM; h++) {
+          const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.w_in), C.c[q] + 16u * h);
+          rec[2 * h] = v2.x;
+          rec[2 * h + 1] = v2.y;
+        }
+#pragma unroll
+        for (int d = 0; d < DIM; d++) {
+          xk[q][d] = rec[d];
+          wk[q][d] = rec[DIM + d];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < TM; q++) {
+        const uint64_t word = t0 + q < T ? C.w[q] : 0ull;
+        if (word & lanebit) {
+          const double cf = __longlong_as_double((long long)(((uint64_t)C.f1[q] << 32) | C.f0[q]));
+          double xi[DIM];
+          for (int d = 0; d < DIM; d++) xi[d] = xk[q][d] - xi_[d];
+          double xe = __builtin_fma(xi[1], wk[q][1] - wi_[1], xi[0] * (wk[q][0] - wi_[0]));
+          if (DIM == 3) xe = __builtin_fma(xi[2], wk[q][2] - wi_[2], xe);
+          const double tt = cf * xe;
+          for (int d = 0; d < DIM; d++) F[d] = __builtin_fma(tt, xi[d], F[d]);
+        }
+      }
+    };
+    Chunk C0, C1;
+    load_chunk(0, C0);
+    for (int t0 = 0; t0 < T; t0 += 2 * TM) {
+      load_chunk(t0 + TM, C1);
+      run_chunk(t0, C0);
+      if (t0 + TM >= T) break;
+      load_chunk(t0 + 2 * TM, C0);
+      run_chunk(t0 + TM, C1);
+    }
+  }
+  for (int off = L / 2; off >= 1; off >>= 1)
+    for (int d = 0; d < DIM; d++) F[d] += __shfl_xor(F[d], off, WAVE);
+  if (!valid) return;
+  for (int d = l; d < DIM; d += L) {
+    const int64_t t = d * N + i, qx = i * 2 * DIM + DIM + d;
+    double fl = F[d];
+    if (q >= 0) fl = fl + A.lfac * lq[d];
+    const double an = fl / m_i;
+    const double vn = v0[d] + P.hdtP * (a0[d] + an);
+    if (A.add) {
+      // U = V + W_m on this row, then the predictor for the next substep
+      const double uu = A.Uxu[qx] + wi_[d];
+      const double vv = A.Uv[t] + vn;
+      const double aa = A.Ua[t] + an;
+      A.Uxu[qx] = uu;
+      A.Uv[t] = vv;
+      A.Ua[t] = aa;
+      A.Uxu_pred[qx] = (uu + P.dtP * vv) + P.hdt2P * aa;
+    } else {
+      A.a[t] = an;
+      A.v[t] = vn;
+      A.w_out[qx] = (wi_[d] + P.dtP * vn) + P.hdt2P * an;
+    }
+  }
 }
 
-
+// Node records [x, 0] of the final-update response.
+__global__ void k_link_records(const double *x, int64_t N, int dim, double *rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  for (int d = 0; d < dim; d++) {
+    rec[i * 2 * dim + d] = x[d * N + i];
+    rec[i * 2 * dim + dim + d] = 0.0;
+  }
+}
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
@@ -567,6 +689,7 @@ static SubstepArgs substep_args(Solver &s, int j, int cur) {
   A.slots = s.sell.slots;
   A.halo_off = s.sell.halo_max ? s.sell.halo_off : nullptr;
   A.halo_ids = s.sell.halo_max ? s.sell.halo_ids : nullptr;
+  A.wg_start = s.sell.halo_max ? s.sell.wg_start : nullptr;
   A.mask = s.sell.mask;
   A.mass = s.mass;
   A.P = s.P;
@@ -605,25 +728,30 @@ void pd_substep(Solver &s, int j) {
   const int L = s.sell.L;
   if (s.sell.halo_max > 0) {
     const size_t shm = (size_t)s.sell.halo_max * 16 * s.dim;
-#define MTS_SUBH(D, LL, MX) k_pd_substep_halo<D, LL, MX><<<grid, kBlock, shm, s.stream>>>(A, s.prm)
-    MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUBH);
+    const int nw = s.sell.wg_waves;
+    const unsigned hgrid = (unsigned)s.sell.n_wg;
+    if (nw == 8) {
+#define MTS_SUBH(D, LL, MX) k_pd_substep_halo<D, LL, MX, 8><<<hgrid, 8 * WAVE, shm, s.stream>>>(A, s.prm)
+      MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUBH);
 #undef MTS_SUBH
+    } else {
+#define MTS_SUBH(D, LL, MX) k_pd_substep_halo<D, LL, MX, 4><<<hgrid, 4 * WAVE, shm, s.stream>>>(A, s.prm)
+      MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUBH);
+#undef MTS_SUBH
+    }
     MTS_LAUNCH_CHECK();
     s.cur ^= 1;
     s.pd_steps++;
     return;
   }
-  switch (s.pd_variant) {
-#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+  switch (s.pd_variant) {  // chunk length (iterations per pipelined chunk)
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 2><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
     case 1: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
 #undef MTS_SUB
-#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 2, true><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 8><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
     case 2: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
 #undef MTS_SUB
-#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 2, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
-    case 3: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
-#undef MTS_SUB
-#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4, true><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+#define MTS_SUB(D, LL, MX) k_pd_substep<D, LL, MX, 4><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
     default: MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUB); break;
 #undef MTS_SUB
   }
@@ -658,21 +786,22 @@ void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const
 
 // ---- link runs (used by coupling.hip) ----
 
-template <int DIM, int NRHS, bool kColor>
+template <int DIM, int NRHS>
 static void launch_link(Solver &s, LinkArgs &A) {
   unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   switch (s.rsell.L) {
-    case 1: k_link_substep<DIM, NRHS, kColor, 1><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
-    case 2: k_link_substep<DIM, NRHS, kColor, 2><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
-    case 4: k_link_substep<DIM, NRHS, kColor, 4><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
-    default: k_link_substep<DIM, NRHS, kColor, 8><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    case 1: k_link_substep<DIM, NRHS, 1><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    case 2: k_link_substep<DIM, NRHS, 2><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    case 4: k_link_substep<DIM, NRHS, 4><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
+    default: k_link_substep<DIM, NRHS, 8><<<grid, kBlock, 0, s.stream>>>(A, s.prm); break;
   }
   MTS_LAUNCH_CHECK();
 }
 
-// One link substep j over the region rows.  u_in/u_out/v/a: [nrhs][dim][N].
-void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const double *lam,
-                  const int32_t *ccolor, const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, bool add) {
+// One substep j of the unit-load responses over the region rows.
+// u_in/u_out/v/a: [nrhs][dim][N].
+void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
+                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs) {
   if (!s.rsell.n_rows) return;
   LinkArgs A{};
   A.x = s.x;
@@ -695,12 +824,51 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
   A.v = v;
   A.a = a;
   A.cidx = s.cidx;
-  A.lam = lam;
   A.ccolor = ccolor;
-  for (int b = 0; b < nrhs && rhs_color; b++) {
+  for (int b = 0; b < nrhs; b++) {
     A.rhs_color[b] = rhs_color[b];
     A.rhs_dir[b] = rhs_dir[b];
   }
+  A.lfac = (double)j / (double)s.m;
+  A.first = j == 1 ? 1 : 0;
+  if (s.dim == 2) {
+    if (nrhs != 8) throw ArgError{"link batch must hold 8 right-hand sides in 2D"};
+    launch_link<2, 8>(s, A);
+  } else {
+    if (nrhs != 6) throw ArgError{"link batch must hold 6 right-hand sides in 3D"};
+    launch_link<3, 6>(s, A);
+  }
+}
+
+void link_records_init(Solver &s) {
+  for (int k = 0; k < 2; k++) {
+    k_link_records<<<nblk(s.N), 256, 0, s.stream>>>(s.x, s.N, s.dim, s.Wxu[k]);
+    MTS_LAUNCH_CHECK();
+  }
+}
+
+// Substep j of the final update's response with multipliers s.lam: reads
+// records Wxu[k], writes Wxu[k ^ 1]; the last substep (add) adds W_m into the
+// PD state.
+void link_final_substep(Solver &s, int j, int k, bool add) {
+  if (!s.rsell.n_rows) return;
+  Link1Args A{};
+  A.N = s.N;
+  A.n_rows = s.rsell.n_rows;
+  A.n_slices = s.rsell.n_slices;
+  A.T = s.rsell.T;
+  A.rows = s.rsell.rows;
+  A.slice_layer = s.rsell.slice_layer;
+  A.jmax = j - 1;
+  A.slots = s.rsell.slots;
+  A.mask = s.rsell.mask;
+  A.mass = s.mass;
+  A.w_in = s.Wxu[k];
+  A.w_out = s.Wxu[k ^ 1];
+  A.v = s.Wv;
+  A.a = s.Wa;
+  A.cidx = s.cidx;
+  A.lam = s.lam;
   A.lfac = (double)j / (double)s.m;
   A.first = j == 1 ? 1 : 0;
   A.add = add ? 1 : 0;
@@ -710,16 +878,25 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
     A.Uv = s.v;
     A.Ua = s.a;
   }
-  if (!ccolor) {
-    if (s.dim == 2) launch_link<2, 1, false>(s, A);
-    else launch_link<3, 1, false>(s, A);
-  } else if (s.dim == 2) {
-    if (nrhs != 8) throw ArgError{"link batch must hold 8 right-hand sides in 2D"};
-    launch_link<2, 8, true>(s, A);
+  const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
+#define MTS_LF(D, LL) k_link_final<D, LL><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+  if (s.dim == 2) {
+    switch (s.rsell.L) {
+      case 1: MTS_LF(2, 1); break;
+      case 2: MTS_LF(2, 2); break;
+      case 4: MTS_LF(2, 4); break;
+      default: MTS_LF(2, 8); break;
+    }
   } else {
-    if (nrhs != 6) throw ArgError{"link batch must hold 6 right-hand sides in 3D"};
-    launch_link<3, 6, true>(s, A);
+    switch (s.rsell.L) {
+      case 1: MTS_LF(3, 1); break;
+      case 2: MTS_LF(3, 2); break;
+      case 4: MTS_LF(3, 4); break;
+      default: MTS_LF(3, 8); break;
+    }
   }
+#undef MTS_LF
+  MTS_LAUNCH_CHECK();
 }
 
 

@@ -194,6 +194,11 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   if (const char *t = std::getenv("MTS_TILE")) s->tiled = std::atoi(t) != 0 ? 1 : 0;  // tuning: row order
   if (const char *t = std::getenv("MTS_PD_VARIANT")) s->pd_variant = std::atoi(t);  // tuning: loop shape
   if (const char *t = std::getenv("MTS_HALO")) s->halo = std::atoi(t) != 0;          // tuning: LDS staging
+  if (const char *t = std::getenv("MTS_REGION_LANES")) {  // tuning: link region lanes per row
+    const int v = std::atoi(t);
+    s->region_lanes = (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
+  }
+  if (const char *t = std::getenv("MTS_HALO_WAVES")) s->halo_waves = std::atoi(t) == 8 ? 8 : 4;  // tuning
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
     const int L = std::atoi(e);
@@ -466,6 +471,8 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
     if (p->mode == MTS_COUPLED) {
       bytes += nl * nl * 8 + nl * 64 * 16 + ne * 8 * 8 * 4 + nfe * 8 * 12 + 4 * rhs * p->dim * p->n_pd * 8;
       bytes += out->nnz_estimate * 5;
+      // final-update response records and the region's slot records
+      bytes += 2 * 2 * p->dim * p->n_pd * 8 + out->nnz_estimate * 12;
     }
     out->device_bytes_estimate = bytes;
     return MTS_OK;
