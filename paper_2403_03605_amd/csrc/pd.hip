@@ -100,9 +100,51 @@ __device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
+// Raw slot data of TM consecutive iterations of a slice, as loaded (decoded
+// only when the chunk runs).
+template <int TM>
+struct SlotChunk {
+  uint64_t w[TM];           // bond-state words
+  uint32_t c[TM];           // neighbour record byte offset (in LDS when staged)
+  uint32_t f0[TM], f1[TM];  // coefficient bits (f1: high word, FP64 only)
+};
+
+// A zero the compiler cannot see through, in a vector register.  The state
+// word of an iteration is the same in every lane; loading it through this
+// lane-varying offset keeps it in vector registers, so a look-ahead load is not
+// waited for at once to move it into scalar registers.
+__device__ __forceinline__ uint32_t lane_zero() {
+  uint32_t z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return z;
+}
+
+// Iterations t .. t + TM - 1 of the slice whose state words start at wo and
+// whose slot index of (iteration 0, this lane) is so.
+template <bool MX, int TM>
+__device__ __forceinline__ void load_slot_chunk(const uint64_t *mask, const uint32_t *slots, int64_t wo, uint32_t so,
+                                                uint32_t zoff, int t, SlotChunk<TM> &C) {
+#pragma unroll
+  for (int q = 0; q < TM; q++) {
+    const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
+    C.w[q] = ld32(mask, (uint32_t)(wo + t + q) * 8u + zoff);
+    if constexpr (MX) {
+      const uint2 v = ld32(reinterpret_cast<const uint2 *>(slots), pos * 8u);  // {offset, coef}
+      C.c[q] = v.x;
+      C.f0[q] = v.y;
+      C.f1[q] = 0u;
+    } else {
+      const uint3 v = ld32(reinterpret_cast<const uint3 *>(slots), pos * 12u);  // {coef lo, coef hi, offset}
+      C.f0[q] = v.x;
+      C.f1[q] = v.y;
+      C.c[q] = v.z;
+    }
+  }
+}
+
 template <int DIM, int L, bool MX, int TM, bool HALO = false>
 __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice,
-                                             const double2 *lds = nullptr) {
+                                             const double2 *lds = nullptr, const SlotChunk<TM> *first = nullptr) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
   // formed in FP64; the accumulated value is the acceleration (coefficient
   // pre-divided by the node mass).  Integration stays FP64.
@@ -112,13 +154,18 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   const int64_t N = A.N;
   const uint32_t N8 = (uint32_t)N * 8u;  // byte stride of one component
   const int jl = lane / L, l = lane % L;
+  const int T = A.T;
+  const int64_t wo = slice * T;
+  const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;  // slot index of (iteration 0, this lane)
+  const uint32_t zoff = lane_zero();
+  // The first chunk of slot data does not depend on the row's node: a caller
+  // may have requested it already (before its staging loads).
+  SlotChunk<TM> C0, C1;
+  if (first) C0 = *first;
   const int64_t row = slice * S + jl;
   const bool valid = row < N;
   const int64_t i = valid ? A.rows[row] : 0;
   const uint32_t i8 = (uint32_t)i * 8u;
-  const int T = A.T;
-  const int64_t wo = slice * T;
-  const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;  // slot index of (iteration 0, this lane)
   constexpr uint32_t RB = 16u * DIM;  // bytes of one node record
   double xi_[DIM], ui_[DIM];
   {
@@ -155,36 +202,8 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   // carry kSpareIters (>= 2 TM - 1) spare iterations past the last slice, so
   // every such load is in bounds; slots past T are masked out.
   static_assert(kSpareIters >= 2 * TM - 1, "spare iterations must cover the look-ahead chunk");
-  // The state word is the same in every lane.  Loading it through a lane-varying
-  // (zero) offset keeps it in vector registers, so the look-ahead load is not
-  // waited for at once to move it into scalar registers.
-  uint32_t zoff;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
   const uint64_t lanebit = 1ull << lane;
-  struct Chunk {
-    uint64_t w[TM];       // bond-state words
-    uint32_t c[TM];       // neighbour record byte offset (in LDS when staged)
-    uint32_t f0[TM], f1[TM];  // coefficient bits (f1: high word, FP64 only)
-  };
-  auto load_chunk = [&](int t, Chunk &C) {
-#pragma unroll
-    for (int q = 0; q < TM; q++) {
-      const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
-      C.w[q] = ld32(static_cast<const uint64_t *>(A.mask), (uint32_t)(wo + t + q) * 8u + zoff);
-      if constexpr (MX) {
-        const uint2 v = ld32(reinterpret_cast<const uint2 *>(A.slots), pos * 8u);
-        C.c[q] = v.x;
-        C.f0[q] = v.y;
-        C.f1[q] = 0u;
-      } else {
-        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);  // {coef lo, coef hi, offset}
-        C.f0[q] = v.x;
-        C.f1[q] = v.y;
-        C.c[q] = v.z;
-      }
-    }
-  };
-  auto run_chunk = [&](int t0, const Chunk &C) {
+  auto run_chunk = [&](int t0, const SlotChunk<TM> &C) {
     double xk[TM][DIM], uk[TM][DIM];
 #pragma unroll
     for (int q = 0; q < TM; q++) {
@@ -273,13 +292,12 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
       }
     }
   };
-  Chunk C0, C1;
-  load_chunk(0, C0);
+  if (!first) load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, 0, C0);
   for (int t0 = 0; t0 < T; t0 += 2 * TM) {
-    load_chunk(t0 + TM, C1);
+    load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, t0 + TM, C1);
     run_chunk(t0, C0);
     if (t0 + TM >= T) break;
-    load_chunk(t0 + 2 * TM, C0);
+    load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, t0 + 2 * TM, C0);
     run_chunk(t0 + TM, C1);
   }
   for (int off = L / 2; off >= 1; off >>= 1) {
@@ -340,16 +358,29 @@ __device__ __forceinline__ void stage_halo(const SubstepArgs &A, int64_t wg, dou
 // wavefronts (consecutive slices of one spatial tile).  With NW = 8 the
 // register budget is held to four wavefronts per SIMD, so that two workgroups
 // share a CU.
-template <int DIM, int L, bool MX, int NW>
+template <int DIM, int L, bool MX, int NW, bool EARLY = (DIM == 2 && MX)>
 __global__ __launch_bounds__(NW * 64, NW == 8 ? 4 : 1) void k_pd_substep_halo(SubstepArgs A, Params P) {
   extern __shared__ double2 lds[];
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  stage_halo<DIM, NW * 64>(A, b, lds);
-  __syncthreads();
   const int s0 = A.wg_start[b], w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (w >= A.wg_start[b + 1] - s0) return;  // after the barrier every wave of the group has staged
+  const bool active = w < A.wg_start[b + 1] - s0;  // wave-uniform
   const int64_t slice = s0 + w;
-  substep_body<DIM, L, MX, 4, true>(A, P, slice, lds);
+  if constexpr (EARLY) {
+    // the first chunk of slot data is requested before the staging loads
+    SlotChunk<4> C0;
+    if (active)
+      load_slot_chunk<MX, 4>(A.mask, A.slots, slice * A.T,
+                             (uint32_t)(slice * A.T * WAVE) + (threadIdx.x & (WAVE - 1)), lane_zero(), 0, C0);
+    stage_halo<DIM, NW * 64>(A, b, lds);
+    __syncthreads();
+    if (!active) return;  // after the barrier every wave of the group has staged
+    substep_body<DIM, L, MX, 4, true>(A, P, slice, lds, &C0);
+  } else {
+    stage_halo<DIM, NW * 64>(A, b, lds);
+    __syncthreads();
+    if (!active) return;
+    substep_body<DIM, L, MX, 4, true>(A, P, slice, lds);
+  }
 }
 
 // Several solvers in one launch: workgroup b (after renumbering) belongs to
@@ -510,9 +541,9 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
   const int64_t r = slice * S + jl;
   const bool valid = r < A.n_rows;
   const int64_t N = A.N;
-  const int64_t i = valid ? A.rows[r] : A.rows[0];
   if (A.slice_layer[slice] > A.jmax) {  // uniform per wavefront: not reached yet, exactly zero
     if (!valid) return;
+    const int64_t i = A.rows[r];
     for (int d = l; d < DIM; d += L) {
       A.w_out[i * 2 * DIM + DIM + d] = 0.0;
       if (A.first) {
@@ -525,6 +556,10 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
   const int T = A.T;
   const int64_t wo = slice * T;
   const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;
+  const uint32_t zoff = lane_zero();
+  SlotChunk<TM> C0, C1;  // the first chunk is requested before the row's node data
+  if (!A.first) load_slot_chunk<false, TM>(A.mask, A.slots, wo, so, zoff, 0, C0);
+  const int64_t i = valid ? A.rows[r] : A.rows[0];
   double xi_[DIM], wi_[DIM];
   {
     double rec[2 * DIM];
@@ -547,30 +582,12 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
   for (int d = 0; d < DIM; d++) {
     v0[d] = A.first ? 0.0 : A.v[d * N + i];
     a0[d] = A.first ? 0.0 : A.a[d * N + i];
-    lq[d] = q >= 0 ? A.lam[q * DIM + d] : 0.0;
   }
   double F[DIM];
   for (int d = 0; d < DIM; d++) F[d] = 0.0;
   if (!A.first) {  // no bond forces from a response at rest
-    uint32_t zoff;  // lane-varying zero: the state words stay in vector registers
-    asm volatile("v_mov_b32 %0, 0" : "=v"(zoff));
     const uint64_t lanebit = 1ull << lane;
-    struct Chunk {
-      uint64_t w[TM];
-      uint32_t c[TM], f0[TM], f1[TM];
-    };
-    auto load_chunk = [&](int t, Chunk &C) {
-#pragma unroll
-      for (int q = 0; q < TM; q++) {
-        const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
-        C.w[q] = ld32(A.mask, (uint32_t)(wo + t + q) * 8u + zoff);
-        const uint3 v = ld32(reinterpret_cast<const uint3 *>(A.slots), pos * 12u);
-        C.f0[q] = v.x;
-        C.f1[q] = v.y;
-        C.c[q] = v.z;
-      }
-    };
-    auto run_chunk = [&](int t0, const Chunk &C) {
+    auto run_chunk = [&](int t0, const SlotChunk<TM> &C) {
       double xk[TM][DIM], wk[TM][DIM];
 #pragma unroll
       for (int q = 0; q < TM; q++) {
@@ -601,16 +618,17 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
         }
       }
     };
-    Chunk C0, C1;
-    load_chunk(0, C0);
+    for (int d = 0; d < DIM; d++) lq[d] = q >= 0 ? A.lam[q * DIM + d] : 0.0;  // in flight during the loop
     for (int t0 = 0; t0 < T; t0 += 2 * TM) {
-      load_chunk(t0 + TM, C1);
+      load_slot_chunk<false, TM>(A.mask, A.slots, wo, so, zoff, t0 + TM, C1);
       run_chunk(t0, C0);
       if (t0 + TM >= T) break;
-      load_chunk(t0 + 2 * TM, C0);
+      load_slot_chunk<false, TM>(A.mask, A.slots, wo, so, zoff, t0 + 2 * TM, C0);
       run_chunk(t0 + TM, C1);
     }
   }
+  if (A.first)
+    for (int d = 0; d < DIM; d++) lq[d] = q >= 0 ? A.lam[q * DIM + d] : 0.0;
   for (int off = L / 2; off >= 1; off >>= 1)
     for (int d = 0; d < DIM; d++) F[d] += __shfl_xor(F[d], off, WAVE);
   if (!valid) return;
