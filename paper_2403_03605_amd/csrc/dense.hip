@@ -5,13 +5,16 @@
 // with a tile-parallel symmetric GEMV whose partial sums are combined in a
 // fixed order.
 //
-// Inversion: the symmetric sweep operator, one 64-wide pivot block at a time,
-// directly on the packed lower tiles.  Sweeping pivot block K of a symmetric A
-// with P = A_KK^-1:
-//   A_IJ <- A_IJ - A_IK P A_KJ   (I, J != K),
+// Inversion: the symmetric sweep operator, directly on the packed lower tiles.
+// Sweeping pivot block K of a symmetric A with P = A_KK^-1:
+//   A_IJ <- A_IJ - A_IK P A_KJ   (I, J not in K),
 //   A_IK <- A_IK P,  A_KJ <- P A_KJ,  A_KK <- -P,
 // keeps A symmetric, so only the lower tiles are touched; sweeping every block
-// leaves -A^-1.  The rank-64 updates run on the FP64 matrix cores.
+// leaves -A^-1.  Sweeping a block equals sweeping its parts one after another,
+// so the pivot blocks are four tiles (256) wide: the diagonal block is swept
+// tile by tile on its own ten tiles (which leaves -P there), and then one
+// rank-256 update on the FP64 matrix cores passes over the whole matrix -- a
+// quarter of the memory traffic of 64-wide pivots for the same flops.
 #include "internal.h"
 
 #include <algorithm>
@@ -134,12 +137,12 @@ __device__ inline void mfma_rows(d4 acc[4], const double (*X)[TS + 1], const dou
   }
 }
 
-// Panel of pivot block k: V_I = A_Ik (from tile (I, k) or the transpose of
-// tile (k, I)) and W_I = V_I P, one workgroup per tile row I.
+// Panel of pivot tile k: V_I = A_Ik (from tile (I, k) or the transpose of
+// tile (k, I)) and W_I = V_I P, one workgroup per tile row I = r0 + block.
 __global__ __launch_bounds__(256) void k_sweep_panel(const double *packed, int64_t k, const double *P, double *V,
-                                                    double *W) {
+                                                    double *W, int64_t r0) {
   __shared__ double Vs[TS][TS + 1], Ps[TS][TS + 1];
-  const int64_t I = blockIdx.x;
+  const int64_t I = r0 + blockIdx.x;
   const bool below = I >= k;
   load_tile(Vs, packed + (below ? tile_index(I, k) : tile_index(k, I)) * TS * TS, !below);
   load_tile(Ps, P, false);
@@ -161,16 +164,17 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const double *packed, int64
     }
 }
 
-// Sweep of pivot block k over every lower tile (one workgroup per tile).
+// Sweep of pivot tile k over the lower tiles of the diagonal block that starts
+// at tile k0 (one workgroup per tile; tile index local to that block).
 // Interior tiles: A_IJ -= W_I V_J^T on the matrix cores with the operands read
 // straight from the (cache-resident) panels: lane group lk of a wavefront
 // supplies the reduction indices 16 lk .. 16 lk + 15 (a permutation of the
 // 64-term sums, so each lane reads contiguous 128-byte runs), no LDS.
 __global__ __launch_bounds__(256) void k_sweep_update(double *packed, int64_t k, const double *P, const double *V,
-                                                     const double *W) {
-  const int64_t tile = blockIdx.x;
-  const int64_t I = tile_row(tile), J = tile - I * (I + 1) / 2;
-  double *A = packed + tile * TS * TS;
+                                                     const double *W, int64_t k0) {
+  const int64_t li = tile_row(blockIdx.x);
+  const int64_t I = k0 + li, J = k0 + (int64_t)blockIdx.x - li * (li + 1) / 2;
+  double *A = packed + tile_index(I, J) * TS * TS;
   if (I == k || J == k) {
     // pivot row / column / diagonal: -P, W_I, or W_J^T
     const double *src = (I == k && J == k) ? P : (J == k ? W + I * TS * TS : W + J * TS * TS);
@@ -218,6 +222,125 @@ __global__ __launch_bounds__(256) void k_sweep_update(double *packed, int64_t k,
 #pragma unroll
       for (int t = 0; t < 4; t++)
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 * hh + s2], b[t][s2], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) A[(16 * w + 4 * g + lk) * TS + 16 * t + lr] = acc[t][g];
+}
+
+// Dense 256 x 256 (row stride KB) multiplier block of the current pivot block:
+// Pb = -(swept diagonal block) = A_KK^-1, both triangles from the lower tiles.
+constexpr int NB = 4;         // tiles per pivot block
+constexpr int KB = NB * TS;   // pivot block width
+__global__ void k_pblock(const double *packed, int64_t k0, int nb, double *Pb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int K = nb * TS;
+  if (e >= K * K) return;
+  const int r = e / K, c = e % K;
+  const int hi = r > c ? r : c, lo = r > c ? c : r;
+  const double *t = packed + tile_index(k0 + hi / TS, k0 + lo / TS) * TS * TS;
+  Pb[r * KB + c] = -t[(hi % TS) * TS + lo % TS];
+}
+
+// Panel of pivot block K = tiles k0 .. k0 + nb - 1 for tile row I (not in K):
+// V_I = A_IK (64 x 64 nb, row stride KB) and the column tile c of W_I = V_I Pb.
+// Grid (T, nb): workgroup (I, c) accumulates over the nb tiles of K on MFMA.
+__global__ __launch_bounds__(256) void k_block_panel(const double *packed, int64_t k0, int nb, const double *Pb,
+                                                    double *V, double *W) {
+  __shared__ double Vs[TS][TS + 1], Ps[TS][TS + 1];
+  const int64_t I = blockIdx.x;
+  const int c = blockIdx.y;
+  if (I >= k0 && I < k0 + nb) return;  // uniform per workgroup
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < nb; kk++) {
+    const int64_t k = k0 + kk;
+    const bool below = I > k;
+    __syncthreads();  // the previous step's tiles are no longer read
+    load_tile(Vs, packed + (below ? tile_index(I, k) : tile_index(k, I)) * TS * TS, !below);
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) Ps[e / TS][e % TS] = Pb[(kk * TS + e / TS) * KB + c * TS + e % TS];
+    __syncthreads();
+    mfma_rows<false>(acc, Vs, Ps, 1.0);
+    if (kk == c)  // V_I's column tile c
+      for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) V[(I * TS + e / TS) * KB + c * TS + e % TS] = Vs[e / TS][e % TS];
+  }
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) W[(I * TS + 16 * w + 4 * g + lk) * KB + c * TS + 16 * t + lr] = acc[t][g];
+}
+
+// Sweep of pivot block K = tiles k0 .. k0 + nb - 1 over every lower tile:
+//   I, J not in K: A_IJ -= W_I V_J^T (rank 64 nb, on MFMA);
+//   J in K:        A_IJ <- column tile of W_I;
+//   I in K:        A_IJ <- transpose of a column tile of W_J;
+//   I, J in K:     unchanged (the diagonal sweep left -P there).
+__global__ __launch_bounds__(256, 4) void k_block_update(double *packed, int64_t k0, int nb, const double *V,
+                                                     const double *W) {
+  const int64_t tile = blockIdx.x;
+  const int64_t I = tile_row(tile), J = tile - I * (I + 1) / 2;
+  const int64_t k1 = k0 + nb;
+  const bool iin = I >= k0 && I < k1, jin = J >= k0 && J < k1;
+  if (iin && jin) return;
+  double *A = packed + tile * TS * TS;
+  if (iin || jin) {
+    // J in K (then I >= k1): W_I's column tile J - k0; I in K (then J < k0): W_J's column tile I - k0, transposed
+    const double *src = jin ? W + I * TS * KB + (J - k0) * TS : W + J * TS * KB + (I - k0) * TS;
+    for (int e = threadIdx.x; e < TS * TS; e += blockDim.x) {
+      const int r = e / TS, c = e % TS;
+      A[e] = jin ? src[r * KB + c] : src[c * KB + r];
+    }
+    return;
+  }
+  // V_J's 64-column chunks pass through LDS once per workgroup (all four
+  // wavefronts need all of V_J); each wavefront reads its own 16 rows of W_I.
+  __shared__ double Vs[TS][TS + 2];  // row stride keeps 16-byte alignment
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) acc[t][g] = A[(16 * w + 4 * g + lk) * TS + 16 * t + lr];
+#pragma unroll 1
+  for (int kk = 0; kk < nb; kk++) {
+    if (kk) __syncthreads();  // the previous chunk is no longer read
+    {
+      const int r = threadIdx.x >> 2, c0 = (threadIdx.x & 3) * 16;
+      const double2 *src = reinterpret_cast<const double2 *>(V + (J * TS + r) * KB + kk * TS + c0);
+#pragma unroll
+      for (int q = 0; q < 8; q++) *reinterpret_cast<double2 *>(&Vs[r][c0 + 2 * q]) = src[q];
+    }
+    const double2 *wrow = reinterpret_cast<const double2 *>(W + (I * TS + 16 * w + lr) * KB + kk * TS + 16 * lk);
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const double2 v = wrow[q];
+      a[2 * q] = -v.x;
+      a[2 * q + 1] = -v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int hh = 0; hh < 2; hh++) {
+      double b[4][8];
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const double2 v = *reinterpret_cast<const double2 *>(&Vs[16 * t + lr][16 * lk + 8 * hh + 2 * q]);
+          b[t][2 * q] = v.x;
+          b[t][2 * q + 1] = v.y;
+        }
+#pragma unroll
+      for (int s2 = 0; s2 < 8; s2++)
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[8 * hh + s2], b[t][s2], acc[t], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int t = 0; t < 4; t++)
@@ -341,9 +464,10 @@ void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps)
   B.colpart = ar.alloc<double>((size_t)B.n_tiles * TS);
   {
     const int64_t Tm = (B.n_max + TS - 1) / TS;
-    B.pv = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * TS);
-    B.pw = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * TS);
+    B.pv = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * KB);
+    B.pw = ar.alloc<double>((size_t)std::max<int64_t>(Tm, 1) * TS * KB);
     B.pinv = ar.alloc<double>((size_t)TS * TS);
+    B.pblk = ar.alloc<double>((size_t)KB * KB);
   }
   std::vector<int32_t> rc, rb;
   for (int64_t c = 0; c < B.n_comp; c++) {
@@ -378,12 +502,24 @@ void sym_blocks_build(Solver &s) {
     tb += ntile;
     k_pack_lower<<<(unsigned)((ntile * TS * TS + 255) / 256), 256, 0, st>>>(s.H, s.nl, B.idx + B.h_off[c], n, T, pk);
     MTS_LAUNCH_CHECK();
-    for (int64_t k = 0; k < T; k++) {
-      k_tile_inverse<<<1, 256, 0, st>>>(pk, k, n, B.pinv);
+    for (int64_t k0 = 0; k0 < T; k0 += NB) {
+      const int nb = (int)std::min<int64_t>(NB, T - k0);
+      // the diagonal block, tile by tile (leaves -A_KK^-1 there)
+      for (int64_t k = k0; k < k0 + nb; k++) {
+        k_tile_inverse<<<1, 256, 0, st>>>(pk, k, n, B.pinv);
+        MTS_LAUNCH_CHECK();
+        k_sweep_panel<<<(unsigned)nb, 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw, k0);
+        MTS_LAUNCH_CHECK();
+        k_sweep_update<<<(unsigned)(nb * (nb + 1) / 2), 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw, k0);
+        MTS_LAUNCH_CHECK();
+      }
+      if (nb == T) break;  // one block: done
+      // the rest of the matrix, one rank-64 nb update
+      k_pblock<<<(unsigned)((nb * TS * nb * TS + 255) / 256), 256, 0, st>>>(pk, k0, nb, B.pblk);
       MTS_LAUNCH_CHECK();
-      k_sweep_panel<<<(unsigned)T, 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw);
+      k_block_panel<<<dim3((unsigned)T, (unsigned)nb), 256, 0, st>>>(pk, k0, nb, B.pblk, B.pv, B.pw);
       MTS_LAUNCH_CHECK();
-      k_sweep_update<<<(unsigned)ntile, 256, 0, st>>>(pk, k, B.pinv, B.pv, B.pw);
+      k_block_update<<<(unsigned)ntile, 256, 0, st>>>(pk, k0, nb, B.pv, B.pw);
       MTS_LAUNCH_CHECK();
     }
     // the sweep leaves -H^-1

@@ -186,8 +186,9 @@ struct Solver {
     int64_t *tile_base = nullptr;   // per component: first tile
     double *packed = nullptr;       // n_tiles * 4096
     double *rowpart = nullptr, *colpart = nullptr;  // n_tiles * 64
-    double *pv = nullptr, *pw = nullptr;  // sweep panels, one 64 x 64 tile per tile row
+    double *pv = nullptr, *pw = nullptr;  // sweep panels, 64 x 256 per tile row
     double *pinv = nullptr;         // inverse of the current pivot tile
+    double *pblk = nullptr;         // inverse of the current 256-wide pivot block
     int64_t n_rows = 0;             // block rows over all components
     int32_t *row_comp = nullptr, *row_block = nullptr;
   } sym;
