@@ -121,10 +121,11 @@ __global__ void k_set_cidx(const int32_t *cn, int64_t nc, int32_t *cidx) {
   if (q < nc) cidx[cn[q]] = (int32_t)q;
 }
 
-// H[(q, d'), (p, dir)] = Wv_b[d'][node q] for the loaded constraint p of RHS b
-// that owns q (the only loaded node whose response can reach q).
+// H[(q, d'), (p, dir)] = velocity d' of RHS b at node q (responses node-major,
+// [N][nrhs][dim]) for the loaded constraint p of RHS b that owns q (the only
+// loaded node whose response can reach q).
 __global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32_t *cn, const int32_t *owner,
-                          const int32_t *rhs_color, const int32_t *rhs_dir, const double *Wv, int64_t N, double *H) {
+                          const int32_t *rhs_color, const int32_t *rhs_dir, const double *Wv, double *H) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
   int64_t node = cn[q];
@@ -134,7 +135,7 @@ __global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32
     int32_t p = owner[(int64_t)c * nc + q];
     if (p < 0) continue;
     for (int d = 0; d < dim; d++)
-      H[(q * dim + d) * nl + (int64_t)p * dim + rhs_dir[b]] = Wv[((int64_t)b * dim + d) * N + node];
+      H[(q * dim + d) * nl + (int64_t)p * dim + rhs_dir[b]] = Wv[(node * nrhs + b) * dim + d];
   }
 }
 
@@ -415,32 +416,30 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   sell_regather_mask(s, s.rsell, full_mask);
   MTS_HIP(hipMemsetAsync(s.H, 0, sizeof(double) * nl * nl, st));
   const int cpb = s.nrhs / dim;  // colours per batch
-  int32_t rc[16], rd[16];
-  int32_t *drc = nullptr, *drd = nullptr;
-  if (!s.rhs_color_dev) {
-    s.rhs_color_dev = s.arena.alloc<int32_t>(16);
-    s.rhs_dir_dev = s.arena.alloc<int32_t>(16);
-  }
-  drc = s.rhs_color_dev;
-  drd = s.rhs_dir_dev;
-  for (int64_t c0 = 0; c0 < s.n_colors; c0 += cpb) {
+  const int64_t nbatch = (s.n_colors + cpb - 1) / cpb;
+  // colour and direction of every RHS of every batch, copied once
+  std::vector<int32_t> rcd((size_t)std::max<int64_t>(nbatch, 1) * 32, -1);
+  for (int64_t bt = 0; bt < nbatch; bt++)
     for (int b = 0; b < s.nrhs; b++) {
-      int64_t c = c0 + b / dim;
-      rc[b] = c < s.n_colors ? (int32_t)c : -1;
-      rd[b] = b % dim;
+      const int64_t c = bt * cpb + b / dim;
+      rcd[bt * 32 + b] = c < s.n_colors ? (int32_t)c : -1;
+      rcd[bt * 32 + 16 + b] = b % dim;
     }
+  int32_t *drcd = s.arena.alloc<int32_t>(rcd.size());
+  MTS_HIP(hipMemcpyAsync(drcd, rcd.data(), sizeof(int32_t) * rcd.size(), hipMemcpyHostToDevice, st));
+  for (int64_t bt = 0; bt < nbatch; bt++) {
+    const int32_t *rc = &rcd[bt * 32], *rd = &rcd[bt * 32 + 16];
     int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
     for (int j = 1; j <= s.m; j++) {
       link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.ccolor, rc, rd, s.nrhs);
       k ^= 1;
     }
-    MTS_HIP(hipMemcpyAsync(drc, rc, sizeof(rc), hipMemcpyHostToDevice, st));
-    MTS_HIP(hipMemcpyAsync(drd, rd, sizeof(rd), hipMemcpyHostToDevice, st));
-    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drc, drd, s.Wv, s.N, s.H);
+    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drcd + bt * 32, drcd + bt * 32 + 16,
+                                        s.Wv, s.H);
     MTS_LAUNCH_CHECK();
-    // the host arrays rc/rd are reused next iteration
-    MTS_HIP(hipStreamSynchronize(st));
   }
+  MTS_HIP(hipStreamSynchronize(st));  // before the host colour table goes away
+  s.arena.release(drcd);
   dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
   k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
                                 s.p.fe_n[1], s.H);

@@ -202,7 +202,6 @@ struct Solver {
   int32_t *ccolor = nullptr;     // colour of each constraint
   int32_t *owner = nullptr;      // n_colors * nc: loaded constraint of that colour reaching q, or -1
   int nrhs = 8;
-  int32_t *rhs_color_dev = nullptr, *rhs_dir_dev = nullptr;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)
   int32_t *pinned_flag = nullptr;  // 2 slots, host-pinned

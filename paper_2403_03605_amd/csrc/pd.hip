@@ -402,20 +402,20 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep_batch(const SubstepEntry 
 //
 // Unit-load responses (setup and rebuild): NRHS right-hand sides share one pass
 // over the bond data; RHS b loads (j/m) e_dir(b) at every constraint node of
-// colour(b).
+// colour(b).  The responses are node-major, [N][NRHS][DIM], so a neighbour's
+// NRHS x DIM values are one contiguous run of 16-byte loads.
 struct LinkArgs {
-  const double *x;
+  const double *xrec;     // node records [x, u] of the free problem (x part read)
   int64_t N, n_rows, n_slices;
   int T;
-  const int32_t *rows, *width, *slice_layer;
+  const int32_t *rows, *slice_layer;
   int jmax;               // rows farther than jmax horizons still hold exact zeros
-  const int64_t *slot_off, *word_off;
   const int32_t *col;
   const double *coef;
   const uint64_t *mask;
   const double *mass;
   const double *u_in;
-  double *u_out, *v, *a;  // [NRHS][DIM][N]
+  double *u_out, *v, *a;  // [N][NRHS][DIM]
   const int32_t *cidx;
   const int32_t *ccolor;  // colour of each constraint
   int32_t rhs_color[16];
@@ -426,71 +426,86 @@ struct LinkArgs {
 
 template <int DIM, int NRHS, int L>
 __device__ __forceinline__ void link_body(const LinkArgs &A, const Params &P, const int64_t slice) {
-  constexpr int S = WAVE / L;
+  constexpr int S = WAVE / L, C = NRHS * DIM;  // C: values per node (even)
+  static_assert(C % 2 == 0, "responses are loaded in pairs");
   const int lane = threadIdx.x & (WAVE - 1);
   const int jl = lane / L, l = lane % L;
   const int64_t r = slice * S + jl;
   const bool valid = r < A.n_rows;
-  const int64_t N = A.N;
   const int64_t i = valid ? A.rows[r] : A.rows[0];
-  const int64_t stride = (int64_t)DIM * N;
   if (A.slice_layer[slice] > A.jmax) {  // uniform per wavefront
     // the response has not reached these rows yet: it is exactly zero
     if (!valid) return;
-    for (int b = 0; b < NRHS; b++)
-      for (int d = 0; d < DIM; d++) {
-        if ((b * DIM + d) % L != l) continue;
-        const int64_t tix = b * stride + d * N + i;
-        A.u_out[tix] = 0.0;
-        if (A.first) {
-          A.v[tix] = 0.0;
-          A.a[tix] = 0.0;
-        }
+    for (int e = l; e < C; e += L) {
+      A.u_out[i * C + e] = 0.0;
+      if (A.first) {
+        A.v[i * C + e] = 0.0;
+        A.a[i * C + e] = 0.0;
       }
+    }
     return;
   }
   const int T = A.T;
   const int64_t wo = slice * T, so = wo * WAVE;
-  double xi_[DIM], ui_[NRHS][DIM];
-  for (int d = 0; d < DIM; d++) xi_[d] = A.x[d * N + i];
-  for (int b = 0; b < NRHS; b++)
-    for (int d = 0; d < DIM; d++) ui_[b][d] = A.first ? 0.0 : A.u_in[b * stride + d * N + i];
-  double F[NRHS][DIM];
-  for (int b = 0; b < NRHS; b++)
-    for (int d = 0; d < DIM; d++) F[b][d] = 0.0;
+  double xi_[DIM], ui_[C];
+  for (int d = 0; d < DIM; d++) xi_[d] = A.xrec[i * 2 * DIM + d];
+  {
+    const double2 *src = reinterpret_cast<const double2 *>(A.u_in + i * C);
+#pragma unroll
+    for (int e = 0; e < C / 2; e++) {
+      const double2 v2 = A.first ? double2{0.0, 0.0} : src[e];
+      ui_[2 * e] = v2.x;
+      ui_[2 * e + 1] = v2.y;
+    }
+  }
+  double F[C];
+#pragma unroll
+  for (int e = 0; e < C; e++) F[e] = 0.0;
   for (int t = 0; t < (A.first ? 0 : T); t++) {  // no bond forces from a response at rest
     const int64_t pos = so + (int64_t)t * WAVE + lane;
     if (!((A.mask[wo + t] >> lane) & 1ull)) continue;
     const int64_t c = A.col[pos];
     const double cf = A.coef[pos];
+    double xk[DIM], uk[C];
+    for (int d = 0; d < DIM; d++) xk[d] = A.xrec[c * 2 * DIM + d];
+    const double2 *src = reinterpret_cast<const double2 *>(A.u_in + c * C);
+#pragma unroll
+    for (int e = 0; e < C / 2; e++) {
+      const double2 v2 = src[e];
+      uk[2 * e] = v2.x;
+      uk[2 * e + 1] = v2.y;
+    }
     double xi[DIM];
-    for (int d = 0; d < DIM; d++) xi[d] = A.x[d * N + c] - xi_[d];
+    for (int d = 0; d < DIM; d++) xi[d] = xk[d] - xi_[d];
+#pragma unroll
     for (int b = 0; b < NRHS; b++) {
-      double xe = xi[0] * (A.u_in[b * stride + c] - ui_[b][0]) + xi[1] * (A.u_in[b * stride + N + c] - ui_[b][1]);
-      if (DIM == 3) xe = xe + xi[2] * (A.u_in[b * stride + 2 * N + c] - ui_[b][2]);
+      double xe = xi[0] * (uk[b * DIM] - ui_[b * DIM]) + xi[1] * (uk[b * DIM + 1] - ui_[b * DIM + 1]);
+      if (DIM == 3) xe = xe + xi[2] * (uk[b * DIM + 2] - ui_[b * DIM + 2]);
       const double tt = cf * xe;
-      for (int d = 0; d < DIM; d++) F[b][d] += tt * xi[d];
+      for (int d = 0; d < DIM; d++) F[b * DIM + d] += tt * xi[d];
     }
   }
   for (int off = L / 2; off >= 1; off >>= 1)
-    for (int b = 0; b < NRHS; b++)
-      for (int d = 0; d < DIM; d++) F[b][d] += __shfl_xor(F[b][d], off, WAVE);
+#pragma unroll
+    for (int e = 0; e < C; e++) F[e] += __shfl_xor(F[e], off, WAVE);
   if (!valid) return;
   const int32_t q = A.cidx[i];
   const double m_i = A.mass[i];
-  for (int b = 0; b < NRHS; b++)
-    for (int d = 0; d < DIM; d++) {
-      if ((b * DIM + d) % L != l) continue;
-      const int64_t tix = b * stride + d * N + i;
-      double fl = F[b][d];
-      if (q >= 0 && A.ccolor[q] == A.rhs_color[b] && d == A.rhs_dir[b]) fl = fl + A.lfac;
-      const double an = fl / m_i;
-      const double v0 = A.first ? 0.0 : A.v[tix], a0 = A.first ? 0.0 : A.a[tix];
-      const double vn = v0 + P.hdtP * (a0 + an);
-      A.a[tix] = an;
-      A.v[tix] = vn;
-      A.u_out[tix] = (ui_[b][d] + P.dtP * vn) + P.hdt2P * an;
-    }
+  const int32_t qc = q >= 0 ? A.ccolor[q] : -1;
+#pragma unroll
+  for (int e = 0; e < C; e++) {
+    if (e % L != l) continue;
+    const int b = e / DIM, d = e % DIM;
+    const int64_t tix = i * C + e;
+    double fl = F[e];
+    if (qc >= 0 && qc == A.rhs_color[b] && d == A.rhs_dir[b]) fl = fl + A.lfac;
+    const double an = fl / m_i;
+    const double v0 = A.first ? 0.0 : A.v[tix], a0 = A.first ? 0.0 : A.a[tix];
+    const double vn = v0 + P.hdtP * (a0 + an);
+    A.a[tix] = an;
+    A.v[tix] = vn;
+    A.u_out[tix] = (ui_[e] + P.dtP * vn) + P.hdt2P * an;
+  }
 }
 
 template <int DIM, int NRHS, int L>
@@ -817,22 +832,19 @@ static void launch_link(Solver &s, LinkArgs &A) {
 }
 
 // One substep j of the unit-load responses over the region rows.
-// u_in/u_out/v/a: [nrhs][dim][N].
+// u_in/u_out/v/a: [N][nrhs][dim].
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
                   const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs) {
   if (!s.rsell.n_rows) return;
   LinkArgs A{};
-  A.x = s.x;
+  A.xrec = s.xu[0];
   A.N = s.N;
   A.n_rows = s.rsell.n_rows;
   A.n_slices = s.rsell.n_slices;
   A.T = s.rsell.T;
   A.rows = s.rsell.rows;
-  A.width = s.rsell.width;
   A.slice_layer = s.rsell.slice_layer;
   A.jmax = j - 1;
-  A.slot_off = s.rsell.slot_off;
-  A.word_off = s.rsell.word_off;
   A.col = s.rsell.col;
   A.coef = s.rsell.coef;
   A.mask = s.rsell.mask;
