@@ -353,48 +353,66 @@ __global__ void k_negate(double *a, int64_t n) {
   if (i < n) a[i] = -a[i];
 }
 
-// One workgroup per tile: row partial A_IJ x_J (for block row I) and, off the
-// diagonal, column partial A_IJ^T x_I (for block row J).  Four threads share a
-// row (or column), 16 products each, combined by a fixed butterfly.
+// Row partial A_IJ x_J (for block row I) and, off the diagonal, column
+// partial A_IJ^T x_I (for block row J) of every packed tile.  Four threads
+// share a row (or column), 16 products each, combined by a fixed butterfly.
+// Each workgroup walks tiles with the grid stride and keeps the next tile's
+// entries and multiplier values in flight while it reduces the current one
+// from LDS (the result of each tile does not depend on the walk).
 __global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
                                                    const int64_t *off, const int32_t *idx, const double *r,
-                                                   double *rowpart, double *colpart) {
+                                                   int64_t n_tiles, double *rowpart, double *colpart) {
   __shared__ double A[TS][TS + 1];
   __shared__ double xI[TS], xJ[TS];
-  const int64_t tile = blockIdx.x;
-  const int comp = tile_meta[tile * 3 + 0], I = tile_meta[tile * 3 + 1], J = tile_meta[tile * 3 + 2];
-  const int64_t base = off[comp], n = off[comp + 1] - off[comp];
-  const double2 *src = reinterpret_cast<const double2 *>(packed + tile * TS * TS);
   const int t = threadIdx.x;
+  int64_t tile = blockIdx.x;
+  if (tile >= n_tiles) return;  // uniform per workgroup
   double2 v[8];
+  double xi = 0.0, xj = 0.0;
+  // entries of tile `tl` and, for threads < 64, its multiplier values
+  auto fetch = [&](int64_t tl) {
+    const double2 *src = reinterpret_cast<const double2 *>(packed + tl * TS * TS);
 #pragma unroll
-  for (int q = 0; q < 8; q++) v[q] = src[q * 256 + t];
-  if (t < TS) {
-    int64_t gi = (int64_t)I * TS + t, gj = (int64_t)J * TS + t;
-    xI[t] = gi < n ? r[idx[base + gi]] : 0.0;
-    xJ[t] = gj < n ? r[idx[base + gj]] : 0.0;
-  }
+    for (int q = 0; q < 8; q++) v[q] = src[q * 256 + t];
+    if (t < TS) {
+      const int comp = tile_meta[tl * 3 + 0], I = tile_meta[tl * 3 + 1], J = tile_meta[tl * 3 + 2];
+      const int64_t base = off[comp], n = off[comp + 1] - base;
+      const int64_t gi = (int64_t)I * TS + t, gj = (int64_t)J * TS + t;
+      xi = gi < n ? r[idx[base + gi]] : 0.0;
+      xj = gj < n ? r[idx[base + gj]] : 0.0;
+    }
+  };
+  fetch(tile);
+  for (; tile < n_tiles; tile += gridDim.x) {
+    const bool diag = tile_meta[tile * 3 + 1] == tile_meta[tile * 3 + 2];
+    if (t < TS) {
+      xI[t] = xi;
+      xJ[t] = xj;
+    }
 #pragma unroll
-  for (int q = 0; q < 8; q++) {
-    const int e = 2 * (q * 256 + t);
-    A[e / TS][e % TS] = v[q].x;
-    A[e / TS][e % TS + 1] = v[q].y;
-  }
-  __syncthreads();
-  const int line = t >> 2, part = t & 3;
-  double rs = 0.0, cs = 0.0;
+    for (int q = 0; q < 8; q++) {
+      const int e = 2 * (q * 256 + t);
+      A[e / TS][e % TS] = v[q].x;
+      A[e / TS][e % TS + 1] = v[q].y;
+    }
+    __syncthreads();
+    if (tile + gridDim.x < n_tiles) fetch(tile + gridDim.x);  // registers are free again
+    const int line = t >> 2, part = t & 3;
+    double rs = 0.0, cs = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; k++) {
-    rs += A[line][part * 16 + k] * xJ[part * 16 + k];
-    cs += A[part * 16 + k][line] * xI[part * 16 + k];
-  }
-  rs += __shfl_xor(rs, 1, WAVE);
-  rs += __shfl_xor(rs, 2, WAVE);
-  cs += __shfl_xor(cs, 1, WAVE);
-  cs += __shfl_xor(cs, 2, WAVE);
-  if (part == 0) {
-    rowpart[tile * TS + line] = rs;
-    if (I != J) colpart[tile * TS + line] = cs;
+    for (int k = 0; k < 16; k++) {
+      rs += A[line][part * 16 + k] * xJ[part * 16 + k];
+      cs += A[part * 16 + k][line] * xI[part * 16 + k];
+    }
+    rs += __shfl_xor(rs, 1, WAVE);
+    rs += __shfl_xor(rs, 2, WAVE);
+    cs += __shfl_xor(cs, 1, WAVE);
+    cs += __shfl_xor(cs, 2, WAVE);
+    if (part == 0) {
+      rowpart[tile * TS + line] = rs;
+      if (!diag) colpart[tile * TS + line] = cs;
+    }
+    __syncthreads();  // LDS is rewritten for the next tile
   }
 }
 
@@ -533,8 +551,9 @@ void sym_blocks_build(Solver &s) {
 void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   auto &B = s.sym;
   if (!B.n_tiles) return;
-  k_sym_tiles<<<(unsigned)B.n_tiles, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.rowpart,
-                                                         B.colpart);
+  // a few resident workgroups per CU, each walking tiles
+  const unsigned g = (unsigned)std::min<int64_t>(B.n_tiles, 256 * 4);
+  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.n_tiles, B.rowpart, B.colpart);
   MTS_LAUNCH_CHECK();
   k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
                                                         B.rowpart, B.colpart, y, y2);

@@ -224,9 +224,10 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
     }
 #pragma unroll
     for (int q = 0; q < TM; q++) {
-      const bool live = t0 + q < T;  // wave-uniform
-      const uint64_t word = live ? C.w[q] : 0ull;
+      if (t0 + q >= T) break;  // wave-uniform: the rest of the chunk lies past the slice
+      const uint64_t word = C.w[q];
       bool bit = (word & lanebit) != 0ull;
+      bool cut = false;  // this lane's bond broke in this iteration
       if (bit) {
         if constexpr (!MX) {
           const R cf = __longlong_as_double((long long)(((uint64_t)C.f1[q] << 32) | C.f0[q]));
@@ -248,6 +249,7 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
             if (breaks(r2, y2, P.K2, P.scrit)) {  // Eq. 3-4
               bit = false;
               broke = 1;
+              cut = true;
             }
           }
           if (bit) {
@@ -277,6 +279,7 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
             if (__builtin_fmaf(2.0f, xe, ee) >= P.K2m1f * r2) {
               bit = false;
               broke = 1;
+              cut = true;
             }
           }
           if (bit) {
@@ -286,9 +289,10 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
           }
         }
       }
-      if (live) {
+      // bits only ever clear, so the word changes exactly when a lane cut a bond
+      if (__any(cut)) {
         const uint64_t nw = __ballot(bit);
-        if (nw != word && lane == 0) A.mask[wo + t0 + q] = nw;
+        if (lane == 0) A.mask[wo + t0 + q] = nw;
       }
     }
   };
