@@ -354,65 +354,73 @@ __global__ void k_negate(double *a, int64_t n) {
 }
 
 // Row partial A_IJ x_J (for block row I) and, off the diagonal, column
-// partial A_IJ^T x_I (for block row J) of every packed tile.  Four threads
-// share a row (or column), 16 products each, combined by a fixed butterfly.
-// Each workgroup walks tiles with the grid stride and keeps the next tile's
-// entries and multiplier values in flight while it reduces the current one
-// from LDS (the result of each tile does not depend on the walk).
-__global__ __launch_bounds__(256) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
+// partial A_IJ^T x_I (for block row J) of every packed tile, one wavefront per
+// tile, from registers (no workgroup barrier).  Load q of lane l brings
+// entries (2q + h, c0) and (2q + h, c0 + 1), h = l / 32, c0 = 2 (l % 32); the
+// tile is taken in quarters of 8 loads.  Column sums accumulate in the
+// lane and pair up across h; each row's 32 two-entry products are summed over
+// its half-wavefront by recursive halving (a fixed order: deterministic).
+__device__ __forceinline__ double pick(bool hi, double a, double b) { return hi ? b : a; }
+
+__global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
                                                    const int64_t *off, const int32_t *idx, const double *r,
                                                    int64_t n_tiles, double *rowpart, double *colpart) {
-  __shared__ double A[TS][TS + 1];
-  __shared__ double xI[TS], xJ[TS];
-  const int t = threadIdx.x;
-  int64_t tile = blockIdx.x;
-  if (tile >= n_tiles) return;  // uniform per workgroup
-  double2 v[8];
-  double xi = 0.0, xj = 0.0;
-  // entries of tile `tl` and, for threads < 64, its multiplier values
-  auto fetch = [&](int64_t tl) {
-    const double2 *src = reinterpret_cast<const double2 *>(packed + tl * TS * TS);
+  __shared__ double xs[4][2][TS];  // per wavefront: x_I, x_J
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int h = lane >> 5, c0 = 2 * (lane & 31);
+  const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t tile = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + w)); tile < n_tiles; tile += stride) {
+    const double2 *src = reinterpret_cast<const double2 *>(packed + tile * TS * TS);
+    double2 e[8];
 #pragma unroll
-    for (int q = 0; q < 8; q++) v[q] = src[q * 256 + t];
-    if (t < TS) {
-      const int comp = tile_meta[tl * 3 + 0], I = tile_meta[tl * 3 + 1], J = tile_meta[tl * 3 + 2];
-      const int64_t base = off[comp], n = off[comp + 1] - base;
-      const int64_t gi = (int64_t)I * TS + t, gj = (int64_t)J * TS + t;
-      xi = gi < n ? r[idx[base + gi]] : 0.0;
-      xj = gj < n ? r[idx[base + gj]] : 0.0;
+    for (int q = 0; q < 8; q++) e[q] = src[q * WAVE + lane];
+    const int comp = tile_meta[tile * 3 + 0], I = tile_meta[tile * 3 + 1], J = tile_meta[tile * 3 + 2];
+    const int64_t base = off[comp], n = off[comp + 1] - base;
+    {
+      const int64_t gi = (int64_t)I * TS + lane, gj = (int64_t)J * TS + lane;
+      const double xi = gi < n ? r[idx[base + gi]] : 0.0;
+      const double xj = gj < n ? r[idx[base + gj]] : 0.0;
+      // the previous tile's reads of xs are done before it is rewritten
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      xs[w][0][lane] = xi;
+      xs[w][1][lane] = xj;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-  };
-  fetch(tile);
-  for (; tile < n_tiles; tile += gridDim.x) {
-    const bool diag = tile_meta[tile * 3 + 1] == tile_meta[tile * 3 + 2];
-    if (t < TS) {
-      xI[t] = xi;
-      xJ[t] = xj;
-    }
+    const double xj0 = xs[w][1][c0], xj1 = xs[w][1][c0 + 1];
+    double cs0 = 0.0, cs1 = 0.0;
+#pragma unroll 1
+    for (int qt = 0; qt < 4; qt++) {  // quarters of 8 loads (16 rows)
+      double p[8];
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const int e = 2 * (q * 256 + t);
-      A[e / TS][e % TS] = v[q].x;
-      A[e / TS][e % TS + 1] = v[q].y;
-    }
-    __syncthreads();
-    if (tile + gridDim.x < n_tiles) fetch(tile + gridDim.x);  // registers are free again
-    const int line = t >> 2, part = t & 3;
-    double rs = 0.0, cs = 0.0;
+      for (int q = 0; q < 8; q++) {
+        const double xr = xs[w][0][2 * (8 * qt + q) + h];
+        cs0 += e[q].x * xr;
+        cs1 += e[q].y * xr;
+        p[q] = e[q].x * xj0 + e[q].y * xj1;
+      }
+      if (qt < 3) {
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-      rs += A[line][part * 16 + k] * xJ[part * 16 + k];
-      cs += A[part * 16 + k][line] * xI[part * 16 + k];
+        for (int q = 0; q < 8; q++) e[q] = src[(8 * (qt + 1) + q) * WAVE + lane];
+      }
+      // recursive halving over the 32 lanes of the half-wavefront
+      double p4[4], p2[2];
+#pragma unroll
+      for (int k = 0; k < 4; k++) p4[k] = pick(b4, p[k], p[4 + k]) + __shfl_xor(pick(b4, p[4 + k], p[k]), 16, WAVE);
+#pragma unroll
+      for (int k = 0; k < 2; k++) p2[k] = pick(b3, p4[k], p4[2 + k]) + __shfl_xor(pick(b3, p4[2 + k], p4[k]), 8, WAVE);
+      double p1 = pick(b2, p2[0], p2[1]) + __shfl_xor(pick(b2, p2[1], p2[0]), 4, WAVE);
+      p1 += __shfl_xor(p1, 2, WAVE);
+      p1 += __shfl_xor(p1, 1, WAVE);
+      // the four lanes 4k .. 4k + 3 of the half hold row 2 (8 qt + k) + h, k = (lane % 32) / 4
+      if ((lane & 3) == 0) rowpart[tile * TS + 2 * (8 * qt + ((lane & 31) >> 2)) + h] = p1;
     }
-    rs += __shfl_xor(rs, 1, WAVE);
-    rs += __shfl_xor(rs, 2, WAVE);
-    cs += __shfl_xor(cs, 1, WAVE);
-    cs += __shfl_xor(cs, 2, WAVE);
-    if (part == 0) {
-      rowpart[tile * TS + line] = rs;
-      if (!diag) colpart[tile * TS + line] = cs;
-    }
-    __syncthreads();  // LDS is rewritten for the next tile
+    cs0 += __shfl_xor(cs0, 32, WAVE);
+    cs1 += __shfl_xor(cs1, 32, WAVE);
+    if (I != J && h == 0) *reinterpret_cast<double2 *>(colpart + tile * TS + c0) = double2{cs0, cs1};
   }
 }
 
@@ -551,8 +559,8 @@ void sym_blocks_build(Solver &s) {
 void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   auto &B = s.sym;
   if (!B.n_tiles) return;
-  // a few resident workgroups per CU, each walking tiles
-  const unsigned g = (unsigned)std::min<int64_t>(B.n_tiles, 256 * 4);
+  // four tiles per workgroup at a time; up to eight resident workgroups per CU
+  const unsigned g = (unsigned)std::min<int64_t>((B.n_tiles + 3) / 4, 256 * 8);
   k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.n_tiles, B.rowpart, B.colpart);
   MTS_LAUNCH_CHECK();
   k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
