@@ -1,0 +1,81 @@
+"""The bond-pass variants (LDS staging with four- or eight-wavefront
+workgroups, direct gathers, tile-ordered or canonical rows, chunk lengths)
+compute the same sums in the same order, so with the lanes per row fixed they
+give bit-identical trajectories and bond states, including ragged tiles at the
+lattice edges and bonds that break."""
+import os
+
+import numpy as np
+import pytest
+
+import mts_inputs as mi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mts():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_03605_amd as m
+    m.load()
+    return m
+
+
+KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT")
+
+
+def _run(mts, inst, n_macro, env):
+    saved = {k: os.environ.get(k) for k in KNOBS}
+    try:
+        for k in KNOBS:
+            os.environ.pop(k, None)
+        os.environ.update(env)
+        s = mts.Solver(inst)  # the knobs are read when the solver is created
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    mu0 = s.bonds()[2]
+    s.advance(n_macro)
+    out = {q: s.read(q) for q in (mts.PD_U, mts.PD_V, mts.DAMAGE, mts.FE_U)}
+    out["mu"] = s.bonds()[2]
+    s.close()
+    return out, int(((mu0 == 1) & (out["mu"] == 0)).sum())  # bonds broken during the run
+
+
+def _same(a, b):
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_3d_variants_bit_identical(mts, precision):
+    # 12 x 12 x 6 nodes: 8 x 4 x 4 and 4 x 4 x 4 tiles are ragged in x and z
+    inst = mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=42, precision=precision,
+                      name="block12 " + precision)
+    print("case", inst["name"], flush=True)
+    ref, nb = _run(mts, inst, 20, {"MTS_LANES": "4"})
+    assert nb > 0
+    for env in ({"MTS_LANES": "4", "MTS_HALO_WAVES": "8"}, {"MTS_LANES": "4", "MTS_HALO_WAVES": "4"},
+                {"MTS_LANES": "4", "MTS_HALO": "0"}, {"MTS_LANES": "4", "MTS_TILE": "0"}):
+        print("  variant", env, flush=True)
+        got, _ = _run(mts, inst, 20, env)
+        _same(ref, got)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_2d_variants_bit_identical(mts, precision):
+    inst = dict(mi.config(0, precision=precision), name="plate50 " + precision)
+    print("case", inst["name"], flush=True)
+    ref, nb = _run(mts, inst, 50, {"MTS_LANES": "2"})
+    assert nb > 0
+    for env in ({"MTS_LANES": "2", "MTS_HALO": "0"}, {"MTS_LANES": "2", "MTS_HALO": "0", "MTS_PD_VARIANT": "1"},
+                {"MTS_LANES": "2", "MTS_HALO": "0", "MTS_PD_VARIANT": "2"}, {"MTS_LANES": "2", "MTS_HALO_WAVES": "8"},
+                {"MTS_LANES": "2", "MTS_TILE": "0"}):
+        print("  variant", env, flush=True)
+        got, _ = _run(mts, inst, 50, env)
+        _same(ref, got)
