@@ -92,8 +92,10 @@ def test_fullsize_pure_pd_substeps(mts, k, precision):
             g, w = s.read(gq), o.get(oq)
             assert np.abs(w).max() > 0
             if precision == "fp64":
+                print("  max relative difference", _rel(g, w))
                 assert _rel(g, w) <= 1e-10
             else:
+                print("  relative L2 difference", _rel_l2(g, w))
                 assert _rel_l2(g, w) <= 1e-4
     _, _, mug = s.bonds()
     _, _, muo = o.bonds()
