@@ -48,67 +48,88 @@ __global__ void k_pack_lower(const double *H, int64_t nl, const int32_t *idx, in
 }
 
 // P = inverse of the diagonal tile (k, k) (symmetric part), its rows/columns
-// past n padded with the identity.  Gauss-Jordan without pivoting (SPD); thread t keeps the 4 x 4
-// sub-block rows 4 (t / 16) .., columns 4 (t % 16) .. in registers, and the
-// pivot row and column pass through LDS (double-buffered: one barrier a step).
+// past n padded with the identity.  The tile is swept in LDS in four 16-wide
+// sub-pivots (the same sweep operator as the whole matrix, which leaves -A^-1):
+// wavefront 0 inverts the 16 x 16 pivot block by Gauss-Jordan in registers
+// (no pivoting: every pivot block is a Schur complement of an SPD tile, hence
+// SPD), exchanging the pivot row and column with shuffles; then all four
+// wavefronts form the panel W = V B^-1 and update the tile, rank 16.
 __global__ __launch_bounds__(256) void k_tile_inverse(const double *packed, int64_t k, int64_t n, double *P) {
-  __shared__ double rowp[2][TS], colp[2][TS];
-  const int t = threadIdx.x, r0 = (t >> 4) * 4, c0 = (t & 15) * 4;
+  constexpr int SB = 16;  // sub-pivot width
+  __shared__ double M[TS][TS + 1];
+  __shared__ double Vs[TS][SB + 1], Ws[TS][SB + 1], Bi[SB][SB + 1];
+  const int t = threadIdx.x;
   const double *D = packed + tile_index(k, k) * TS * TS;
   const int kb = (int)std::min<int64_t>(TS, n - k * TS);
-  double M[4][4];
+  for (int e = t; e < TS * TS; e += blockDim.x) {
+    const int r = e / TS, c = e % TS;
+    M[r][c] = (r < kb && c < kb) ? D[e] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int r0 = (t >> 4) * 4, c0 = (t & 15) * 4;  // this thread's 4 x 4 block of the tile
+  for (int o = 0; o < TS; o += SB) {
+    if (t < WAVE) {
+      // lane t holds B[br][bc .. bc + 3] of the pivot block B = M[o.., o..]
+      const int br = t >> 2, bc = (t & 3) * 4;
+      double b[4];
 #pragma unroll
-  for (int a = 0; a < 4; a++)
+      for (int j = 0; j < 4; j++) b[j] = M[o + br][o + bc + j];
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int r = r0 + a, c = c0 + b;
-      M[a][b] = (r < kb && c < kb) ? D[r * TS + c] : (r == c ? 1.0 : 0.0);
+      for (int p = 0; p < SB; p++) {
+        double rp[4];  // pivot row p, columns bc .. bc + 3
+#pragma unroll
+        for (int j = 0; j < 4; j++) rp[j] = __shfl(b[j], 4 * p + (t & 3), WAVE);
+        const double cp = __shfl(b[p & 3], 4 * br + (p >> 2), WAVE);   // B[br][p]
+        const double piv = __shfl(b[p & 3], 4 * p + (p >> 2), WAVE);  // B[p][p]
+        const double d = 1.0 / piv;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int c = bc + j;
+          if (br == p) b[j] = (c == p) ? d : rp[j] * d;
+          else if (c == p) b[j] = -cp * d;
+          else b[j] = b[j] - cp * (rp[j] * d);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) Bi[br][bc + j] = b[j];
     }
-  for (int p = 0; p < TS; p++) {
-    const int buf = p & 1;
-    // (constant register indices only: a runtime index would move M to scratch)
+    for (int e = t; e < TS * SB; e += blockDim.x) Vs[e / SB][e % SB] = M[e / SB][o + e % SB];
+    __syncthreads();
+    for (int e = t; e < TS * SB; e += blockDim.x) {
+      const int i = e / SB, kk = e % SB;
+      double w = 0.0;
+#pragma unroll
+      for (int q = 0; q < SB; q++) w += Vs[i][q] * Bi[q][kk];
+      Ws[i][kk] = w;
+    }
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < 4; a++)
-      if (r0 + a == p)
 #pragma unroll
-        for (int b = 0; b < 4; b++) rowp[buf][c0 + b] = M[a][b];
+      for (int bb = 0; bb < 4; bb++) {
+        const int r = r0 + a, c = c0 + bb;
+        const bool rin = r >= o && r < o + SB, cin = c >= o && c < o + SB;
+        double v;
+        if (rin && cin) v = -Bi[r - o][c - o];  // A_KK <- -P
+        else if (cin) v = Ws[r][c - o];         // A_IK <- A_IK P
+        else if (rin) v = Ws[c][r - o];         // A_KJ <- P A_KJ = (A_JK P)^T
+        else {
+          v = M[r][c];
 #pragma unroll
-    for (int b = 0; b < 4; b++)
-      if (c0 + b == p)
-#pragma unroll
-        for (int a = 0; a < 4; a++) colp[buf][r0 + a] = M[a][b];
-    __syncthreads();
-    const double d = 1.0 / rowp[buf][p];
-    double rs[4];
-#pragma unroll
-    for (int b = 0; b < 4; b++) rs[b] = rowp[buf][c0 + b] * d;
-#pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int r = r0 + a;
-      const double cp = colp[buf][r];
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const int c = c0 + b;
-        if (r == p) M[a][b] = (c == p) ? d : rs[b];
-        else if (c == p) M[a][b] = -cp * d;
-        else M[a][b] = M[a][b] - cp * rs[b];
+          for (int q = 0; q < SB; q++) v -= Vs[r][q] * Ws[c][q];  // A_IJ - A_IK P A_KJ
+        }
+        M[r][c] = v;
       }
-    }
+    __syncthreads();
   }
-  // P is symmetric up to rounding; storing its symmetric part keeps the sweep
-  // exactly symmetric, which the lower-tile storage relies on.
-  __shared__ double S[TS][TS + 1];
+  // the sweep left -A^-1; P is its negated symmetric part (symmetric P keeps
+  // the sweep of the whole matrix exactly symmetric, as its storage assumes)
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) S[r0 + a][c0 + b] = M[a][b];
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int r = r0 + a, c = c0 + b;
-      P[r * TS + c] = 0.5 * (S[r][c] + S[c][r]);
+    for (int bb = 0; bb < 4; bb++) {
+      const int r = r0 + a, c = c0 + bb;
+      P[r * TS + c] = -0.5 * (M[r][c] + M[c][r]);
     }
 }
 
