@@ -140,6 +140,14 @@ mts_status mts_sync(mts_solver *s);
  * or the quantity does not exist in this mode. */
 mts_status mts_read(mts_solver *s, int32_t what, double *host_out, int64_t cap, int64_t *n);
 
+/* The same quantity, written into device memory (for instance a torch
+ * tensor's storage) on the solver's stream: asynchronous, ordered after the
+ * work enqueued before it; the caller synchronizes that stream (mts_sync)
+ * before reading dev_out elsewhere.  Same layout, counts and errors as
+ * mts_read (MTS_H needs a problem small enough for H to be kept); dev_out
+ * stays owned by the caller. */
+mts_status mts_read_device(mts_solver *s, int32_t what, double *dev_out, int64_t cap, int64_t *n);
+
 /* Overwrite MTS_PD_U/V/A, MTS_FE_U/V/A or MTS_LAMBDA from host memory
  * (synchronous; n must equal the quantity's size). */
 mts_status mts_write(mts_solver *s, int32_t what, const double *host_in, int64_t n);

@@ -64,7 +64,7 @@ class PoolInfo(C.Structure):
                 ("n_running", C.c_int32), ("n_ready", C.c_int32), ("max_slots", C.c_int32), ("lanes", C.c_int32)]
 
 
-EXPORTS = ["mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_write", "mts_read_bonds",
+EXPORTS = ["mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
            "mts_query", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
            "mts_pool_create", "mts_pool_submit", "mts_pool_step", "mts_pool_poll", "mts_pool_read",
            "mts_pool_release", "mts_pool_query", "mts_pool_destroy"]
@@ -90,6 +90,7 @@ def load():
     lib.mts_advance.argtypes = [C.c_void_p, C.c_int64]
     lib.mts_sync.argtypes = [C.c_void_p]
     lib.mts_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), C.c_int64, P(C.c_int64)]
+    lib.mts_read_device.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, P(C.c_int64)]
     lib.mts_write.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), C.c_int64]
     lib.mts_read_bonds.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_uint8), C.c_int64, P(C.c_int64)]
     lib.mts_query.argtypes = [C.c_void_p, P(Info)]
@@ -110,7 +111,7 @@ def load():
     lib.mts_pool_query.argtypes = [C.c_void_p, P(PoolInfo)]
     lib.mts_pool_destroy.argtypes = [C.c_void_p]
     lib.mts_pool_destroy.restype = None
-    for f in ("mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_write", "mts_read_bonds",
+    for f in ("mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
               "mts_query", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
               "mts_pool_step", "mts_pool_poll", "mts_pool_read", "mts_pool_release", "mts_pool_query"):
         getattr(lib, f).restype = C.c_int
@@ -225,6 +226,28 @@ class Solver:
         if what == H:
             k = int(round(np.sqrt(out.size)))
             out = out.reshape(k, k)
+        return out
+
+    def read_device(self, what: int, out=None):
+        """The quantity written into a float64 CUDA/HIP tensor on the solver's
+        stream (no host round trip); `out` is allocated when not given.  Same
+        shape as read(); synchronize the solver's stream before using `out`
+        on another stream."""
+        import torch
+        info = self.query()
+        n = _sizes(info, what)
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor")
+        got = C.c_int64()
+        _check(self.lib.mts_read_device(self.h, what, C.c_void_p(out.data_ptr()), out.numel(), C.byref(got)))
+        out = out[:got.value]
+        if what in (PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, FE_X, LAMBDA):
+            out = out.view(-1, self.dim)
+        if what == H:
+            k = int(round(got.value ** 0.5))
+            out = out.view(k, k)
         return out
 
     def write(self, what: int, arr):

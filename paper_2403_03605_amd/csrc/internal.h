@@ -278,6 +278,7 @@ void check_finite(Solver &s);
 void resolve_pending(Solver &s);
 void snapshot_states(Solver &s, int slot);
 mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n);
+mts_status read_device_impl(Solver &s, int32_t what, double *dev_out, int64_t cap, int64_t *n);
 void query_impl(Solver &s, mts_info *o);
 // progress log on stderr when MTS_VERBOSE is set
 void vlog(const Solver &s, const char *fmt, ...);

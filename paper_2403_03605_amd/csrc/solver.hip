@@ -539,9 +539,60 @@ mts_status mts_read(mts_solver *h, int32_t what, double *out, int64_t cap, int64
   return read_impl(h->s, what, out, cap, n);
 }
 
+mts_status mts_read_device(mts_solver *h, int32_t what, double *dev_out, int64_t cap, int64_t *n) {
+  if (!h || !dev_out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  return read_device_impl(h->s, what, dev_out, cap, n);
+}
+
 }  // extern "C"
 
 namespace mts {
+namespace {
+__global__ void k_index_to_double(const int32_t *a, int64_t n, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)a[i];
+}
+}  // namespace
+
+// Device-side read: the node-major form of a quantity written into dev_out on
+// the solver's stream (no host synchronization).
+mts_status read_device_impl(Solver &s, int32_t what, double *dev_out, int64_t cap, int64_t *n) {
+  try {
+    const int64_t sz = qsize(s, what);
+    if (sz < 0) throw ArgError{"quantity not available"};
+    if (cap < sz) throw ArgError{"output capacity too small"};
+    if (n) *n = sz;
+    if (sz == 0) return MTS_OK;
+    hipStream_t st = s.stream;
+    const unsigned nb = (unsigned)((s.N + 255) / 256);
+    const double *src = nullptr;
+    switch (what) {
+      case MTS_PD_U: k_xu_to_aos<<<nb, 256, 0, st>>>(s.xu[s.cur], dev_out, s.N, s.dim); break;
+      case MTS_PD_V: k_soa_to_aos<<<nb, 256, 0, st>>>(s.v, dev_out, s.N, s.dim); break;
+      case MTS_PD_A: k_soa_to_aos<<<nb, 256, 0, st>>>(s.a, dev_out, s.N, s.dim); break;
+      case MTS_CONSTRAINT_NODES:
+        k_index_to_double<<<(unsigned)((sz + 255) / 256), 256, 0, st>>>(s.cn, sz, dev_out);
+        break;
+      case MTS_FE_U: src = s.uF; break;
+      case MTS_FE_V: src = s.vF; break;
+      case MTS_FE_A: src = s.aF; break;
+      case MTS_FE_X: src = s.xF; break;
+      case MTS_FE_MASS: src = s.mF; break;
+      case MTS_DAMAGE: pd_damage(s); src = s.damage; break;
+      case MTS_PD_ALPHA: src = s.alpha; break;
+      case MTS_PD_MASS: src = s.mass; break;
+      case MTS_LAMBDA: src = s.lam0; break;
+      case MTS_H: src = s.Hcopy; break;
+      default: throw ArgError{"unknown quantity"};
+    }
+    MTS_LAUNCH_CHECK();
+    if (src) MTS_HIP(hipMemcpyAsync(dev_out, src, sizeof(double) * sz, hipMemcpyDeviceToDevice, st));
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
 mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n) {
   try {
     int64_t sz = qsize(s, what);

@@ -1,0 +1,41 @@
+"""C-ABI entry points beyond the parity path: the device-memory read gives the
+same values as the host read, for every quantity, in both modes."""
+import numpy as np
+import pytest
+
+import mts_inputs as mi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mts():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_03605_amd as m
+    m.load()
+    return m
+
+
+@pytest.mark.parametrize("mode", ["coupled", "pure_pd"])
+def test_read_device_equals_read(mts, mode):
+    import torch
+    inst = mi.config(0) if mode == "coupled" else mi.plate2d(30, 2, 4, 1e-8, perturb=1e-6, seed=13,
+                                                             mode="pure_pd", name="pure30")
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    s.advance(10)
+    qs = [mts.PD_U, mts.PD_V, mts.PD_A, mts.DAMAGE, mts.PD_ALPHA, mts.PD_MASS]
+    if mode == "coupled":
+        qs += [mts.FE_U, mts.FE_V, mts.FE_A, mts.FE_X, mts.FE_MASS, mts.LAMBDA, mts.CONSTRAINT_NODES, mts.H]
+    for q in qs:
+        host = s.read(q)
+        dev = s.read_device(q)
+        s.sync()
+        assert np.array_equal(dev.cpu().numpy(), host), q
+    # a too small output is rejected before anything is written
+    small = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(mts.MtsError):
+        s.read_device(mts.PD_U, small)
+    s.close()
