@@ -91,7 +91,7 @@ typedef struct mts_info {
 
 typedef struct mts_plan_info {
   int64_t n_pd, nnz_estimate, n_fe_nodes, n_constraints_estimate;
-  int64_t device_bytes_estimate; /* upper estimate of what mts_create allocates */
+  int64_t device_bytes_estimate; /* upper estimate of what mts_create allocates, temporaries included */
 } mts_plan_info;
 
 /* Quantities for mts_read / mts_write (vectors node-major, dim per node). */
@@ -124,6 +124,16 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out);
  * n_pd <= 0, a crack line off the FE node lines, a constraint node in an element
  * with no weight), MTS_ENOMEM, MTS_EDEVICE. */
 mts_status mts_create(const mts_problem *p, void *hip_stream, mts_solver **out);
+
+/* mts_create with all of the solver's device memory carved out of a
+ * caller-owned region (for instance a torch uint8 tensor): dev_arena (256-byte
+ * aligned) .. dev_arena + arena_bytes must stay valid until mts_destroy, and
+ * the library never frees it.  mts_plan's device_bytes_estimate is enough;
+ * a region that turns out too small fails with MTS_ENOMEM (also later, if a
+ * rebuild of the unit-load responses needs more scratch than is left).
+ * dev_arena = NULL behaves as mts_create.  Other errors as mts_create. */
+mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_bytes, void *hip_stream,
+                         mts_solver **out);
 
 /* Enqueue n_macro macro steps (one FE step and m PD substeps each,
  * Algorithm 1).  Returns after enqueueing the last macro step; it may wait on

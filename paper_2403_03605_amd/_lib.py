@@ -64,7 +64,7 @@ class PoolInfo(C.Structure):
                 ("n_running", C.c_int32), ("n_ready", C.c_int32), ("max_slots", C.c_int32), ("lanes", C.c_int32)]
 
 
-EXPORTS = ["mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
+EXPORTS = ["mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
            "mts_query", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
            "mts_pool_create", "mts_pool_submit", "mts_pool_step", "mts_pool_poll", "mts_pool_read",
            "mts_pool_release", "mts_pool_query", "mts_pool_destroy"]
@@ -87,6 +87,7 @@ def load():
     P = C.POINTER
     lib.mts_plan.argtypes = [P(Problem), P(PlanInfo)]
     lib.mts_create.argtypes = [P(Problem), C.c_void_p, P(C.c_void_p)]
+    lib.mts_create_in.argtypes = [P(Problem), C.c_void_p, C.c_int64, C.c_void_p, P(C.c_void_p)]
     lib.mts_advance.argtypes = [C.c_void_p, C.c_int64]
     lib.mts_sync.argtypes = [C.c_void_p]
     lib.mts_read.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), C.c_int64, P(C.c_int64)]
@@ -111,7 +112,7 @@ def load():
     lib.mts_pool_query.argtypes = [C.c_void_p, P(PoolInfo)]
     lib.mts_pool_destroy.argtypes = [C.c_void_p]
     lib.mts_pool_destroy.restype = None
-    for f in ("mts_plan", "mts_create", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
+    for f in ("mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
               "mts_query", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
               "mts_pool_step", "mts_pool_poll", "mts_pool_read", "mts_pool_release", "mts_pool_query"):
         getattr(lib, f).restype = C.c_int
@@ -180,7 +181,9 @@ def _sizes(info, what):
 class Solver:
     """One solver instance (mts_create ... mts_destroy)."""
 
-    def __init__(self, inst: dict, stream=None):
+    def __init__(self, inst: dict, stream=None, arena=None):
+        """arena: optional contiguous uint8 device tensor that holds all of the
+        solver's device memory (mts_create_in); kept referenced until close()."""
         self.lib = load()
         p, self._pos = make_problem(inst)
         if stream is None:
@@ -191,7 +194,15 @@ class Solver:
                 stream = 0
         self.stream = int(stream)
         h = C.c_void_p()
-        _check(self.lib.mts_create(C.byref(p), C.c_void_p(self.stream), C.byref(h)))
+        self.arena = arena
+        if arena is None:
+            _check(self.lib.mts_create(C.byref(p), C.c_void_p(self.stream), C.byref(h)))
+        else:
+            if not arena.is_cuda or not arena.is_contiguous():
+                raise ValueError("arena must be a contiguous device tensor")
+            nbytes = arena.numel() * arena.element_size()
+            _check(self.lib.mts_create_in(C.byref(p), C.c_void_p(arena.data_ptr()), nbytes,
+                                          C.c_void_p(self.stream), C.byref(h)))
         self.h = h
         self.dim = int(inst["dim"])
 
@@ -199,6 +210,7 @@ class Solver:
         if getattr(self, "h", None):
             self.lib.mts_destroy(self.h)
             self.h = None
+        self.arena = None
 
     def __del__(self):
         self.close()

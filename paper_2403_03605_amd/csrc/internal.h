@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/mtspd.h"
@@ -32,21 +33,45 @@ struct MemError {
 
 #define MTS_LAUNCH_CHECK() MTS_HIP(hipGetLastError())
 
-// Device allocations owned by one solver.
+// Device allocations of one solver: hipMalloc per allocation, or first-fit
+// sub-allocation (256-byte aligned, freed extents coalesced) inside a
+// caller-owned region that the solver never frees.
 struct DeviceArena {
-  std::vector<void *> blocks;
-  size_t bytes = 0;
+  std::vector<std::pair<void *, size_t>> blocks;
+  size_t live = 0;  // bytes held now
+  char *region = nullptr;
+  size_t region_bytes = 0;
+  std::map<size_t, size_t> free_ext, used_ext;  // offset -> size
+  void use_region(void *base, size_t n) {
+    region = static_cast<char *>(base);
+    region_bytes = n & ~size_t(255);
+    free_ext.clear();
+    used_ext.clear();
+    if (region_bytes) free_ext[0] = region_bytes;
+  }
   template <class T>
   T *alloc(size_t n) {
-    void *p = nullptr;
     size_t b = sizeof(T) * (n ? n : 1);
     b = (b + 255) & ~size_t(255);
-    if (hipMalloc(&p, b) != hipSuccess) {
-      (void)hipGetLastError();
-      throw MemError{"hipMalloc of " + std::to_string(b) + " bytes failed"};
+    void *p = nullptr;
+    if (region) {
+      auto it = free_ext.begin();
+      while (it != free_ext.end() && it->second < b) ++it;
+      if (it == free_ext.end())
+        throw MemError{"caller arena of " + std::to_string(region_bytes) + " bytes is too small"};
+      const size_t off = it->first, sz = it->second;
+      free_ext.erase(it);
+      if (sz > b) free_ext[off + b] = sz - b;
+      used_ext[off] = b;
+      p = region + off;
+    } else {
+      if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        throw MemError{"hipMalloc of " + std::to_string(b) + " bytes failed"};
+      }
+      blocks.push_back({p, b});
     }
-    blocks.push_back(p);
-    bytes += b;
+    live += b;
     return static_cast<T *>(p);
   }
   void release(void *p);

@@ -439,7 +439,7 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
     return err;
   }
   std::lock_guard<std::mutex> lk(P->mu);
-  const int64_t actual = (int64_t)r->s->arena.bytes;
+  const int64_t actual = (int64_t)r->s->arena.live;
   P->used += actual - est;
   r->charged = actual;
   P->creating--;

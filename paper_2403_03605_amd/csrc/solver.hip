@@ -29,18 +29,41 @@ void vlog(const Solver &s, const char *fmt, ...) {
 }
 
 void DeviceArena::release(void *p) {
+  if (region) {
+    auto it = used_ext.find((size_t)(static_cast<char *>(p) - region));
+    if (it == used_ext.end()) return;
+    size_t off = it->first, sz = it->second;
+    used_ext.erase(it);
+    live -= sz;
+    auto nx = free_ext.lower_bound(off);
+    if (nx != free_ext.end() && nx->first == off + sz) {  // merge with the next free extent
+      sz += nx->second;
+      nx = free_ext.erase(nx);
+    }
+    if (nx != free_ext.begin()) {  // and with the previous one
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += sz;
+        return;
+      }
+    }
+    free_ext[off] = sz;
+    return;
+  }
   for (size_t k = 0; k < blocks.size(); k++)
-    if (blocks[k] == p) {
+    if (blocks[k].first == p) {
       (void)hipFree(p);
+      live -= blocks[k].second;
       blocks.erase(blocks.begin() + (long)k);
       return;
     }
 }
 
 void DeviceArena::free_all() {
-  for (void *p : blocks) (void)hipFree(p);
+  for (auto &b : blocks) (void)hipFree(b.first);
   blocks.clear();
-  bytes = 0;
+  live = 0;
+  if (region) use_region(region, region_bytes);  // the region itself stays the caller's
 }
 
 void Solver::prof_begin(int k, hipEvent_t *e0) {
@@ -457,23 +480,35 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
     int64_t nc = 0;
     if (p->mode == MTS_COUPLED) {
       double vol_in = 1.0, vol = 1.0;
-      for (int a = 0; a < p->dim; a++) {
-        double L = p->pd_hi[a] - p->pd_lo[a];
+      for (int a = 0; a < p->dim; a++) {  // bands only on the faces inside the domain
+        const double L = p->pd_hi[a] - p->pd_lo[a], tol = 1e-9 * (p->dom_hi[a] - p->dom_lo[a]);
+        const int inner = (p->pd_lo[a] > p->dom_lo[a] + tol) + (p->pd_hi[a] < p->dom_hi[a] - tol);
         vol *= L;
-        vol_in *= std::max(0.0, L - 2 * p->overlap);
+        vol_in *= std::max(0.0, L - inner * p->overlap);
       }
       nc = (int64_t)std::ceil(p->n_pd * (1.0 - vol_in / vol)) + 64;
     }
     out->n_constraints_estimate = nc;
-    int64_t nl = nc * p->dim;
-    int64_t rhs = p->dim == 2 ? 8 : 6;
-    int64_t bytes = out->nnz_estimate * (4 + 4 + 1) + p->n_pd * (8 * (6 * p->dim + 6) + 16);
+    // An upper estimate of everything the solver allocates during mts_create
+    // (temporaries included, as if none were freed), used for pool admission
+    // and to size a caller arena.
+    const int64_t nl = nc * p->dim, d = p->dim;
+    const int64_t rhs = d == 2 ? 8 : 6;
+    const int64_t slots = out->nnz_estimate + out->nnz_estimate / 10 + p->n_pd;  // sliced-ELL padding
+    // per slot: index 4, coefficients 8 + 4, slot record 12, state bit, staging
+    // index 4 (temporary), canonical CSR index 4; per node: positions, records,
+    // velocities, accelerations, loads, weights, masses, damage, maps, cell lists
+    int64_t bytes = slots * 40 + p->n_pd * (96 * d + 96) + ((int64_t)8 << 20);
     if (p->mode == MTS_COUPLED) {
-      bytes += nl * nl * 8 + nl * 64 * 16 + ne * 8 * 8 * 4 + nfe * 8 * 12 + 4 * rhs * p->dim * p->n_pd * 8;
-      bytes += out->nnz_estimate * 5;
-      // final-update response records and the region's slot records
-      bytes += 2 * 2 * p->dim * p->n_pd * 8 + out->nnz_estimate * 12;
+      const int64_t T = (nl + 63) / 64, tiles = T * (T + 1) / 2;
+      bytes += nl * nl * 8 * (nl <= 4096 ? 2 : 1);   // H (and its copy, when kept)
+      bytes += tiles * (64 * 64 * 8 + 2 * 64 * 8);    // packed inverse, GEMV partial sums
+      bytes += 2 * T * 64 * 256 * 8 + 256 * 256 * 8 + 64 * 64 * 8;  // sweep panels and pivot blocks
+      bytes += 4 * rhs * d * p->n_pd * 8 + 2 * 2 * d * p->n_pd * 8;  // link responses, final-update records
+      bytes += slots * 40;                            // link region layout (at most every slot)
+      bytes += ne * 8 * 8 * 8 + nfe * 8 * 24 + nc * 64 * 8;  // FE mesh and state, coupling tables
     }
+    bytes += bytes / 8;
     out->device_bytes_estimate = bytes;
     return MTS_OK;
   } catch (...) {
@@ -482,14 +517,24 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
 }
 
 mts_status mts_create(const mts_problem *p, void *hip_stream, mts_solver **out) {
+  return mts_create_in(p, nullptr, 0, hip_stream, out);
+}
+
+mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_bytes, void *hip_stream,
+                         mts_solver **out) {
   if (!out) {
     std::snprintf(g_err, sizeof g_err, "null output pointer");
     return MTS_EINVAL;
   }
   *out = nullptr;
+  if (dev_arena && (arena_bytes <= 0 || ((uintptr_t)dev_arena & 255u) != 0)) {
+    std::snprintf(g_err, sizeof g_err, "the arena must be 256-byte aligned and non-empty");
+    return MTS_EINVAL;
+  }
   mts_solver *h = nullptr;
   try {
     h = new mts_solver();
+    if (dev_arena) h->s.arena.use_region(dev_arena, (size_t)arena_bytes);
     create_impl(p, hip_stream, &h->s);
     *out = h;
     return MTS_OK;
@@ -737,7 +782,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->macro_steps = s.macro_steps;
   o->n_rebuilds = s.n_rebuilds;
   o->n_colors = s.n_colors;
-  o->device_bytes = (int64_t)s.arena.bytes;
+  o->device_bytes = (int64_t)s.arena.live;
   o->dim = s.dim;
   o->precision = s.precision;
 }

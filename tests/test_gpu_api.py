@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import mts_inputs as mi
+from paper_2403_03605_amd import _lib
 
 pytestmark = pytest.mark.gpu
 
@@ -39,3 +40,31 @@ def test_read_device_equals_read(mts, mode):
     with pytest.raises(mts.MtsError):
         s.read_device(mts.PD_U, small)
     s.close()
+
+
+@pytest.mark.parametrize("which", ["plate", "block"])
+def test_caller_arena(mts, which):
+    """mts_create_in: the solver lives in a caller-owned torch tensor of the
+    planned size and computes exactly what a self-allocating solver computes;
+    a region that is too small fails cleanly with MTS_ENOMEM."""
+    import torch
+    inst = mi.config(0) if which == "plate" else mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=42,
+                                                             name="block12")
+    print("case", inst["name"], flush=True)
+    est = mts.plan(inst)["device_bytes_estimate"]
+    ref = mts.Solver(inst)
+    used = ref.query()["device_bytes"]
+    print("  planned", est, "allocated", used, flush=True)
+    assert est >= used
+    arena = torch.empty(est, dtype=torch.uint8, device="cuda")
+    s = mts.Solver(inst, arena=arena)
+    for x in (ref, s):
+        x.advance(20)
+    for q in (mts.PD_U, mts.PD_V, mts.DAMAGE, mts.FE_U, mts.LAMBDA):
+        assert np.array_equal(s.read(q), ref.read(q)), q
+    s.close()
+    ref.close()
+    small = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mts.MtsError) as e:
+        mts.Solver(inst, arena=small)
+    assert e.value.status == _lib.ENOMEM

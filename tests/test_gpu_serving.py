@@ -131,7 +131,15 @@ def test_admission_by_budget(mts):
     est = mts.plan(insts[2])["device_bytes_estimate"]
     with pytest.raises(mts.MtsError):
         mts.Pool(est // 2, max_slots=4).submit(insts[2], 1)   # ETOOBIG
-    pool = mts.Pool(int(est * 1.5), max_slots=4)
+    # what a built request holds (its estimate is charged only while it builds)
+    probe = mts.Pool(int(est * 1.5), max_slots=4)
+    a = probe.submit(insts[2], 2)
+    held = probe.query()["used_bytes"]
+    assert 0 < held <= est
+    _drain(probe, [a])
+    probe.release(a)
+    probe.close()
+    pool = mts.Pool(est + held // 2, max_slots=4)
     a = pool.submit(insts[2], 2)
     assert a is not None
     assert pool.submit(insts[2], 2) is None  # EAGAIN: budget held by the first
