@@ -89,6 +89,16 @@ typedef struct mts_info {
   int32_t dim, precision;
 } mts_info;
 
+/* Energies of the current state (J, per unit thickness in 2D) and the bonds
+ * broken since setup (pre-crack cuts excluded). */
+typedef struct mts_energy_info {
+  double kinetic;        /* 1/2 v^T M v, weighted PD and FE masses (Eq. 17-18) */
+  double strain_pd;      /* 1/4 sum_i sum_k mu w c (xi.eta)^2 V_i V_k (Eq. 6-7) */
+  double strain_fe;      /* 1/2 u^T K u, alpha-weighted FE stiffness (Eq. 34) */
+  double external_work;  /* P . u of the constant loads */
+  int64_t n_broken;
+} mts_energy_info;
+
 typedef struct mts_plan_info {
   int64_t n_pd, nnz_estimate, n_fe_nodes, n_constraints_estimate;
   int64_t device_bytes_estimate; /* upper estimate of what mts_create allocates, temporaries included */
@@ -169,6 +179,11 @@ mts_status mts_read_bonds(mts_solver *s, int64_t *host_row_ptr, int32_t *host_co
                           uint8_t *host_intact, int64_t cap, int64_t *nnz);
 
 mts_status mts_query(mts_solver *s, mts_info *out);
+
+/* Energies and broken bonds of the state after the work enqueued so far
+ * (synchronous: waits for the solver's stream).  Each term is summed in a
+ * fixed order, so repeated calls give identical values. */
+mts_status mts_energy(mts_solver *s, mts_energy_info *out);
 
 /* HIP-event timing on the solver's stream while enabled.  MTS_KT_PD_SUBSTEP:
  * one event pair brackets the m back-to-back substep launches of a macro step

@@ -53,6 +53,11 @@ class Info(C.Structure):
     ]
 
 
+class EnergyInfo(C.Structure):
+    _fields_ = [("kinetic", C.c_double), ("strain_pd", C.c_double), ("strain_fe", C.c_double),
+                ("external_work", C.c_double), ("n_broken", C.c_int64)]
+
+
 class PlanInfo(C.Structure):
     _fields_ = [("n_pd", C.c_int64), ("nnz_estimate", C.c_int64), ("n_fe_nodes", C.c_int64),
                 ("n_constraints_estimate", C.c_int64), ("device_bytes_estimate", C.c_int64)]
@@ -65,7 +70,7 @@ class PoolInfo(C.Structure):
 
 
 EXPORTS = ["mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
-           "mts_query", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
+           "mts_query", "mts_energy", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
            "mts_pool_create", "mts_pool_submit", "mts_pool_step", "mts_pool_poll", "mts_pool_read",
            "mts_pool_release", "mts_pool_query", "mts_pool_destroy"]
 
@@ -95,6 +100,7 @@ def load():
     lib.mts_write.argtypes = [C.c_void_p, C.c_int32, P(C.c_double), C.c_int64]
     lib.mts_read_bonds.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_uint8), C.c_int64, P(C.c_int64)]
     lib.mts_query.argtypes = [C.c_void_p, P(Info)]
+    lib.mts_energy.argtypes = [C.c_void_p, P(EnergyInfo)]
     lib.mts_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.mts_kernel_time.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double)]
     lib.mts_destroy.argtypes = [C.c_void_p]
@@ -113,7 +119,7 @@ def load():
     lib.mts_pool_destroy.argtypes = [C.c_void_p]
     lib.mts_pool_destroy.restype = None
     for f in ("mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
-              "mts_query", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
+              "mts_query", "mts_energy", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
               "mts_pool_step", "mts_pool_poll", "mts_pool_read", "mts_pool_release", "mts_pool_query"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -225,6 +231,11 @@ class Solver:
         o = Info()
         _check(self.lib.mts_query(self.h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in Info._fields_}
+
+    def energy(self) -> dict:
+        o = EnergyInfo()
+        _check(self.lib.mts_energy(self.h, C.byref(o)))
+        return {k: getattr(o, k) for k, _ in EnergyInfo._fields_}
 
     def read(self, what: int) -> np.ndarray:
         info = self.query()

@@ -470,6 +470,19 @@ void fe_free_step(Solver &s) {
   MTS_LAUNCH_CHECK();
 }
 
+// Element forces of the current (corrected) FE displacement into fe_buf
+// (inspection: energies).  fe_buf is free between macro steps.
+void fe_elem_forces_current(Solver &s) {
+  hipStream_t st = s.stream;
+  if (s.dim == 2)
+    k_fe_elem_force<2><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.p.thickness,
+                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+  else
+    k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.p.thickness,
+                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+  MTS_LAUNCH_CHECK();
+}
+
 void fe_correct(Solver &s) {
   if (!s.n_ring) return;
   k_fe_correct_ring<<<(unsigned)((s.n_ring * WAVE + 255) / 256), 256, 0, s.stream>>>(

@@ -153,6 +153,7 @@ struct Solver {
   int m = 1;
   bool unstable = false;
   int64_t pd_steps = 0, macro_steps = 0, n_rebuilds = 0;
+  int64_t n_intact0 = 0;  // intact bonds after setup (pre-crack cuts removed)
 
   // ---- PD ----
   double *x = nullptr;           // SoA dim*N
@@ -304,6 +305,9 @@ void resolve_pending(Solver &s);
 void snapshot_states(Solver &s, int slot);
 mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n);
 mts_status read_device_impl(Solver &s, int32_t what, double *dev_out, int64_t cap, int64_t *n);
+// energies and broken-bond count of the current state (energy.hip)
+int64_t count_intact(Solver &s);
+void energy_impl(Solver &s, mts_energy_info *out);
 void query_impl(Solver &s, mts_info *o);
 // progress log on stderr when MTS_VERBOSE is set
 void vlog(const Solver &s, const char *fmt, ...);

@@ -280,6 +280,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
   s->pinned_flag[0] = s->pinned_flag[1] = 0;
   pd_damage(*s);
+  s->n_intact0 = count_intact(*s);
   MTS_HIP(hipStreamSynchronize(st));
 }
 
@@ -582,6 +583,16 @@ mts_status mts_sync(mts_solver *h) {
 mts_status mts_read(mts_solver *h, int32_t what, double *out, int64_t cap, int64_t *n) {
   if (!h || !out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
   return read_impl(h->s, what, out, cap, n);
+}
+
+mts_status mts_energy(mts_solver *h, mts_energy_info *out) {
+  if (!h || !out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  try {
+    energy_impl(h->s, out);
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
 }
 
 mts_status mts_read_device(mts_solver *h, int32_t what, double *dev_out, int64_t cap, int64_t *n) {

@@ -37,7 +37,7 @@ def test_struct_layout_matches_header(tmp_path):
     equal the ctypes mirrors used by the binding."""
     checks = []
     for cname, cls in (("mts_problem", _lib.Problem), ("mts_info", _lib.Info), ("mts_plan_info", _lib.PlanInfo),
-                      ("mts_pool_info", _lib.PoolInfo)):
+                      ("mts_pool_info", _lib.PoolInfo), ("mts_energy_info", _lib.EnergyInfo)):
         checks.append((f"sizeof({cname})", C.sizeof(cls)))
         for fname, _ in cls._fields_:
             checks.append((f"offsetof({cname}, {fname})", getattr(cls, fname).offset))
