@@ -85,8 +85,9 @@ typedef struct mts_info {
   double delta, volume, c0, s_crit, dt_pd, dt_fe;
   int64_t n_pd, nnz, n_fe_nodes, n_fe_elems, n_constraints, n_region;
   int64_t pd_steps, macro_steps, n_rebuilds, n_colors;
-  int64_t device_bytes;
+  int64_t device_bytes;  /* device memory the solver holds */
   int32_t dim, precision;
+  double dt_bound_pd;    /* PD stability bound of the step (create rejects dt_pd above it) */
 } mts_info;
 
 /* Energies of the current state (J, per unit thickness in 2D) and the bonds
@@ -130,7 +131,8 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out);
  * constraint set, the unit-load responses and the multiplier matrix (eq. unit,
  * Eq. 49), all enqueued on `hip_stream` (a hipStream_t, or NULL for the null
  * stream).  The solver owns its device memory.  On error *out stays NULL.
- * Errors: MTS_EINVAL (bad description: dim, m < 1, dt_pd <= 0, horizon_factor < 1,
+ * Errors: MTS_EINVAL (bad description: dim, m < 1, dt_pd <= 0 or above the PD
+ * stability bound (mts_info.dt_bound_pd), horizon_factor < 1,
  * n_pd <= 0, a crack line off the FE node lines, a constraint node in an element
  * with no weight), MTS_ENOMEM, MTS_EDEVICE. */
 mts_status mts_create(const mts_problem *p, void *hip_stream, mts_solver **out);

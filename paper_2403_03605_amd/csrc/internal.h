@@ -154,6 +154,7 @@ struct Solver {
   bool unstable = false;
   int64_t pd_steps = 0, macro_steps = 0, n_rebuilds = 0;
   int64_t n_intact0 = 0;  // intact bonds after setup (pre-crack cuts removed)
+  double dt_bound_pd = 0.0;  // PD stability bound of the step
 
   // ---- PD ----
   double *x = nullptr;           // SoA dim*N

@@ -6,6 +6,7 @@
 // Equations: Eq. 2 (force), Eq. 3 (stretch), Eq. 4 (bond state), Eq. 5 (damage),
 // Eq. 38 with gamma = 1/2, beta = 0 (velocity Verlet), Eq. 48a/48b (free and
 // link problems), Eq. 17-18 and Eq. 34 (Arlequin weights of stiffness and mass).
+#include <cstdio>
 #include <cstring>
 #include <type_traits>
 
@@ -686,6 +687,43 @@ __global__ void k_link_records(const double *x, int64_t N, int dim, double *rec)
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Stability bound of the explicit PD step at node i (the Silling-Askari
+// criterion with the Arlequin bond weights): sqrt(2 m_i / sum_k w c |xi|^2 V_i V_k).
+__global__ void k_pd_dt_bound(int64_t N, int dim, const double *x, const int32_t *rp, const int32_t *row_of, int L,
+                              const int64_t *slot_off, const int32_t *col, const double *coef, const double *mass,
+                              double *dt_node) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t r = row_of ? row_of[i] : i;
+  const int S = WAVE / L;
+  double k = 0.0;
+  for (int q = 0; q < rp[i + 1] - rp[i]; q++) {
+    const int64_t pos = sell_slot(slot_off[r / S], (int)(r % S), q, L);
+    const int64_t c = col[pos];
+    double r2 = 0.0;
+    for (int d = 0; d < dim; d++) {
+      const double t = x[d * N + c] - x[d * N + i];
+      r2 += t * t;
+    }
+    k += coef[pos] * r2;
+  }
+  dt_node[i] = k > 0.0 ? sqrt(2.0 * mass[i] / k) : 1e300;
+}
+
+// smallest of n values (one workgroup; the minimum does not depend on the order)
+__global__ void k_min(const double *a, int64_t n, double *out) {
+  __shared__ double part[256];
+  double m = 1e300;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmin(m, a[i]);
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] = fmin(part[threadIdx.x], part[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
+
 }  // namespace
 
 void pd_setup(Solver &s) {
@@ -701,6 +739,26 @@ void pd_setup(Solver &s) {
   k_init_accel<<<nblk(N), 256, 0, st>>>(N, s.dim, s.P, s.mass, s.a);
   MTS_LAUNCH_CHECK();
   sell_coefficients(s, s.sell);
+  {
+    // the step must respect the PD stability bound (an explicit step above it
+    // grows without limit)
+    double *t = s.arena.alloc<double>(N + 1);
+    k_pd_dt_bound<<<nblk(N), 256, 0, st>>>(N, s.dim, s.x, s.rp, s.sell.row_of, s.sell.L, s.sell.slot_off,
+                                           s.sell.col, s.sell.coef, s.mass, t);
+    MTS_LAUNCH_CHECK();
+    k_min<<<1, 256, 0, st>>>(t, N, t + N);
+    MTS_LAUNCH_CHECK();
+    double bound = 0.0;
+    MTS_HIP(hipMemcpyAsync(&bound, t + N, sizeof(double), hipMemcpyDeviceToHost, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    s.arena.release(t);
+    s.dt_bound_pd = bound;
+    if (s.prm.dtP > bound) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "dt_pd = %.4g s exceeds the PD stability bound %.4g s", s.prm.dtP, bound);
+      throw ArgError{msg};
+    }
+  }
   sell_pack_slots(s, s.sell);
   if (s.halo) sell_build_halo(s, s.sell);
 }

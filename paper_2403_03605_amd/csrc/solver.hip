@@ -796,6 +796,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->device_bytes = (int64_t)s.arena.live;
   o->dim = s.dim;
   o->precision = s.precision;
+  o->dt_bound_pd = s.dt_bound_pd;
 }
 
 extern "C" {

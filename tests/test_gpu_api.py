@@ -116,3 +116,20 @@ def test_energy_conservation_on_device(mts):
     print("  energy error", e1, e2, flush=True)
     assert e1 < 2e-2
     assert 3.0 < e1 / e2 < 5.0
+
+
+def test_step_above_pd_stability_bound_rejected(mts):
+    """create reports the PD stability bound (the oracle's, to rounding) and
+    rejects a step above it with MTS_EINVAL."""
+    from oracle import Oracle
+    inst = mi.config(0)
+    s = mts.Solver(inst)
+    bound = s.query()["dt_bound_pd"]
+    s.close()
+    ref = Oracle(inst, setup_only=True).dt_bound(0)
+    print("  PD bound", bound, "oracle", ref, flush=True)
+    assert abs(bound - ref) <= 1e-12 * ref
+    mts.Solver(dict(inst, dt_pd=0.99 * bound)).close()
+    with pytest.raises(mts.MtsError) as e:
+        mts.Solver(dict(inst, dt_pd=1.01 * bound))
+    assert e.value.status == _lib.EINVAL
