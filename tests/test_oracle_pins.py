@@ -272,6 +272,32 @@ def test_force_uniform_strain_interior_zero():
     assert np.abs(f[inner]).max() <= 1e-10 * fb
 
 
+def test_ghost_force_confined_and_ordered_by_weight():
+    """Arlequin weights under a uniform strain (Sec. 3.2, the overlap-weight
+    study of Table 1): the weighted PD force vanishes wherever a node's whole
+    family lies where alpha = 0, so the ghost force is confined to the
+    overlap; just inside it, where the weight starts to rise, it is largest for
+    the constant weight (a jump), smaller for the linear one (a kink) and
+    smallest for the cubic one (smooth)."""
+    worst = {}
+    for wk in ("constant", "linear", "cubic"):
+        inst = mi.plate2d(40, 4, 8, 4e-8, traction=0.0, weight=wk, name="ghost " + wk)
+        inst["cracks"] = []
+        o = Oracle(inst, setup_only=True)
+        pos = np.asarray(inst["pos"], float)
+        al = o.get(O.PD_ALPHA)
+        u = np.stack([1e-3 * pos[:, 0], -3e-4 * pos[:, 1]], 1)
+        f = np.abs(o.pd_force(u)).max(axis=1)
+        rp, col, _ = o.bonds()
+        fam_free = np.array([al[i] == 0 and np.all(al[col[rp[i]:rp[i + 1]]] == 0) for i in range(len(pos))])
+        scale = f.max()
+        assert fam_free.sum() > 100
+        assert f[fam_free].max() <= 1e-10 * scale, wk
+        worst[wk] = f[(al == 0) & ~fam_free].max()  # alpha = 0, weight rising within the family
+    print("ghost force next to the overlap", worst)
+    assert worst["constant"] > worst["linear"] > worst["cubic"] > 0
+
+
 def test_precrack_cuts_and_symmetry():
     inst = mi.config(0)
     o = Oracle(inst)
