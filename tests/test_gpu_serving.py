@@ -166,3 +166,51 @@ def test_serve_loop(mts):
         u, phi, _ = _alone(mts, inst)
         assert np.array_equal(out["results"][k]["u"], u)
         assert np.array_equal(out["results"][k]["damage"], phi)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_pool_3d_alone_mix_and_solver(mts, precision):
+    """3D requests in a pool (batched 3D substep kernel): alone and in a mix
+    give bit-identical results, equal to a plain solver in the same layout
+    (4 lanes per row, canonical rows, direct gathers)."""
+    import os
+    insts = [mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=51, precision=precision, name="b12"),
+             mi.block3d(10, 10, 6, 8, 80, 2.5e-8, perturb=1e-6, seed=52, precision=precision, name="b10")]
+    nm = [6, 4]
+
+    def read3(pool, rid, inst):
+        n = inst["pos"].shape[0]
+        return pool.read(rid, mts.PD_U, 3 * n), pool.read(rid, mts.DAMAGE, n)
+
+    alone = []
+    for inst, n in zip(insts, nm):
+        pool = mts.Pool(BIG, max_slots=4, dim=3, precision=precision)
+        rid = pool.submit(inst, n)
+        _drain(pool, [rid])
+        alone.append(read3(pool, rid, inst))
+        pool.release(rid)
+        pool.close()
+    pool = mts.Pool(BIG, max_slots=4, dim=3, precision=precision)
+    ids = [pool.submit(insts[0], nm[0])]
+    pool.step()
+    ids.append(pool.submit(insts[1], nm[1]))
+    _drain(pool, ids)
+    for k, rid in enumerate(ids):
+        u, phi = read3(pool, rid, insts[k])
+        assert np.array_equal(u, alone[k][0]) and np.array_equal(phi, alone[k][1]), k
+        assert np.abs(u).max() > 0
+        pool.release(rid)
+    pool.close()
+    saved = {k: os.environ.get(k) for k in ("MTS_LANES", "MTS_HALO", "MTS_TILE")}
+    os.environ.update({"MTS_LANES": "4", "MTS_HALO": "0", "MTS_TILE": "0"})
+    try:
+        s = mts.Solver(insts[0])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    s.advance(nm[0])
+    assert np.array_equal(s.read(mts.PD_U).ravel(), alone[0][0].ravel())
+    s.close()
