@@ -250,11 +250,23 @@ void coupling_setup(Solver &s) {
   std::vector<int32_t> rrows;
   for (int64_t i = 0; i < N; i++)
     if (reg[i]) rrows.push_back((int32_t)i);
+  // with tiled rows the region takes the same spatial tile order, so each
+  // workgroup of the final update can stage its neighbours' records in LDS
+  const bool region_tiled = s.halo && !s.h_node_tile.empty();
+  if (region_tiled)
+    std::stable_sort(rrows.begin(), rrows.end(),
+                     [&](int32_t a, int32_t b) { return s.h_node_tile[a] < s.h_node_tile[b]; });
   s.n_region = (int64_t)rrows.size();
   build_sell(s, s.rsell, rrows, s.sell.mask,
              s.region_lanes ? s.region_lanes : pick_lanes(s.n_region, s.dim, s.dim == 3 ? ((int64_t)1 << 18) : (int64_t)120000));
   sell_coefficients(s, s.rsell);
-  sell_pack_slots(s, s.rsell, nullptr, true);  // the final update runs in FP64 in both forms
+  s.rsell.fp64_slots = true;  // the final update runs in FP64 in both forms
+  sell_pack_slots(s, s.rsell);
+  if (region_tiled && s.rsell.n_slices) {
+    s.rsell.h_tile.resize(rrows.size());
+    for (size_t r = 0; r < rrows.size(); r++) s.rsell.h_tile[r] = s.h_node_tile[rrows[r]];
+    sell_build_halo(s, s.rsell);
+  }
   s.rsell.slice_layer = ar.alloc<int32_t>(s.rsell.n_slices);
   if (s.rsell.n_slices) {
     k_slice_layer<<<nb(s.rsell.n_slices), 256, 0, st>>>(s.rsell.rows, s.rsell.n_rows, s.rsell.n_slices, s.rsell.L,

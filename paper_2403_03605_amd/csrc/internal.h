@@ -127,6 +127,7 @@ struct Sell {
   int32_t halo_max = 0;  // 0: no staging
   int32_t wg_waves = 4;  // at most this many slices (wavefronts) per workgroup of the staged pass
   std::vector<int64_t> h_tile;  // host: spatial tile of each row (empty: rows not tiled)
+  bool fp64_slots = false;      // slot records keep FP64 coefficients in the mixed form too
 };
 
 // Lanes per row: enough wavefronts to cover the chip, with as few lanes per row
@@ -154,6 +155,7 @@ struct Solver {
   bool unstable = false;
   int64_t pd_steps = 0, macro_steps = 0, n_rebuilds = 0;
   int64_t n_intact0 = 0;  // intact bonds after setup (pre-crack cuts removed)
+  std::vector<int64_t> h_node_tile;  // host: spatial tile of each node (empty: rows not tiled)
   double dt_bound_pd = 0.0;  // PD stability bound of the step
 
   // ---- PD ----

@@ -283,7 +283,7 @@ __global__ void k_pack_slots(int64_t n, const int32_t *col, uint32_t rb, const d
 }  // namespace
 
 void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col, bool fp64) {
-  const bool mixed = !fp64 && s.precision == MTS_MIXED;
+  const bool mixed = !fp64 && !out.fp64_slots && s.precision == MTS_MIXED;
   const int64_t n = out.n_slots + kSpareIters * WAVE;
   if (!out.slots) out.slots = s.arena.alloc<uint32_t>((size_t)n * (mixed ? 2 : 3));
   k_pack_slots<<<blocks_for(n), kThreads, 0, s.stream>>>(n, dev_col ? dev_col : out.col, 16u * (uint32_t)s.dim, out.coef,

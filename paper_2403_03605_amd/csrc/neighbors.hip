@@ -264,6 +264,7 @@ void build_neighbors(Solver &s) {
     std::stable_sort(rows.begin(), rows.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     s.sell.h_tile.resize(N);
     for (int64_t r = 0; r < N; r++) s.sell.h_tile[r] = key[rows[r]];
+    s.h_node_tile = key;
     std::vector<int32_t> row_of(N);
     for (int64_t r = 0; r < N; r++) row_of[rows[r]] = (int32_t)r;
     s.sell.row_of = ar.alloc<int32_t>(N);

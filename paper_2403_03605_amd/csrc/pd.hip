@@ -546,16 +546,37 @@ struct Link1Args {
   // substep's input) and write the next predictor, instead of storing W_m
   int add;
   double *Uxu, *Uxu_pred, *Uv, *Ua;
+  // staged form: workgroup b runs slices wg_start[b] .. wg_start[b + 1] - 1
+  // and first copies the records halo_ids[halo_off[b] ..] into LDS
+  const int32_t *wg_start, *halo_off, *halo_ids;
 };
 
-template <int DIM, int L>
+template <int DIM, int L, bool HALO>
 __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
   constexpr int S = WAVE / L, TM = 4;
   constexpr uint32_t RB = 16u * DIM;
   static_assert(kSpareIters >= 2 * TM - 1, "spare iterations must cover the look-ahead chunk");
-  const int64_t slice = __builtin_amdgcn_readfirstlane(
-      (int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
-  if (slice >= A.n_slices) return;
+  extern __shared__ double2 lds[];
+  int64_t slice;
+  if constexpr (HALO) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (!A.first) {  // the first substep has no bond loop: nothing to stage (uniform per launch)
+      const int h0 = A.halo_off[b], nh = A.halo_off[b + 1] - h0;
+      const double2 *src = reinterpret_cast<const double2 *>(A.w_in);
+      for (int h = threadIdx.x; h < nh; h += kBlock) {
+        const uint32_t rb = (uint32_t)A.halo_ids[h0 + h] * RB;
+#pragma unroll
+        for (int q = 0; q < DIM; q++) lds[h * DIM + q] = ld32(src, rb + 16u * q);
+      }
+      __syncthreads();
+    }
+    const int s0 = A.wg_start[b], w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (w >= A.wg_start[b + 1] - s0) return;  // after the barrier every wave of the group has staged
+    slice = s0 + w;
+  } else {
+    slice = __builtin_amdgcn_readfirstlane((int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+    if (slice >= A.n_slices) return;
+  }
   const int lane = threadIdx.x & (WAVE - 1);
   const int jl = lane / L, l = lane % L;
   const int64_t r = slice * S + jl;
@@ -614,7 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
         double rec[2 * DIM];
 #pragma unroll
         for (int h = 0; h < DIM; h++) {
-          const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.w_in), C.c[q] + 16u * h);
+          double2 v2;
+          if constexpr (HALO) v2 = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(lds) + C.c[q] + 16u * h);
+          else v2 = ld32(reinterpret_cast<const double2 *>(A.w_in), C.c[q] + 16u * h);
           rec[2 * h] = v2.x;
           rec[2 * h + 1] = v2.y;
         }
@@ -970,8 +993,21 @@ void link_final_substep(Solver &s, int j, int k, bool add) {
     A.Uv = s.v;
     A.Ua = s.a;
   }
-  const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
-#define MTS_LF(D, LL) k_link_final<D, LL><<<grid, kBlock, 0, s.stream>>>(A, s.prm)
+  const bool halo = s.rsell.halo_max > 0;
+  unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
+  size_t shm = 0;
+  if (halo) {  // the slot records hold LDS offsets: the staged kernel is the only one that reads them
+    A.wg_start = s.rsell.wg_start;
+    A.halo_off = s.rsell.halo_off;
+    A.halo_ids = s.rsell.halo_ids;
+    grid = (unsigned)s.rsell.n_wg;
+    shm = (size_t)s.rsell.halo_max * 16 * s.dim;
+  }
+#define MTS_LF(D, LL)                                                                        \
+  do {                                                                                       \
+    if (halo) k_link_final<D, LL, true><<<grid, kBlock, shm, s.stream>>>(A, s.prm);          \
+    else k_link_final<D, LL, false><<<grid, kBlock, 0, s.stream>>>(A, s.prm);                \
+  } while (0)
   if (s.dim == 2) {
     switch (s.rsell.L) {
       case 1: MTS_LF(2, 1); break;
