@@ -235,6 +235,12 @@ def main():
         for name, k in (("link", mts.KT_LINK), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA)):
             n_l, ms_l = s.kernel_time(k)
             other[name] = {"launch_groups": n_l, "total_ms": ms_l}
+        # the multiplier solve streams the packed inverse once per macro step:
+        # its bytes over the whole phase's time bound the GEMV's rate from below
+        inv = s.query()["inverse_bytes"]
+        n_l, ms_l = other["lambda"]["launch_groups"], other["lambda"]["total_ms"]
+        other["lambda"]["inverse_bytes"] = inv
+        other["lambda"]["inverse_GBps_over_phase"] = (inv * n_l / (ms_l * 1e-3) / 1e9) if ms_l > 0 else None
         roof["other_phases"] = other
     info = s.query()
     s.close()

@@ -88,6 +88,9 @@ typedef struct mts_info {
   int64_t device_bytes;  /* device memory the solver holds */
   int32_t dim, precision;
   double dt_bound_pd;    /* PD stability bound of the step (create rejects dt_pd above it) */
+  int64_t inverse_bytes; /* bytes of the packed inverse of H that each multiplier solve
+                            (Eq. 49) reads: 64 x 64 FP64 lower tiles of every
+                            component block; 0 in pure-PD mode */
 } mts_info;
 
 /* Energies of the current state (J, per unit thickness in 2D) and the bonds

@@ -797,6 +797,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->dim = s.dim;
   o->precision = s.precision;
   o->dt_bound_pd = s.dt_bound_pd;
+  o->inverse_bytes = s.sym.n_tiles * 64 * 64 * (int64_t)sizeof(double);
 }
 
 extern "C" {
