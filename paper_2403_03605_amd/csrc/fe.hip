@@ -179,27 +179,32 @@ __global__ void k_fe_init(int64_t nfe, int dim, const uint8_t *nact, const uint8
   }
 }
 
-__global__ void k_fe_predict(int64_t nfe, int dim, const uint8_t *nact, const uint8_t *bc, double dt, double hdt2,
-                             double vbc, const double *u, const double *v, const double *a, double *ut) {
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nfe || !nact[n]) return;
-  for (int d = 0; d < dim; d++) {
-    int64_t t = n * dim + d;
-    ut[t] = bc[t] ? u[t] + dt * vbc : (u[t] + dt * v[t]) + hdt2 * a[t];
-  }
+// Predictor of the FE free problem (beta = 0), one dof: prescribed-velocity
+// dofs move at vbc.
+__device__ __forceinline__ double fe_predict(const uint8_t *bc, const double *u, const double *v, const double *a,
+                                             int64_t t, double dt, double hdt2, double vbc) {
+  return bc[t] ? u[t] + dt * vbc : (u[t] + dt * v[t]) + hdt2 * a[t];
 }
 
 // Element force f_e = sum_gp alpha B^T D B u_e detJ t (engineering shear strains).
-template <int DIM>
+// PRED: u_e is the free problem's predictor of (u, v, a), formed per element
+// (the node-wise kernel that follows stores the same values).
+template <int DIM, bool PRED>
 __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *eact, const double *gpa,
-                                const double *u, double thick, const FeTables *__restrict__ tab, double *fe_buf) {
+                                const double *u, const double *v, const double *acc, const uint8_t *bc, double dt,
+                                double hdt2, double vbc, double thick, const FeTables *__restrict__ tab,
+                                double *fe_buf) {
   constexpr int NEN = DIM == 2 ? 4 : 8;
   constexpr int NSTR = DIM == 2 ? 3 : 6;
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne || !eact[e]) return;
   double ue[NEN * DIM], fe[NEN * DIM];
   for (int a = 0; a < NEN; a++)
-    for (int d = 0; d < DIM; d++) ue[a * DIM + d] = u[(int64_t)conn[e * NEN + a] * DIM + d];
+    for (int d = 0; d < DIM; d++) {
+      const int64_t t = (int64_t)conn[e * NEN + a] * DIM + d;
+      if constexpr (PRED) ue[a * DIM + d] = fe_predict(bc, u, v, acc, t, dt, hdt2, vbc);
+      else ue[a * DIM + d] = u[t];
+    }
   for (int t = 0; t < NEN * DIM; t++) fe[t] = 0.0;
   for (int g = 0; g < NEN; g++) {
     double al = gpa[e * NEN + g];
@@ -244,13 +249,13 @@ __global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *
 }
 
 // Gather element forces per node (ascending element order), then the free
-// problem's acceleration and velocity (Eq. 47a).
+// problem's predictor, acceleration and velocity (Eq. 47a).
 // Nodes that carry no multiplier (no constraint interpolates from them) are
 // final after the free problem and are written to the state directly.
 __global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n2e_ptr, const int32_t *n2e,
                                  const uint8_t *eact, const uint8_t *nact, const uint8_t *bc, const double *fe_buf,
-                                 const double *PF, const double *mF, double *v, double *a, double hdt,
-                                 double vbc, double *at, double *vt, const int32_t *f2c_ptr, const double *ut,
+                                 const double *PF, const double *mF, double *v, double *a, double dt, double hdt2,
+                                 double hdt, double vbc, double *at, double *vt, const int32_t *f2c_ptr, double *ut,
                                  double *u) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nfe || !nact[n]) return;
@@ -264,6 +269,7 @@ __global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n
   const bool final_now = !f2c_ptr || f2c_ptr[n + 1] == f2c_ptr[n];
   for (int d = 0; d < dim; d++) {
     int64_t t = n * dim + d;
+    const double un = fe_predict(bc, u, v, a, t, dt, hdt2, vbc);  // as the element pass formed it
     double an, vn;
     if (bc[t]) {
       an = 0.0;
@@ -273,10 +279,11 @@ __global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n
       vn = v[t] + hdt * (a[t] + an);
     }
     if (final_now) {
-      u[t] = ut[t];
+      u[t] = un;
       v[t] = vn;
       a[t] = an;
     } else {
+      ut[t] = un;
       at[t] = an;
       vt[t] = vn;
     }
@@ -454,19 +461,19 @@ void fe_setup(Solver &s) {
 void fe_free_step(Solver &s) {
   hipStream_t st = s.stream;
   int64_t nfe = s.nfe;
-  k_fe_predict<<<nb(nfe), 256, 0, st>>>(nfe, s.dim, s.nact, s.bc, s.prm.dtF, s.prm.hdt2F, s.p.vel_bc, s.uF, s.vF,
-                                        s.aF, s.ut);
-  MTS_LAUNCH_CHECK();
+  const double dt = s.prm.dtF, hdt2 = s.prm.hdt2F, vbc = s.p.vel_bc;
   if (s.dim == 2)
-    k_fe_elem_force<2><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness,
-                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+    k_fe_elem_force<2, true><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.vF, s.aF, s.bc, dt, hdt2,
+                                                       vbc, s.p.thickness, static_cast<const FeTables *>(s.fe_tab),
+                                                       s.fe_buf);
   else
-    k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.ut, s.p.thickness,
-                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+    k_fe_elem_force<3, true><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.vF, s.aF, s.bc, dt, hdt2,
+                                                       vbc, s.p.thickness, static_cast<const FeTables *>(s.fe_tab),
+                                                       s.fe_buf);
   MTS_LAUNCH_CHECK();
   k_fe_gather_free<<<nb(nfe), 256, 0, st>>>(nfe, s.dim, s.nen, s.n2e_ptr, s.n2e, s.eact, s.nact, s.bc, s.fe_buf,
-                                            s.PF, s.mF, s.vF, s.aF, s.prm.hdtF, s.p.vel_bc, s.at, s.vt, s.f2c_ptr,
-                                            s.ut, s.uF);
+                                            s.PF, s.mF, s.vF, s.aF, dt, hdt2, s.prm.hdtF, vbc, s.at, s.vt,
+                                            s.f2c_ptr, s.ut, s.uF);
   MTS_LAUNCH_CHECK();
 }
 
@@ -475,11 +482,13 @@ void fe_free_step(Solver &s) {
 void fe_elem_forces_current(Solver &s) {
   hipStream_t st = s.stream;
   if (s.dim == 2)
-    k_fe_elem_force<2><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.p.thickness,
-                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+    k_fe_elem_force<2, false><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, nullptr, nullptr, nullptr,
+                                                        0.0, 0.0, 0.0, s.p.thickness,
+                                                        static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
   else
-    k_fe_elem_force<3><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.p.thickness,
-                                                 static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+    k_fe_elem_force<3, false><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, nullptr, nullptr, nullptr,
+                                                        0.0, 0.0, 0.0, s.p.thickness,
+                                                        static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
   MTS_LAUNCH_CHECK();
 }
 
