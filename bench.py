@@ -28,14 +28,14 @@ HBM_PEAK = 8.0e12
 
 def bytes_per_launch(info, inst):
     """Algorithmic HBM bytes of one fused PD substep launch (layout of this build):
-    per bond slot: neighbour index 4 B + bond coefficient (8 B FP64, 4 B mixed)
-    + bond-state bit 1/8 B;
+    per bond slot: the slot record the library reports (FP64: coefficient 8 B +
+    neighbour offset 4 B; mixed: 4 + 4 B, or 6 B when the neighbour records are
+    staged in LDS and two slots share a 12-byte record) + bond-state bit 1/8 B;
     per node: position (8 dim), u read (8 dim), v and a read+write (32 dim),
     predicted u write (8 dim), mass 8, constraint index 4, damage 8/m.
     Neighbour positions and displacements are counted once per node."""
     dim = info["dim"]
-    coef = 8.0 if info["precision"] == 0 else 4.0
-    per_bond = 4.0 + coef + 1.0 / 8.0
+    per_bond = info["slot_bytes"] + 1.0 / 8.0
     per_node = 8.0 * dim * (1 + 1 + 4 + 1) + 8 + 4 + 8.0 / inst["m"]
     return info["nnz"] * per_bond + info["n_pd"] * per_node, per_bond, per_node
 

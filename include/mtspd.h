@@ -91,6 +91,9 @@ typedef struct mts_info {
   int64_t inverse_bytes; /* bytes of the packed inverse of H that each multiplier solve
                             (Eq. 49) reads: 64 x 64 FP64 lower tiles of every
                             component block; 0 in pure-PD mode */
+  double slot_bytes;     /* bytes of slot record the bond pass reads per bond slot: 12 (FP64
+                            coefficient and neighbour offset), 8 (mixed), 6 (mixed with
+                            neighbour records staged in LDS: two slots per 12-byte record) */
 } mts_info;
 
 /* Energies of the current state (J, per unit thickness in 2D) and the bonds

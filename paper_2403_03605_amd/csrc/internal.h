@@ -128,6 +128,7 @@ struct Sell {
   int32_t wg_waves = 4;  // at most this many slices (wavefronts) per workgroup of the staged pass
   std::vector<int64_t> h_tile;  // host: spatial tile of each row (empty: rows not tiled)
   bool fp64_slots = false;      // slot records keep FP64 coefficients in the mixed form too
+  bool pair_slots = false;      // mixed staged pass: one record per two iterations (16-bit list positions)
 };
 
 // Lanes per row: enough wavefronts to cover the chip, with as few lanes per row

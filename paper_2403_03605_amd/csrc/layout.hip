@@ -282,6 +282,45 @@ __global__ void k_pack_slots(int64_t n, const int32_t *col, uint32_t rb, const d
 }
 }  // namespace
 
+namespace {
+// Mixed-form slot records of the staged pass, one per two iterations of a
+// lane: {coef32(t), coef32(t + 1), idx(t) | idx(t + 1) << 16}, idx being the
+// neighbour's position in the workgroup's LDS list.  Record (slice, pair P,
+// lane) sits at (slice * TP + P) * 64 + lane; an odd T leaves the second half
+// of the last pair empty, and kSpareIters * 64 empty records follow.
+__global__ void k_pack_pairs(int64_t n_rec, int64_t n_real, int T, int TP, const int32_t *local, const float *coef32,
+                             uint32_t *rec) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rec) return;
+  uint32_t c0 = 0u, c1 = 0u, ix = 0u;
+  if (r < n_real) {
+    const int64_t lane = r % WAVE, g = r / WAVE, sl = g / TP, pr = g % TP;
+    const int t0 = (int)(2 * pr);
+    const int64_t p0 = (sl * T + t0) * WAVE + lane;
+    c0 = __float_as_uint(coef32[p0]);
+    ix = (uint32_t)local[p0];
+    if (t0 + 1 < T) {
+      c1 = __float_as_uint(coef32[p0 + WAVE]);
+      ix |= (uint32_t)local[p0 + WAVE] << 16;
+    }
+  }
+  rec[3 * r] = c0;
+  rec[3 * r + 1] = c1;
+  rec[3 * r + 2] = ix;
+}
+}  // namespace
+
+void sell_pack_pairs(Solver &s, Sell &out, const int32_t *dev_local) {
+  const int T = out.T, TP = (T + 1) / 2;
+  const int64_t n_real = out.n_slices * TP * WAVE, n_rec = n_real + kSpareIters * WAVE;
+  uint32_t *rec = s.arena.alloc<uint32_t>((size_t)n_rec * 3);
+  k_pack_pairs<<<blocks_for(n_rec), kThreads, 0, s.stream>>>(n_rec, n_real, T, TP, dev_local, out.coef32, rec);
+  MTS_LAUNCH_CHECK();
+  if (out.slots) s.arena.release(out.slots);
+  out.slots = rec;
+  out.pair_slots = true;
+}
+
 void sell_pack_slots(Solver &s, Sell &out, const int32_t *dev_col, bool fp64) {
   const bool mixed = !fp64 && !out.fp64_slots && s.precision == MTS_MIXED;
   const int64_t n = out.n_slots + kSpareIters * WAVE;
@@ -303,7 +342,7 @@ void sell_build_halo(Solver &s, Sell &out) {
   int dev = 0, lds_max = 65536;
   MTS_HIP(hipGetDevice(&dev));
   MTS_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const int kHaloMax = std::min(G == 8 ? 81920 : 65536, lds_max) / (16 * s.dim);  // records that fit
+  const int kHaloMax = std::min(G == 8 ? 81920 : 65536, lds_max) / (16 * s.dim);  // records that fit (< 2^16)
   out.halo_max = 0;
   if (!out.n_slices) return;
   hipStream_t st = s.stream;
@@ -352,7 +391,9 @@ void sell_build_halo(Solver &s, Sell &out) {
   MTS_HIP(hipMemcpyAsync(out.halo_off, off.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(out.halo_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(dlocal, local.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-  sell_pack_slots(s, out, dlocal);
+  // the mixed form's staged pass reads paired records with 16-bit list positions
+  if (!out.fp64_slots && s.precision == MTS_MIXED) sell_pack_pairs(s, out, dlocal);
+  else sell_pack_slots(s, out, dlocal);
   MTS_HIP(hipStreamSynchronize(st));
   s.arena.release(dlocal);
   out.halo_max = hmax;

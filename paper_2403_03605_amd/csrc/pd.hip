@@ -122,9 +122,30 @@ __device__ __forceinline__ uint32_t lane_zero() {
 
 // Iterations t .. t + TM - 1 of the slice whose state words start at wo and
 // whose slot index of (iteration 0, this lane) is so.
-template <bool MX, int TM>
+// PAIR (mixed form, staged pass): one record per two iterations,
+// {coef(t), coef(t + 1), idx(t) | idx(t + 1) << 16} with idx the neighbour's
+// position in the workgroup's LDS list; so is then the record index of
+// (iterations 0 and 1, this lane) and t is even.  Both c entries of a pair
+// keep the packed word, which is split where it is used.
+template <bool MX, int TM, bool PAIR = false>
 __device__ __forceinline__ void load_slot_chunk(const uint64_t *mask, const uint32_t *slots, int64_t wo, uint32_t so,
                                                 uint32_t zoff, int t, SlotChunk<TM> &C) {
+  if constexpr (PAIR) {
+    static_assert(MX && TM % 2 == 0, "paired records: mixed form, whole pairs per chunk");
+#pragma unroll
+    for (int q = 0; q < TM; q++) C.w[q] = ld32(mask, (uint32_t)(wo + t + q) * 8u + zoff);
+#pragma unroll
+    for (int p = 0; p < TM / 2; p++) {
+      const uint32_t rpos = so + (uint32_t)((t >> 1) + p) * WAVE;
+      const uint3 v = ld32(reinterpret_cast<const uint3 *>(slots), rpos * 12u);
+      C.f0[2 * p] = v.x;
+      C.f0[2 * p + 1] = v.y;
+      C.c[2 * p] = v.z;
+      C.c[2 * p + 1] = v.z;
+      C.f1[2 * p] = C.f1[2 * p + 1] = 0u;
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < TM; q++) {
     const uint32_t pos = so + (uint32_t)(t + q) * WAVE;
@@ -143,7 +164,7 @@ __device__ __forceinline__ void load_slot_chunk(const uint64_t *mask, const uint
   }
 }
 
-template <int DIM, int L, bool MX, int TM, bool HALO = false>
+template <int DIM, int L, bool MX, int TM, bool HALO = false, bool PAIR = false>
 __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice,
                                              const double2 *lds = nullptr, const SlotChunk<TM> *first = nullptr) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
@@ -157,7 +178,8 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
   const int jl = lane / L, l = lane % L;
   const int T = A.T;
   const int64_t wo = slice * T;
-  const uint32_t so = (uint32_t)(wo * WAVE) + (uint32_t)lane;  // slot index of (iteration 0, this lane)
+  // slot index of (iteration 0, this lane); with paired records, record index of (iterations 0 and 1)
+  const uint32_t so = (uint32_t)((PAIR ? slice * ((T + 1) >> 1) : wo) * WAVE) + (uint32_t)lane;
   const uint32_t zoff = lane_zero();
   // The first chunk of slot data does not depend on the row's node: a caller
   // may have requested it already (before its staging loads).
@@ -212,7 +234,10 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
 #pragma unroll
       for (int h = 0; h < DIM; h++) {
         double2 v2;
-        if constexpr (HALO) v2 = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(lds) + C.c[q] + 16u * h);
+        if constexpr (PAIR) {
+          const uint32_t idx = (q & 1) ? (C.c[q] >> 16) : (C.c[q] & 0xffffu);
+          v2 = lds[idx * DIM + h];
+        } else if constexpr (HALO) v2 = *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(lds) + C.c[q] + 16u * h);
         else v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), C.c[q] + 16u * h);
         rec[2 * h] = v2.x;
         rec[2 * h + 1] = v2.y;
@@ -297,12 +322,12 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
       }
     }
   };
-  if (!first) load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, 0, C0);
+  if (!first) load_slot_chunk<MX, TM, PAIR>(A.mask, A.slots, wo, so, zoff, 0, C0);
   for (int t0 = 0; t0 < T; t0 += 2 * TM) {
-    load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, t0 + TM, C1);
+    load_slot_chunk<MX, TM, PAIR>(A.mask, A.slots, wo, so, zoff, t0 + TM, C1);
     run_chunk(t0, C0);
     if (t0 + TM >= T) break;
-    load_slot_chunk<MX, TM>(A.mask, A.slots, wo, so, zoff, t0 + 2 * TM, C0);
+    load_slot_chunk<MX, TM, PAIR>(A.mask, A.slots, wo, so, zoff, t0 + 2 * TM, C0);
     run_chunk(t0 + TM, C1);
   }
   for (int off = L / 2; off >= 1; off >>= 1) {
@@ -370,21 +395,23 @@ __global__ __launch_bounds__(NW * 64, NW == 8 ? 4 : 1) void k_pd_substep_halo(Su
   const int s0 = A.wg_start[b], w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool active = w < A.wg_start[b + 1] - s0;  // wave-uniform
   const int64_t slice = s0 + w;
+  // the mixed form's staged pass reads paired slot records
   if constexpr (EARLY) {
     // the first chunk of slot data is requested before the staging loads
     SlotChunk<4> C0;
     if (active)
-      load_slot_chunk<MX, 4>(A.mask, A.slots, slice * A.T,
-                             (uint32_t)(slice * A.T * WAVE) + (threadIdx.x & (WAVE - 1)), lane_zero(), 0, C0);
+      load_slot_chunk<MX, 4, MX>(
+          A.mask, A.slots, slice * A.T,
+          (uint32_t)(slice * (MX ? (A.T + 1) >> 1 : A.T) * WAVE) + (threadIdx.x & (WAVE - 1)), lane_zero(), 0, C0);
     stage_halo<DIM, NW * 64>(A, b, lds);
     __syncthreads();
     if (!active) return;  // after the barrier every wave of the group has staged
-    substep_body<DIM, L, MX, 4, true>(A, P, slice, lds, &C0);
+    substep_body<DIM, L, MX, 4, true, MX>(A, P, slice, lds, &C0);
   } else {
     stage_halo<DIM, NW * 64>(A, b, lds);
     __syncthreads();
     if (!active) return;
-    substep_body<DIM, L, MX, 4, true>(A, P, slice, lds);
+    substep_body<DIM, L, MX, 4, true, MX>(A, P, slice, lds);
   }
 }
 
@@ -845,6 +872,8 @@ void pd_substep(Solver &s, int j) {
   const unsigned grid = (unsigned)((A.n_slices * WAVE + kBlock - 1) / kBlock);
   const int L = s.sell.L;
   if (s.sell.halo_max > 0) {
+    // the staged pass reads paired slot records in the mixed form
+    if ((s.precision == MTS_MIXED) != s.sell.pair_slots) throw ArgError{"internal: staged pass slot record layout mismatch"};
     const size_t shm = (size_t)s.sell.halo_max * 16 * s.dim;
     const int nw = s.sell.wg_waves;
     const unsigned hgrid = (unsigned)s.sell.n_wg;

@@ -798,6 +798,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->precision = s.precision;
   o->dt_bound_pd = s.dt_bound_pd;
   o->inverse_bytes = s.sym.n_tiles * 64 * 64 * (int64_t)sizeof(double);
+  o->slot_bytes = s.sell.pair_slots ? 6.0 : s.precision == MTS_MIXED ? 8.0 : 12.0;
 }
 
 extern "C" {
