@@ -313,10 +313,11 @@ __global__ void k_pack_pairs(int64_t n_rec, int64_t n_real, int T, int TP, const
 void sell_pack_pairs(Solver &s, Sell &out, const int32_t *dev_local) {
   const int T = out.T, TP = (T + 1) / 2;
   const int64_t n_real = out.n_slices * TP * WAVE, n_rec = n_real + kSpareIters * WAVE;
+  // the unpaired records are not needed any more: free them first (lower peak)
+  if (out.slots) s.arena.release(out.slots);
   uint32_t *rec = s.arena.alloc<uint32_t>((size_t)n_rec * 3);
   k_pack_pairs<<<blocks_for(n_rec), kThreads, 0, s.stream>>>(n_rec, n_real, T, TP, dev_local, out.coef32, rec);
   MTS_LAUNCH_CHECK();
-  if (out.slots) s.arena.release(out.slots);
   out.slots = rec;
   out.pair_slots = true;
 }
