@@ -65,7 +65,8 @@ struct SubstepArgs {
   int T;
   const int32_t *width;
   const int64_t *slot_off, *word_off;
-  const uint32_t *slots;  // per slot: record byte offset (LDS offset when staged) and coefficient
+  const uint32_t *slots;  // per slot: record byte offset (LDS offset when staged) and coefficient;
+                          // mixed staged pass: one record per two slots (see load_slot_chunk)
   const int32_t *halo_off, *halo_ids;  // per-workgroup staged neighbour lists (or nullptr)
   const int32_t *wg_start;             // staged pass: first slice of each workgroup
   uint64_t *mask;
@@ -873,7 +874,8 @@ void pd_substep(Solver &s, int j) {
   const int L = s.sell.L;
   if (s.sell.halo_max > 0) {
     // the staged pass reads paired slot records in the mixed form
-    if ((s.precision == MTS_MIXED) != s.sell.pair_slots) throw ArgError{"internal: staged pass slot record layout mismatch"};
+    if ((s.precision == MTS_MIXED) != s.sell.pair_slots)
+      throw ArgError{"internal: staged pass slot record layout mismatch"};
     const size_t shm = (size_t)s.sell.halo_max * 16 * s.dim;
     const int nw = s.sell.wg_waves;
     const unsigned hgrid = (unsigned)s.sell.n_wg;
