@@ -79,3 +79,9 @@ def test_2d_variants_bit_identical(mts, precision):
         print("  variant", env, flush=True)
         got, _ = _run(mts, inst, 50, env)
         _same(ref, got)
+    # four lanes per row: 7 iterations, so the mixed staged pass's last paired
+    # slot record is half empty
+    ref4, _ = _run(mts, inst, 50, {"MTS_LANES": "4"})
+    print("  variant lanes 4, staged vs direct", flush=True)
+    got, _ = _run(mts, inst, 50, {"MTS_LANES": "4", "MTS_HALO": "0"})
+    _same(ref4, got)
