@@ -21,7 +21,7 @@ namespace mts {
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
                   const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
 void link_records_init(Solver &s);
-void link_final_substep(Solver &s, int j, int k, bool add);
+void link_final_substep(Solver &s, int j, int k, bool add, int side);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 
 namespace {
@@ -466,9 +466,9 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   vlog(s, "coupling: H inverted");
 }
 
-void coupling_solve_and_correct(Solver &s) {
+bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe) {
   coupling_lambda(s);
-  coupling_link(s);
+  return coupling_link(s, fuse_next_fe);
 }
 
 void coupling_lambda(Solver &s) {
@@ -479,20 +479,34 @@ void coupling_lambda(Solver &s) {
   MTS_LAUNCH_CHECK();
   sym_blocks_apply(s, s.rhs, s.lam, s.lam0);  // lambda_0 <- lambda_m for the next macro step too
   s.prof_end(MTS_KT_LAMBDA, e0);
-  fe_correct(s);
 }
 
-void coupling_link(Solver &s) {
-  // PD: U = V + Y lambda_m by re-running the link problem with lambda_m
+bool coupling_link(Solver &s, bool fuse_next_fe) {
+  // FE: the ring nodes' final update; PD: U = V + Y lambda_m by re-running the
+  // link problem with lambda_m.  Both need only lambda_m, so the FE pass runs as
+  // extra workgroups of the first link launch; with fuse_next_fe (2D, m >= 3)
+  // the next macro step's FE free step (element forces, then the gather)
+  // follows in the second and third (they read the FE state this step's
+  // correction leaves).
+  if (!s.rsell.n_rows) {
+    fe_correct(s);
+    return false;
+  }
+  const bool fuse = fuse_next_fe && s.m >= 3 && s.dim == 2;
   hipEvent_t e1 = nullptr;
   s.prof_begin(MTS_KT_LINK, &e1);
   // m substeps from rest; the last one adds W_m into the PD state directly
   int k = 0;
   for (int j = 1; j <= s.m; j++) {
-    link_final_substep(s, j, k, j == s.m);
+    int side = kSideNone;
+    if (j == 1 && s.n_ring) side = kSideRing;
+    if (fuse && j == 2) side = kSideElem;
+    if (fuse && j == 3) side = kSideGather;
+    link_final_substep(s, j, k, j == s.m, side);
     k ^= 1;
   }
   s.prof_end(MTS_KT_LINK, e1);
+  return fuse;
 }
 
 }  // namespace mts

@@ -3,20 +3,13 @@
 // every Gauss point of the stiffness and of the row-sum lumped mass (Eq. 24-34),
 // explicit Newmark (gamma = 1/2, beta = 0) at dt_FE = m dt_PD, element forces
 // computed per element and gathered per node in a fixed order (no atomics).
-#include "internal.h"
+#include "fe_device.h"
 
 #include <cmath>
 
 namespace mts {
 
 namespace {
-
-struct FeTables {
-  double N[8][8];       // [gauss point][local node]
-  double dN[8][8][3];   // physical derivatives
-  double D[6][6];
-  double detJ;
-};
 
 __device__ inline double nat(int dim, int a, int c) {
   // local node a natural coordinate along axis c: Q4 (-1,-1),(1,-1),(1,1),(-1,1); Hex8 adds z.
@@ -179,150 +172,15 @@ __global__ void k_fe_init(int64_t nfe, int dim, const uint8_t *nact, const uint8
   }
 }
 
-// Predictor of the FE free problem (beta = 0), one dof: prescribed-velocity
-// dofs move at vbc.
-__device__ __forceinline__ double fe_predict(const uint8_t *bc, const double *u, const double *v, const double *a,
-                                             int64_t t, double dt, double hdt2, double vbc) {
-  return bc[t] ? u[t] + dt * vbc : (u[t] + dt * v[t]) + hdt2 * a[t];
-}
-
-// Element force f_e = sum_gp alpha B^T D B u_e detJ t (engineering shear strains).
-// PRED: u_e is the free problem's predictor of (u, v, a), formed per element
-// (the node-wise kernel that follows stores the same values).
 template <int DIM, bool PRED>
-__global__ void k_fe_elem_force(int64_t ne, const int32_t *conn, const uint8_t *eact, const double *gpa,
-                                const double *u, const double *v, const double *acc, const uint8_t *bc, double dt,
-                                double hdt2, double vbc, double thick, const FeTables *__restrict__ tab,
-                                double *fe_buf) {
-  constexpr int NEN = DIM == 2 ? 4 : 8;
-  constexpr int NSTR = DIM == 2 ? 3 : 6;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne || !eact[e]) return;
-  double ue[NEN * DIM], fe[NEN * DIM];
-  for (int a = 0; a < NEN; a++)
-    for (int d = 0; d < DIM; d++) {
-      const int64_t t = (int64_t)conn[e * NEN + a] * DIM + d;
-      if constexpr (PRED) ue[a * DIM + d] = fe_predict(bc, u, v, acc, t, dt, hdt2, vbc);
-      else ue[a * DIM + d] = u[t];
-    }
-  for (int t = 0; t < NEN * DIM; t++) fe[t] = 0.0;
-  for (int g = 0; g < NEN; g++) {
-    double al = gpa[e * NEN + g];
-    if (al == 0.0) continue;
-    double eps[NSTR], sig[NSTR];
-    for (int r = 0; r < NSTR; r++) eps[r] = 0.0;
-    for (int a = 0; a < NEN; a++) {
-      const double *dN = tab->dN[g][a];
-      const double *uu = ue + a * DIM;
-      if (DIM == 2) {
-        eps[0] += dN[0] * uu[0];
-        eps[1] += dN[1] * uu[1];
-        eps[2] += dN[1] * uu[0] + dN[0] * uu[1];
-      } else {
-        eps[0] += dN[0] * uu[0];
-        eps[1] += dN[1] * uu[1];
-        eps[2] += dN[2] * uu[2];
-        eps[3] += dN[1] * uu[0] + dN[0] * uu[1];
-        eps[4] += dN[2] * uu[1] + dN[1] * uu[2];
-        eps[5] += dN[2] * uu[0] + dN[0] * uu[2];
-      }
-    }
-    for (int r = 0; r < NSTR; r++) {
-      sig[r] = 0.0;
-      for (int c = 0; c < NSTR; c++) sig[r] += tab->D[r][c] * eps[c];
-    }
-    double scale = al * tab->detJ * thick;
-    for (int a = 0; a < NEN; a++) {
-      const double *dN = tab->dN[g][a];
-      double *f = fe + a * DIM;
-      if (DIM == 2) {
-        f[0] += scale * (dN[0] * sig[0] + dN[1] * sig[2]);
-        f[1] += scale * (dN[1] * sig[1] + dN[0] * sig[2]);
-      } else {
-        f[0] += scale * (dN[0] * sig[0] + dN[1] * sig[3] + dN[2] * sig[5]);
-        f[1] += scale * (dN[1] * sig[1] + dN[0] * sig[3] + dN[2] * sig[4]);
-        f[2] += scale * (dN[2] * sig[2] + dN[1] * sig[4] + dN[0] * sig[5]);
-      }
-    }
-  }
-  for (int t = 0; t < NEN * DIM; t++) fe_buf[e * NEN * DIM + t] = fe[t];
+__global__ void k_fe_elem_force(FeElemArgs E) {
+  fe_elem_force_one<DIM, PRED>(E, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Gather element forces per node (ascending element order), then the free
-// problem's predictor, acceleration and velocity (Eq. 47a).
-// Nodes that carry no multiplier (no constraint interpolates from them) are
-// final after the free problem and are written to the state directly.
-__global__ void k_fe_gather_free(int64_t nfe, int dim, int nen, const int32_t *n2e_ptr, const int32_t *n2e,
-                                 const uint8_t *eact, const uint8_t *nact, const uint8_t *bc, const double *fe_buf,
-                                 const double *PF, const double *mF, double *v, double *a, double dt, double hdt2,
-                                 double hdt, double vbc, double *at, double *vt, const int32_t *f2c_ptr, double *ut,
-                                 double *u) {
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nfe || !nact[n]) return;
-  double f[3] = {0.0, 0.0, 0.0};
-  for (int t = n2e_ptr[n]; t < n2e_ptr[n + 1]; t++) {
-    int64_t e = n2e[t] / nen;
-    int la = n2e[t] % nen;
-    if (!eact[e]) continue;
-    for (int d = 0; d < dim; d++) f[d] += fe_buf[(e * nen + la) * dim + d];
-  }
-  const bool final_now = !f2c_ptr || f2c_ptr[n + 1] == f2c_ptr[n];
-  for (int d = 0; d < dim; d++) {
-    int64_t t = n * dim + d;
-    const double un = fe_predict(bc, u, v, a, t, dt, hdt2, vbc);  // as the element pass formed it
-    double an, vn;
-    if (bc[t]) {
-      an = 0.0;
-      vn = vbc;
-    } else {
-      an = (PF[t] - f[d]) / mF[n];
-      vn = v[t] + hdt * (a[t] + an);
-    }
-    if (final_now) {
-      u[t] = un;
-      v[t] = vn;
-      a[t] = an;
-    } else {
-      ut[t] = un;
-      at[t] = an;
-      vt[t] = vn;
-    }
-  }
-}
+__global__ void k_fe_gather_free(FeGatherArgs G) { fe_gather_free_one(G, (int64_t)blockIdx.x * blockDim.x + threadIdx.x); }
 
-// Final update of the overlap FE nodes: U = V + Y^FE lambda with
-// Y^FE = (-M^-1 G_F^T, -dt/2 M^-1 G_F^T, 0) (Eq. 50, link problem Eq. 47b at
-// beta = 0).  One wavefront per node, lanes over its constraint entries.
-__global__ void k_fe_correct_ring(int64_t n_ring, const int32_t *ring, int dim, int nen, const uint8_t *bc,
-                                  const int32_t *f2c_ptr, const int32_t *f2c, const double *cw, const double *lam,
-                                  const double *mF, const double *ut, const double *vt, const double *at,
-                                  double hdt, double *uF, double *vF, double *aF) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  if (w >= n_ring) return;
-  const int64_t n = ring[w];
-  double tl[3] = {0.0, 0.0, 0.0};
-  for (int t = f2c_ptr[n] + lane; t < f2c_ptr[n + 1]; t += WAVE) {
-    const int64_t q = f2c[t] / nen;
-    const int aa = f2c[t] % nen;
-    const double wgt = cw[q * nen + aa];
-    for (int d = 0; d < dim; d++) tl[d] += wgt * lam[q * dim + d];
-  }
-  for (int off = WAVE / 2; off >= 1; off >>= 1)
-    for (int d = 0; d < 3; d++) tl[d] += __shfl_down(tl[d], off, WAVE);
-  if (lane != 0) return;
-  for (int d = 0; d < dim; d++) {
-    const int64_t t = n * dim + d;
-    uF[t] = ut[t];
-    if (bc[t]) {
-      vF[t] = vt[t];
-      aF[t] = at[t];
-    } else {
-      const double g = tl[d] / mF[n];
-      aF[t] = at[t] - g;
-      vF[t] = vt[t] - hdt * g;
-    }
-  }
+__global__ void k_fe_correct_ring(FeRingArgs R) {
+  fe_correct_ring_wave(R, ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE, (int)(threadIdx.x & (WAVE - 1)));
 }
 
 inline unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -458,22 +316,83 @@ void fe_setup(Solver &s) {
   MTS_HIP(hipStreamSynchronize(st));
 }
 
+FeElemArgs fe_elem_args(Solver &s, bool predict) {
+  FeElemArgs E{};
+  E.ne = s.ne;
+  E.conn = s.conn;
+  E.eact = s.eact;
+  E.gpa = s.gpa;
+  E.u = s.uF;
+  if (predict) {
+    E.v = s.vF;
+    E.acc = s.aF;
+    E.bc = s.bc;
+    E.dt = s.prm.dtF;
+    E.hdt2 = s.prm.hdt2F;
+    E.vbc = s.p.vel_bc;
+  }
+  E.thick = s.p.thickness;
+  E.tab = static_cast<const FeTables *>(s.fe_tab);
+  E.fe_buf = s.fe_buf;
+  return E;
+}
+
+FeGatherArgs fe_gather_args(Solver &s) {
+  FeGatherArgs G{};
+  G.nfe = s.nfe;
+  G.dim = s.dim;
+  G.nen = s.nen;
+  G.n2e_ptr = s.n2e_ptr;
+  G.n2e = s.n2e;
+  G.eact = s.eact;
+  G.nact = s.nact;
+  G.bc = s.bc;
+  G.fe_buf = s.fe_buf;
+  G.PF = s.PF;
+  G.mF = s.mF;
+  G.v = s.vF;
+  G.a = s.aF;
+  G.dt = s.prm.dtF;
+  G.hdt2 = s.prm.hdt2F;
+  G.hdt = s.prm.hdtF;
+  G.vbc = s.p.vel_bc;
+  G.at = s.at;
+  G.vt = s.vt;
+  G.f2c_ptr = s.f2c_ptr;
+  G.ut = s.ut;
+  G.u = s.uF;
+  return G;
+}
+
+FeRingArgs fe_ring_args(Solver &s) {
+  FeRingArgs R{};
+  R.n_ring = s.n_ring;
+  R.ring = s.fe_ring;
+  R.dim = s.dim;
+  R.nen = s.nen;
+  R.bc = s.bc;
+  R.f2c_ptr = s.f2c_ptr;
+  R.f2c = s.f2c;
+  R.cw = s.cw;
+  R.lam = s.lam;
+  R.mF = s.mF;
+  R.ut = s.ut;
+  R.vt = s.vt;
+  R.at = s.at;
+  R.hdt = s.prm.hdtF;
+  R.uF = s.uF;
+  R.vF = s.vF;
+  R.aF = s.aF;
+  return R;
+}
+
 void fe_free_step(Solver &s) {
   hipStream_t st = s.stream;
-  int64_t nfe = s.nfe;
-  const double dt = s.prm.dtF, hdt2 = s.prm.hdt2F, vbc = s.p.vel_bc;
-  if (s.dim == 2)
-    k_fe_elem_force<2, true><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.vF, s.aF, s.bc, dt, hdt2,
-                                                       vbc, s.p.thickness, static_cast<const FeTables *>(s.fe_tab),
-                                                       s.fe_buf);
-  else
-    k_fe_elem_force<3, true><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, s.vF, s.aF, s.bc, dt, hdt2,
-                                                       vbc, s.p.thickness, static_cast<const FeTables *>(s.fe_tab),
-                                                       s.fe_buf);
+  const FeElemArgs E = fe_elem_args(s, true);
+  if (s.dim == 2) k_fe_elem_force<2, true><<<nb(s.ne), 256, 0, st>>>(E);
+  else k_fe_elem_force<3, true><<<nb(s.ne), 256, 0, st>>>(E);
   MTS_LAUNCH_CHECK();
-  k_fe_gather_free<<<nb(nfe), 256, 0, st>>>(nfe, s.dim, s.nen, s.n2e_ptr, s.n2e, s.eact, s.nact, s.bc, s.fe_buf,
-                                            s.PF, s.mF, s.vF, s.aF, dt, hdt2, s.prm.hdtF, vbc, s.at, s.vt,
-                                            s.f2c_ptr, s.ut, s.uF);
+  k_fe_gather_free<<<nb(s.nfe), 256, 0, st>>>(fe_gather_args(s));
   MTS_LAUNCH_CHECK();
 }
 
@@ -481,22 +400,15 @@ void fe_free_step(Solver &s) {
 // (inspection: energies).  fe_buf is free between macro steps.
 void fe_elem_forces_current(Solver &s) {
   hipStream_t st = s.stream;
-  if (s.dim == 2)
-    k_fe_elem_force<2, false><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, nullptr, nullptr, nullptr,
-                                                        0.0, 0.0, 0.0, s.p.thickness,
-                                                        static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
-  else
-    k_fe_elem_force<3, false><<<nb(s.ne), 256, 0, st>>>(s.ne, s.conn, s.eact, s.gpa, s.uF, nullptr, nullptr, nullptr,
-                                                        0.0, 0.0, 0.0, s.p.thickness,
-                                                        static_cast<const FeTables *>(s.fe_tab), s.fe_buf);
+  const FeElemArgs E = fe_elem_args(s, false);
+  if (s.dim == 2) k_fe_elem_force<2, false><<<nb(s.ne), 256, 0, st>>>(E);
+  else k_fe_elem_force<3, false><<<nb(s.ne), 256, 0, st>>>(E);
   MTS_LAUNCH_CHECK();
 }
 
 void fe_correct(Solver &s) {
   if (!s.n_ring) return;
-  k_fe_correct_ring<<<(unsigned)((s.n_ring * WAVE + 255) / 256), 256, 0, s.stream>>>(
-      s.n_ring, s.fe_ring, s.dim, s.nen, s.bc, s.f2c_ptr, s.f2c, s.cw, s.lam, s.mF, s.ut, s.vt, s.at, s.prm.hdtF,
-      s.uF, s.vF, s.aF);
+  k_fe_correct_ring<<<(unsigned)((s.n_ring * WAVE + 255) / 256), 256, 0, s.stream>>>(fe_ring_args(s));
   MTS_LAUNCH_CHECK();
 }
 

@@ -254,6 +254,7 @@ struct Solver {
 
   // profiling
   bool profiling = false;
+  bool fe_free_done = false;  // the coming macro step's FE free step is already enqueued
   hipEvent_t ev_start[MTS_KT_COUNT]{}, ev_stop[MTS_KT_COUNT]{};
   struct EvPair {
     hipEvent_t e0, e1;
@@ -295,9 +296,13 @@ void fe_correct(Solver &s);
 // coupling (coupling.hip)
 void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);
-void coupling_solve_and_correct(Solver &s);
-void coupling_lambda(Solver &s);  // lambda_m and the FE correction
-void coupling_link(Solver &s);    // the PD correction (link re-run)
+// fuse_next_fe: the next macro step's FE free step rides in the link
+// launches (its kernels are independent of them); returns whether it did
+bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe = false);
+void coupling_lambda(Solver &s);                          // lambda_m
+bool coupling_link(Solver &s, bool fuse_next_fe = false);  // FE and PD corrections (link re-run)
+// independent FE passes run by extra workgroups of a link launch
+enum { kSideNone = 0, kSideRing = 1, kSideElem = 2, kSideGather = 3 };
 // dense linear algebra (dense.hip)
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);

@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "device_math.h"
+#include "fe_device.h"
 
 namespace mts {
 
@@ -577,7 +578,26 @@ struct Link1Args {
   // staged form: workgroup b runs slices wg_start[b] .. wg_start[b + 1] - 1
   // and first copies the records halo_ids[halo_off[b] ..] into LDS
   const int32_t *wg_start, *halo_off, *halo_ids;
+  // workgroups past n_link_blocks run an independent FE pass (side): the FE
+  // ring correction, or the next macro step's element forces or gather
+  int64_t n_link_blocks;
+  int side;
+  FeRingArgs ring;
+  FeElemArgs elem;
+  FeGatherArgs gather;
 };
+
+// (the Hex8 element pass would raise the 3D link kernel's register count, so
+// the next FE free step joins the link launches in 2D only)
+template <int DIM>
+__device__ __forceinline__ void link_side_pass(const Link1Args &A, int64_t bb) {
+  const int64_t g = bb * kBlock + threadIdx.x;
+  if (A.side == kSideRing) fe_correct_ring_wave(A.ring, g / WAVE, (int)(threadIdx.x & (WAVE - 1)));
+  if constexpr (DIM == 2) {
+    if (A.side == kSideElem) fe_elem_force_one<DIM, true>(A.elem, g);
+    else if (A.side == kSideGather) fe_gather_free_one(A.gather, g);
+  }
+}
 
 template <int DIM, int L, bool HALO>
 __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
@@ -585,9 +605,14 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
   constexpr uint32_t RB = 16u * DIM;
   static_assert(kSpareIters >= 2 * TM - 1, "spare iterations must cover the look-ahead chunk");
   extern __shared__ double2 lds[];
+  if ((int64_t)blockIdx.x >= A.n_link_blocks) {  // uniform per workgroup
+    link_side_pass<DIM>(A, (int64_t)blockIdx.x - A.n_link_blocks);
+    return;
+  }
+  const int nlb = (int)A.n_link_blocks;
   int64_t slice;
   if constexpr (HALO) {
-    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int b = xcd_block(blockIdx.x, nlb);
     if (!A.first) {  // the first substep has no bond loop: nothing to stage (uniform per launch)
       const int h0 = A.halo_off[b], nh = A.halo_off[b + 1] - h0;
       const double2 *src = reinterpret_cast<const double2 *>(A.w_in);
@@ -602,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_link_final(Link1Args A, Params P) {
     if (w >= A.wg_start[b + 1] - s0) return;  // after the barrier every wave of the group has staged
     slice = s0 + w;
   } else {
-    slice = __builtin_amdgcn_readfirstlane((int)(xcd_block(blockIdx.x, gridDim.x) * (kBlock / WAVE) + (threadIdx.x >> 6)));
+    slice = __builtin_amdgcn_readfirstlane((int)(xcd_block(blockIdx.x, nlb) * (kBlock / WAVE) + (threadIdx.x >> 6)));
     if (slice >= A.n_slices) return;
   }
   const int lane = threadIdx.x & (WAVE - 1);
@@ -996,7 +1021,7 @@ void link_records_init(Solver &s) {
 // Substep j of the final update's response with multipliers s.lam: reads
 // records Wxu[k], writes Wxu[k ^ 1]; the last substep (add) adds W_m into the
 // PD state.
-void link_final_substep(Solver &s, int j, int k, bool add) {
+void link_final_substep(Solver &s, int j, int k, bool add, int side) {
   if (!s.rsell.n_rows) return;
   Link1Args A{};
   A.N = s.N;
@@ -1034,6 +1059,20 @@ void link_final_substep(Solver &s, int j, int k, bool add) {
     grid = (unsigned)s.rsell.n_wg;
     shm = (size_t)s.rsell.halo_max * 16 * s.dim;
   }
+  A.n_link_blocks = grid;
+  A.side = side;
+  int64_t side_threads = 0;
+  if (side == kSideRing) {
+    A.ring = fe_ring_args(s);
+    side_threads = s.n_ring * WAVE;
+  } else if (side == kSideElem) {
+    A.elem = fe_elem_args(s, true);
+    side_threads = s.ne;
+  } else if (side == kSideGather) {
+    A.gather = fe_gather_args(s);
+    side_threads = s.nfe;
+  }
+  grid += (unsigned)((side_threads + kBlock - 1) / kBlock);
 #define MTS_LF(D, LL)                                                                        \
   do {                                                                                       \
     if (halo) k_link_final<D, LL, true><<<grid, kBlock, shm, s.stream>>>(A, s.prm);          \

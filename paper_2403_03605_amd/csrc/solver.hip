@@ -387,12 +387,13 @@ void advance_impl(Solver &s, int64_t n) {
   const bool coupled = s.p.mode == MTS_COUPLED;
   const bool track = coupled && s.m >= 2;
   for (int64_t k = 0; k < n; k++) {
-    if (coupled) {
+    if (coupled && !s.fe_free_done) {
       hipEvent_t e0 = nullptr;
       s.prof_begin(MTS_KT_FE, &e0);
       fe_free_step(s);
       s.prof_end(MTS_KT_FE, e0);
     }
+    s.fe_free_done = false;
     {
       // the m substep launches run back to back; one event pair brackets them
       hipEvent_t e0 = nullptr;
@@ -407,7 +408,10 @@ void advance_impl(Solver &s, int64_t n) {
       MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
     }
     resolve_pending(s);  // previous macro step's check
-    if (coupled) coupling_solve_and_correct(s);
+    // the next macro step's FE free step joins this one's link launches when
+    // another macro step of this call follows (the state between calls stays
+    // that of a whole macro step) and no per-phase timing is taken
+    if (coupled) s.fe_free_done = coupling_solve_and_correct(s, k + 1 < n && !s.profiling);
     if (track) {
       s.pending = true;
       s.pending_slot = slot;
