@@ -161,34 +161,34 @@ def block3d(nx: int, ny: int, nz: int, m: int, n_pd_steps: int, dt_pd: float, *,
 # explicit-FE bound divided by m, and below the Gershgorin FE bound / m.  The
 # bounds scale with dx for these layouts; the test suite re-derives them.
 DT = {
-    "C1": 1.0e-7,
-    "C2": 6.0e-9,
-    "C3": 2.4e-9,
-    "C4": 2.5e-8,
+    "plate50": 1.0e-7,
+    "plate400": 6.0e-9,
+    "plate1000": 2.4e-9,
+    "block100": 2.5e-8,
 }
 
 
 def config(k: int, **over) -> Dict:
     """The five workloads: 0 small 2D, 1 plain FP64 2D, 2 mixed 2D, 3 mixed 3D."""
     if k == 0:
-        kw = dict(nx=50, m=4, n_pd_steps=200, dt_pd=DT["C1"], perturb=0.0, seed=SEED_BASE,
-                  precision="fp64", name="C1 plate 50x20 m=4 fp64")
+        kw = dict(nx=50, m=4, n_pd_steps=200, dt_pd=DT["plate50"], perturb=0.0, seed=SEED_BASE,
+                  precision="fp64", name="plate 50x20 m=4 fp64")
         kw.update(over)
         return plate2d(**kw)
     if k == 1:
-        kw = dict(nx=400, m=10, n_pd_steps=4000, dt_pd=DT["C2"], perturb=1e-6,
-                  seed=SEED_BASE + 1, precision="fp64", name="C2 plate 400x160 m=10 fp64")
+        kw = dict(nx=400, m=10, n_pd_steps=4000, dt_pd=DT["plate400"], perturb=1e-6,
+                  seed=SEED_BASE + 1, precision="fp64", name="plate 400x160 m=10 fp64")
         kw.update(over)
         return plate2d(**kw)
     if k == 2:
-        kw = dict(nx=1000, m=10, n_pd_steps=5000, dt_pd=DT["C3"], perturb=1e-6,
-                  seed=SEED_BASE + 2, precision="mixed", name="C3 plate 1000x400 m=10 mixed")
+        kw = dict(nx=1000, m=10, n_pd_steps=5000, dt_pd=DT["plate1000"], perturb=1e-6,
+                  seed=SEED_BASE + 2, precision="mixed", name="plate 1000x400 m=10 mixed")
         kw.update(over)
         return plate2d(**kw)
     if k == 3:
-        kw = dict(nx=100, ny=100, nz=20, m=8, n_pd_steps=2000, dt_pd=DT["C4"], perturb=1e-6,
+        kw = dict(nx=100, ny=100, nz=20, m=8, n_pd_steps=2000, dt_pd=DT["block100"], perturb=1e-6,
                   seed=SEED_BASE + 3, precision="mixed", material="steel",
-                  name="C4 block 100x100x20 m=8 mixed")
+                  name="block 100x100x20 m=8 mixed")
         kw.update(over)
         return block3d(**kw)
     raise ValueError(k)

@@ -643,14 +643,14 @@ def test_config_time_steps_stable():
         c = mi.config(k) if k == 0 else None
         dx = 0.05 / (50, 400, 1000)[k]
         m = (4, 10, 10)[k]
-        dt = mi.DT[("C1", "C2", "C3")[k]]
+        dt = mi.DT[("plate50", "plate400", "plate1000")[k]]
         assert dt <= 0.8 * b2[0] * dx
         assert dt <= 0.8 * b2[1] * dx / m
         assert dt <= b2[2] * dx / m
     p3 = mi.block3d(20, 20, 6, 8, 16, 1e-9)
     o3 = Oracle(p3)
     b3 = [o3.dt_bound(k) / p3["dx"] for k in range(3)]
-    dx, m, dt = 1e-3, 8, mi.DT["C4"]
+    dx, m, dt = 1e-3, 8, mi.DT["block100"]
     assert dt <= 0.8 * b3[0] * dx * 0.97      # PD bound shrinks slightly with block size
     assert dt <= 0.8 * b3[1] * dx / m
     assert dt <= b3[2] * dx / m
