@@ -85,3 +85,25 @@ def test_2d_variants_bit_identical(mts, precision):
     print("  variant lanes 4, staged vs direct", flush=True)
     got, _ = _run(mts, inst, 50, {"MTS_LANES": "4", "MTS_HALO": "0"})
     _same(ref4, got)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fe_passes_in_link_launches_bit_identical(mts, dim):
+    """Within one mts_advance call the next macro step's FE free step runs as
+    extra workgroups of the link launches (2D); one macro step per call runs it
+    on its own launches.  Both orders compute the same values."""
+    if dim == 2:
+        inst = dict(mi.config(0), name="plate50 fp64")
+    else:
+        inst = mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=43, name="block12 fp64")
+    print("case", inst["name"], flush=True)
+    n = 12
+    a = mts.Solver(inst)
+    a.advance(n)
+    b = mts.Solver(inst)
+    for _ in range(n):
+        b.advance(1)
+    for q in (mts.PD_U, mts.PD_V, mts.FE_U, mts.FE_V, mts.FE_A, mts.LAMBDA, mts.DAMAGE):
+        assert np.array_equal(a.read(q), b.read(q)), q
+    a.close()
+    b.close()
