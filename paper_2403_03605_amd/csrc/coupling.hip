@@ -21,7 +21,7 @@ namespace mts {
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
                   const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
 void link_records_init(Solver &s);
-void link_final_substep(Solver &s, int j, int k, bool add, int side);
+void link_final_substep(Solver &s, int j, int k, bool add, int side, int snap_slot);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
 
 namespace {
@@ -466,9 +466,9 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   vlog(s, "coupling: H inverted");
 }
 
-bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe) {
+bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe, int snap_slot) {
   coupling_lambda(s);
-  return coupling_link(s, fuse_next_fe);
+  return coupling_link(s, fuse_next_fe, snap_slot);
 }
 
 void coupling_lambda(Solver &s) {
@@ -481,7 +481,7 @@ void coupling_lambda(Solver &s) {
   s.prof_end(MTS_KT_LAMBDA, e0);
 }
 
-bool coupling_link(Solver &s, bool fuse_next_fe) {
+bool coupling_link(Solver &s, bool fuse_next_fe, int snap_slot) {
   // FE: the ring nodes' final update; PD: U = V + Y lambda_m by re-running the
   // link problem with lambda_m.  Both need only lambda_m, so the FE pass runs as
   // extra workgroups of the first link launch; with fuse_next_fe (2D, m >= 3)
@@ -490,6 +490,7 @@ bool coupling_link(Solver &s, bool fuse_next_fe) {
   // correction leaves).
   if (!s.rsell.n_rows) {
     fe_correct(s);
+    if (snap_slot >= 0) snapshot_masks(s, snap_slot);
     return false;
   }
   const bool fuse = fuse_next_fe && s.m >= 3 && s.dim == 2;
@@ -497,14 +498,20 @@ bool coupling_link(Solver &s, bool fuse_next_fe) {
   s.prof_begin(MTS_KT_LINK, &e1);
   // m substeps from rest; the last one adds W_m into the PD state directly
   int k = 0;
+  bool snapped = snap_slot < 0;
   for (int j = 1; j <= s.m; j++) {
     int side = kSideNone;
     if (j == 1 && s.n_ring) side = kSideRing;
     if (fuse && j == 2) side = kSideElem;
     if (fuse && j == 3) side = kSideGather;
-    link_final_substep(s, j, k, j == s.m, side);
+    if (side == kSideNone && !snapped) {  // the first launch with room saves the bond states
+      side = kSideSnap;
+      snapped = true;
+    }
+    link_final_substep(s, j, k, j == s.m, side, snap_slot);
     k ^= 1;
   }
+  if (!snapped) snapshot_masks(s, snap_slot);
   s.prof_end(MTS_KT_LINK, e1);
   return fuse;
 }

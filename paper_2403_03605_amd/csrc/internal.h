@@ -298,11 +298,13 @@ void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);
 // fuse_next_fe: the next macro step's FE free step rides in the link
 // launches (its kernels are independent of them); returns whether it did
-bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe = false);
-void coupling_lambda(Solver &s);                          // lambda_m
-bool coupling_link(Solver &s, bool fuse_next_fe = false);  // FE and PD corrections (link re-run)
-// independent FE passes run by extra workgroups of a link launch
-enum { kSideNone = 0, kSideRing = 1, kSideElem = 2, kSideGather = 3 };
+// snap_slot >= 0: also save this macro step's bond states into that slot and
+// clear the rebuild flag (after the caller copied it to the host)
+bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe = false, int snap_slot = -1);
+void coupling_lambda(Solver &s);  // lambda_m
+bool coupling_link(Solver &s, bool fuse_next_fe = false, int snap_slot = -1);  // FE and PD corrections
+// independent passes run by extra workgroups of a link launch
+enum { kSideNone = 0, kSideRing = 1, kSideElem = 2, kSideGather = 3, kSideSnap = 4 };
 // dense linear algebra (dense.hip)
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
@@ -314,6 +316,7 @@ void set_error(const char *fmt, ...);
 void check_finite(Solver &s);
 void resolve_pending(Solver &s);
 void snapshot_states(Solver &s, int slot);
+void snapshot_masks(Solver &s, int slot);  // the bond states and the flag clear only
 mts_status read_impl(Solver &s, int32_t what, double *out, int64_t cap, int64_t *n);
 mts_status read_device_impl(Solver &s, int32_t what, double *dev_out, int64_t cap, int64_t *n);
 // energies and broken-bond count of the current state (energy.hip)

@@ -585,6 +585,11 @@ struct Link1Args {
   FeRingArgs ring;
   FeElemArgs elem;
   FeGatherArgs gather;
+  // kSideSnap: copy the free problem's bond states, then clear the rebuild flag
+  const uint64_t *snap_src;
+  uint64_t *snap_dst;
+  int64_t snap_n;
+  int32_t *snap_flag;
 };
 
 // (the Hex8 element pass would raise the 3D link kernel's register count, so
@@ -593,6 +598,10 @@ template <int DIM>
 __device__ __forceinline__ void link_side_pass(const Link1Args &A, int64_t bb) {
   const int64_t g = bb * kBlock + threadIdx.x;
   if (A.side == kSideRing) fe_correct_ring_wave(A.ring, g / WAVE, (int)(threadIdx.x & (WAVE - 1)));
+  if (A.side == kSideSnap) {
+    if (g < A.snap_n) A.snap_dst[g] = A.snap_src[g];
+    if (g == 0) A.snap_flag[0] = 0;
+  }
   if constexpr (DIM == 2) {
     if (A.side == kSideElem) fe_elem_force_one<DIM, true>(A.elem, g);
     else if (A.side == kSideGather) fe_gather_free_one(A.gather, g);
@@ -1021,7 +1030,7 @@ void link_records_init(Solver &s) {
 // Substep j of the final update's response with multipliers s.lam: reads
 // records Wxu[k], writes Wxu[k ^ 1]; the last substep (add) adds W_m into the
 // PD state.
-void link_final_substep(Solver &s, int j, int k, bool add, int side) {
+void link_final_substep(Solver &s, int j, int k, bool add, int side, int snap_slot) {
   if (!s.rsell.n_rows) return;
   Link1Args A{};
   A.N = s.N;
@@ -1071,6 +1080,12 @@ void link_final_substep(Solver &s, int j, int k, bool add, int side) {
   } else if (side == kSideGather) {
     A.gather = fe_gather_args(s);
     side_threads = s.nfe;
+  } else if (side == kSideSnap) {
+    A.snap_src = s.sell.mask;
+    A.snap_dst = s.mask_snap[snap_slot];
+    A.snap_n = s.sell.n_words;
+    A.snap_flag = s.region_flag;
+    side_threads = std::max<int64_t>(s.sell.n_words, 1);
   }
   grid += (unsigned)((side_threads + kBlock - 1) / kBlock);
 #define MTS_LF(D, LL)                                                                        \

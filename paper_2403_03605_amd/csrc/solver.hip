@@ -360,6 +360,10 @@ __global__ void k_snapshot(const uint64_t *mask, uint64_t *snap, int64_t n, int3
 // memset, so the sequence can be recorded into a graph).
 void snapshot_states(Solver &s, int slot) {
   MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  snapshot_masks(s, slot);
+}
+
+void snapshot_masks(Solver &s, int slot) {
   const int64_t n = std::max<int64_t>(s.sell.n_words, 1);
   k_snapshot<<<(unsigned)((n + 255) / 256), 256, 0, s.stream>>>(s.sell.mask, s.mask_snap[slot], s.sell.n_words,
                                                                s.region_flag);
@@ -403,15 +407,18 @@ void advance_impl(Solver &s, int64_t n) {
     }
     int slot = -1;
     if (track) {
+      // the rebuild flag goes to the host now; the bond states are saved (and
+      // the flag cleared) by extra workgroups of a link launch below, before
+      // the next macro step's substeps and any rebuild that reads them
       slot = (int)(s.macro_steps & 1);
-      snapshot_states(s, slot);
+      MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
       MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
     }
     resolve_pending(s);  // previous macro step's check
     // the next macro step's FE free step joins this one's link launches when
     // another macro step of this call follows (the state between calls stays
     // that of a whole macro step) and no per-phase timing is taken
-    if (coupled) s.fe_free_done = coupling_solve_and_correct(s, k + 1 < n && !s.profiling);
+    if (coupled) s.fe_free_done = coupling_solve_and_correct(s, k + 1 < n && !s.profiling, slot);
     if (track) {
       s.pending = true;
       s.pending_slot = slot;
