@@ -654,3 +654,306 @@ def test_config_time_steps_stable():
     assert dt <= 0.8 * b3[0] * dx * 0.97      # PD bound shrinks slightly with block size
     assert dt <= 0.8 * b3[1] * dx / m
     assert dt <= b3[2] * dx / m
+
+
+# ---------------------------------------------------------------------------
+# Bond breaking (Eq. 3 stretch, Eq. 4 irreversible state; reading R6)
+#
+# Two-node lattices whose coordinates are dyadic rationals, so that the
+# stretch of Eq. 3 is exact in FP64 and the threshold can be hit exactly.
+# The predictor leaves u unchanged when v = a = 0, so the one substep tests
+# the displacement that was written.
+# ---------------------------------------------------------------------------
+def _pair(pos, s_crit, dx=0.5, hf=1.6):
+    pos = np.asarray(pos, dtype=np.float64)
+    dim = pos.shape[1]
+    lo = tuple(pos.min(0) - dx)
+    hi = tuple(pos.max(0) + dx)
+    inst = dict(dim=dim, mode="pure_pd", pos=pos, dx=dx, horizon_factor=hf, pd_lo=lo, pd_hi=hi,
+                dom_lo=lo, dom_hi=hi, cracks=[], m=1, dt_pd=1e-9, E=1e9, rho=1000.0, G0=1.0,
+                s_crit=s_crit, thickness=1.0, traction=0.0, breaking=True)
+    return inst, Oracle(inst)
+
+
+def _states(o):
+    rp, col, mu = o.bonds()
+    return {(i, int(col[t])): int(mu[t]) for i in range(len(rp) - 1) for t in range(rp[i], rp[i + 1])}
+
+
+def _step_with(o, u):
+    n = o.info()["n_pd"]
+    o.set(O.PD_U, u)
+    o.set(O.PD_V, np.zeros_like(u))
+    o.set(O.PD_A, np.zeros_like(u))
+    o.advance(1)
+    return _states(o)
+
+
+# (xi, eta, s_crit, breaks): xi = x_1 - x_0, eta = u_1 - u_0 (u_0 = 0).  The
+# exact stretch (|xi + eta| - |xi|) / |xi| of each case is a dyadic rational.
+_BREAK_CASES = [
+    # axis-aligned, |xi| = 0.5: s = 0.5 at the threshold (inclusive), just below, above
+    ("tie", (0.5, 0.0), (0.25, 0.0), 0.5, True),
+    ("just below", (0.5, 0.0), (0.25 - 2.0 ** -44, 0.0), 0.5, False),
+    ("above", (0.5, 0.0), (0.3, 0.0), 0.5, True),
+    # compression with |s| above s_crit never breaks
+    ("compression", (0.5, 0.0), (-0.3, 0.0), 0.5, False),
+    # displacement normal to the bond: |xi + eta| = 0.625, s = 0.25 exactly
+    # (the linearised stretch xi.eta/|xi|^2 would be 0)
+    ("normal tie", (0.5, 0.0), (0.0, 0.375), 0.25, True),
+    ("normal below", (0.5, 0.0), (0.0, 0.375), 0.25 + 2.0 ** -40, False),
+    # oblique bond |xi| = 0.625 stretched by half along itself: s = 0.5
+    ("oblique tie", (0.375, 0.5), (0.1875, 0.25), 0.5, True),
+    # a rotation of the bond by 90 degrees keeps the length: s = 0
+    ("rotation", (0.5, 0.0), (-0.5, 0.5), 1e-6, False),
+    # 3D, out-of-plane displacement: |xi + eta| = 0.625 with |xi| = 0.5
+    ("3d normal tie", (0.5, 0.0, 0.0), (0.0, 0.0, 0.375), 0.25, True),
+    ("3d normal below", (0.5, 0.0, 0.0), (0.0, 0.0, 0.375), 0.25 + 2.0 ** -40, False),
+    # 3D oblique |xi| = 0.75, s = 0.5
+    ("3d oblique tie", (0.25, 0.5, 0.5), (0.125, 0.25, 0.25), 0.5, True),
+]
+
+
+@pytest.mark.parametrize("case", _BREAK_CASES, ids=lambda c: c[0])
+def test_break_decision_two_nodes(case):
+    """Eq. 4 on one bond: broken iff the exact Eq. 3 stretch reaches s_crit
+    (ties break, compression and rigid rotation never do), in both directions of
+    the bond at once, and the broken bond carries no force in the same substep
+    (break first, then force); damage (Eq. 5) of both nodes is then 1."""
+    name, xi, eta, sc, breaks = case
+    dim = len(xi)
+    pos = np.array([[0.0] * dim, list(xi)])
+    inst, o = _pair(pos, sc)
+    assert o.info()["s_crit"] == sc
+    u = np.array([[0.0] * dim, list(eta)])
+    st = _step_with(o, u)
+    assert st == {(0, 1): int(not breaks), (1, 0): int(not breaks)}, name
+    a = o.get(O.PD_A)
+    phi = o.get(O.DAMAGE)
+    if breaks:
+        assert np.all(a == 0.0)
+        assert np.all(phi == 1.0)
+        assert o.info()["n_broken"] == 2
+    else:
+        # Eq. 2 on the intact bond: f_0 = c(|xi|) (xi.eta) xi V V, a = f / (rho V)
+        info = o.info()
+        r = math.sqrt(sum(x * x for x in xi))
+        xe = sum(x * e for x, e in zip(xi, eta))
+        f0 = info["c0"] / r ** 3 * xe * np.array(xi) * info["volume"] ** 2
+        m0 = inst["rho"] * info["volume"]
+        assert np.allclose(a[0], f0 / m0, rtol=1e-13, atol=1e-300)
+        assert np.allclose(a[1], -f0 / m0, rtol=1e-13, atol=1e-300)
+        assert np.all(phi == 0.0)
+
+
+def test_broken_bond_never_heals():
+    """Once broken (Eq. 4 takes the history over all earlier times), a bond stays
+    broken when the nodes return to, or move closer than, the reference distance."""
+    inst, o = _pair([[0.0, 0.0], [0.5, 0.0]], 0.5)
+    assert _step_with(o, np.array([[0.0, 0.0], [0.3, 0.0]])) == {(0, 1): 0, (1, 0): 0}
+    for u1 in ((0.0, 0.0), (-0.2, 0.0), (0.1, 0.0)):
+        st = _step_with(o, np.array([[0.0, 0.0], list(u1)]))
+        assert st == {(0, 1): 0, (1, 0): 0}
+        assert np.all(o.get(O.PD_A) == 0.0)
+    assert o.info()["n_broken"] == 2
+
+
+def test_break_decision_uses_the_substep_displacement():
+    """The test sees the predicted displacement of the substep, u + dt v + dt^2/2 a
+    (Eq. 38), not the displacement at the start of the substep."""
+    inst, o = _pair([[0.0, 0.0], [0.5, 0.0]], 0.5)
+    dt = inst["dt_pd"]
+    o.set(O.PD_U, np.array([[0.0, 0.0], [0.2, 0.0]]))     # s = 0.4 at the start
+    o.set(O.PD_V, np.array([[0.0, 0.0], [0.1 / dt, 0.0]]))  # predicted u_1 = 0.3: s = 0.6
+    o.set(O.PD_A, np.zeros((2, 2)))
+    o.advance(1)
+    assert _states(o) == {(0, 1): 0, (1, 0): 0}
+
+
+# ---------------------------------------------------------------------------
+# Hex8 elements (Eq. 24-27 in 3D; nu = 1/4, so lambda = mu = 0.4 E)
+# Closed forms of the trilinear brick of side h with exact 2x2x2 quadrature:
+#   int (dN_a/dx)^2 dV = h/9,  int dN_a/dx dN_a/dy dV = xi_a eta_a h/12,
+#   int dN_a/dx dN_b/dx dV = -h/9, int dN_a/dy dN_b/dy dV = h/18 for the x-edge a-b.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def coupled_3d():
+    inst = mi.block3d(16, 8, 8, 2, 4, 1e-8, name="hex8 small")
+    return inst, Oracle(inst)
+
+
+def test_hex8_element_stiffness_closed_form(coupled_3d):
+    inst, o = coupled_3d
+    nfe = o.info()["n_fe_nodes"]
+    E, h = inst["E"], inst["fe_h"]
+    lam = mu = 0.4 * E
+    X = o.get(O.FE_X)
+    assert np.all(X[0] == 0.0) and X[1, 0] == pytest.approx(h) and np.all(X[1, 1:] == 0.0)
+    # node 0 (corner (0,0,0)) belongs to element 0 only, which lies outside the
+    # PD block (alpha = 1 at its Gauss points)
+    u = np.zeros((nfe, 3))
+    u[0, 0] = 1.0
+    f = o.fe_force(u)
+    assert f[0, 0] == pytest.approx((lam + 4 * mu) * h / 9, rel=1e-12)      # = 2 E h / 9
+    assert f[0, 1] == pytest.approx((lam + mu) * h / 12, rel=1e-12)         # = E h / 15
+    assert f[0, 2] == pytest.approx((lam + mu) * h / 12, rel=1e-12)
+    u = np.zeros((nfe, 3))
+    u[1, 0] = 1.0                    # node 1 = (h, 0, 0): the x-edge partner of node 0
+    f = o.fe_force(u)
+    assert f[0, 0] == pytest.approx(-(lam + 2 * mu) * h / 9 + 2 * mu * h / 18, rel=1e-12)
+    assert abs(f[0, 1]) <= 1e-12 * E * h                                     # (mu - lam) h / 12 = 0
+    assert abs(f[0, 2]) <= 1e-12 * E * h                                     # (mu - lam) h / 12 = 0
+    # y-y entry of the same pair: mu (-h/9) + (lambda + 2 mu) h/18 + mu h/18
+    u = np.zeros((nfe, 3))
+    u[1, 1] = 1.0
+    f = o.fe_force(u)
+    assert f[0, 1] == pytest.approx((lam + mu) * h / 18, rel=1e-12)
+    # x-z coupling of the pair: lambda int N0,x N1,z + mu int N0,z N1,x = (lambda - mu) h/12
+    u = np.zeros((nfe, 3))
+    u[1, 2] = 1.0
+    f = o.fe_force(u)
+    assert abs(f[0, 0]) <= 1e-12 * E * h
+
+
+def test_hex8_masses(coupled_3d):
+    """Row-sum lumped mass of unweighted elements: rho h^3 at interior nodes,
+    rho h^3 / 8 at the bar's corner (Eq. 34 with alpha = 1, reading R10)."""
+    inst, o = coupled_3d
+    mF = o.get(O.FE_MASS)
+    X = o.get(O.FE_X)
+    h, rho = inst["fe_h"], inst["rho"]
+    assert mF[0] == pytest.approx(rho * h ** 3 / 8, rel=1e-14)
+    lo = np.array(inst["pd_lo"]) - 2 * h
+    inner = (X[:, 0] > h / 2) & (X[:, 0] < lo[0]) & (X[:, 1] > h / 2) & (X[:, 1] < inst["dom_hi"][1] - h / 2) \
+        & (X[:, 2] > h / 2) & (X[:, 2] < inst["dom_hi"][2] - h / 2)
+    assert inner.sum() >= 4
+    assert np.allclose(mF[inner], rho * h ** 3, rtol=1e-14)
+
+
+def test_hex8_patch_rigid_and_face_resultants(coupled_3d):
+    """Uniform strain leaves no force at nodes whose elements are all unweighted;
+    rigid translation and infinitesimal rotation give no force; and the resultant
+    on the face x = 0 equals -sigma . n A for uniaxial strain (lambda + 2 mu),
+    lateral strain (lambda) and shear (mu)."""
+    inst, o = coupled_3d
+    X = o.get(O.FE_X)
+    mF = o.get(O.FE_MASS)
+    act = mF > 0
+    E, h = inst["E"], inst["fe_h"]
+    lam = mu = 0.4 * E
+    Ly, Lz = inst["dom_hi"][1], inst["dom_hi"][2]
+    A = Ly * Lz
+    face = act & (X[:, 0] == 0.0)
+    inner = act & (X[:, 0] > h / 2) & (X[:, 0] < inst["pd_lo"][0] - 2 * h) & (X[:, 1] > h / 2) \
+        & (X[:, 1] < Ly - h / 2) & (X[:, 2] > h / 2) & (X[:, 2] < Lz - h / 2)
+    assert inner.sum() >= 4
+    G = np.array([[2e-4, 1e-4, -3e-5], [5e-5, -1e-4, 2e-5], [-4e-5, 3e-5, 1.5e-4]])
+    u = X @ G.T
+    f = o.fe_force(u)
+    scale = np.abs(f[act]).max()
+    assert np.abs(f[inner]).max() <= 1e-9 * scale
+    W = np.array([[0.0, -1.0, 2.0], [1.0, 0.0, -0.5], [-2.0, 0.5, 0.0]]) * 1e-6
+    ur = X @ W.T + np.array([1e-5, -2e-5, 3e-5])
+    assert np.abs(o.fe_force(ur)).max() <= 1e-8 * scale * 1e-6 / 2e-4
+    e = 1e-4
+    z = np.zeros_like(X[:, 0])
+    f = o.fe_force(np.stack([e * X[:, 0], z, z], 1))
+    assert f[face, 0].sum() == pytest.approx(-(lam + 2 * mu) * e * A, rel=1e-12)
+    f = o.fe_force(np.stack([z, e * X[:, 1], z], 1))
+    assert f[face, 0].sum() == pytest.approx(-lam * e * A, rel=1e-12)
+    f = o.fe_force(np.stack([z, e * X[:, 0], z], 1))
+    assert f[face, 1].sum() == pytest.approx(-mu * e * A, rel=1e-12)
+    f = o.fe_force(np.stack([z, z, e * X[:, 0]], 1))
+    assert f[face, 2].sum() == pytest.approx(-mu * e * A, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Load of the pure-PD comparison model: the edge traction T becomes a body force
+# T / delta per unit volume on the nodes within delta of each loaded face
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pure_pd_load(dim):
+    T = 2.5e6
+    if dim == 2:
+        inst = mi.plate2d(20, 1, 4, 1e-8, mode="pure_pd", traction=T)
+        inst["cracks"] = []
+    else:
+        inst = mi.block3d(8, 10, 6, 1, 4, 1e-8, mode="pure_pd")
+        inst["traction"] = T
+    o = Oracle(inst)
+    info = o.info()
+    dx, delta, V = inst["dx"], info["delta"], info["volume"]
+    nx, ny = inst["pd_n"][0], inst["pd_n"][1]
+    nz = inst["pd_n"][2] if dim == 3 else 1
+    assert V == pytest.approx(dx ** dim * (inst["thickness"] if dim == 2 else 1.0), rel=1e-15)
+    P = o.get(O.PD_P)
+    iy = np.arange(nx * ny * nz) // nx % ny
+    # cell-centred rows j with (j + 1/2) dx < delta: j = 0, 1, 2 at delta = 3.015 dx
+    rows = 3
+    low, high = iy < rows, iy >= ny - rows
+    q = T / delta * V
+    assert np.all(P[low, 1] == -q) and np.all(P[high, 1] == q)
+    assert np.all(P[~(low | high)] == 0.0)
+    assert np.all(P[:, 0] == 0.0) and (dim == 2 or np.all(P[:, 2] == 0.0))
+    # face totals: T times the loaded face area (x thickness in 2D), scaled by
+    # the 3 dx of lattice rows the layer of width delta holds
+    area = nx * dx * (nz * dx if dim == 3 else inst["thickness"])
+    assert P[low, 1].sum() == pytest.approx(-T * area * rows * dx / delta, rel=1e-12)
+    assert P[high, 1].sum() == pytest.approx(T * area * rows * dx / delta, rel=1e-12)
+    # initial accelerations a0 = P / m (reading R15), unweighted masses rho V
+    assert np.allclose(o.get(O.PD_A), P / (inst["rho"] * V), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("weight,vals", [("cubic", (125 / 216, 1 / 8, 1 / 216)),
+                                         ("linear", (5 / 6, 1 / 2, 1 / 6)),
+                                         ("constant", (0.5, 0.5, 0.5))])
+def test_arlequin_weight_values(weight, vals):
+    """alpha at the PD nodes of the overlap band (Sec. 3.2 weight functions,
+    l^O = 3 dx, reading R9): the cell-centred columns 0, 1, 2 lie 2.5, 1.5 and
+    0.5 dx outside the PD-only box; corners take the larger (L-infinity)
+    distance; alpha = 0 inside the box."""
+    inst = mi.plate2d(20, 2, 4, 1e-8, weight=weight, name="weights")
+    o = Oracle(inst, setup_only=True)
+    nx, ny = inst["pd_n"][0], inst["pd_n"][1]
+    al = o.get(O.PD_ALPHA).reshape(ny, nx)
+    mid = ny // 2
+    for c in range(3):
+        assert al[mid, c] == pytest.approx(vals[c], rel=1e-12)
+        assert al[mid, nx - 1 - c] == pytest.approx(vals[c], rel=1e-12)
+        assert al[c, nx // 2] == pytest.approx(vals[c], rel=1e-12)
+        assert al[ny - 1 - c, nx // 2] == pytest.approx(vals[c], rel=1e-12)
+    assert al[0, 2] == pytest.approx(vals[0], rel=1e-12)      # corner: max(2.5, 0.5) dx
+    assert np.all(al[3:ny - 3, 3:nx - 3] == 0.0)
+    mP = o.get(O.PD_MASS).reshape(ny, nx)
+    assert np.allclose(mP, (1 - al) * inst["rho"] * inst["dx"] ** 2 * inst["thickness"], rtol=1e-14)
+
+
+def test_fe_edge_traction_and_slit(coupled_small):
+    """FE load and pre-crack (reading R20): the traction resultant on each loaded
+    edge equals T L h (the edges lie outside the PD strip, alpha = 1); the FE
+    mesh holds one extra copy of every grid node on the crack line with x < a,
+    and an opening displacement of everything above the line moves the two sides
+    of the slit apart without force there."""
+    inst, o = coupled_small
+    X = o.get(O.FE_X)
+    P = o.get(O.FE_P)
+    T, L, t = inst["traction"], inst["dom_hi"][0], inst["thickness"]
+    bot, top = X[:, 1] == 0.0, X[:, 1] == inst["dom_hi"][1]
+    assert P[bot, 1].sum() == pytest.approx(-T * L * t, rel=1e-12)
+    assert P[top, 1].sum() == pytest.approx(T * L * t, rel=1e-12)
+    assert np.all(P[~(bot | top)] == 0.0) and np.all(P[:, 0] == 0.0)
+    fx, fy = inst["fe_n"][0], inst["fe_n"][1]
+    h = inst["fe_h"]
+    yc, a = inst["cracks"][0][0], inst["cracks"][0][2]
+    ngrid = (fx + 1) * (fy + 1)
+    n_slit = int(math.ceil(a / h - 1e-9))         # grid nodes x = i h < a on the line
+    assert o.info()["n_fe_nodes"] == ngrid + n_slit
+    dup = np.arange(len(X)) >= ngrid
+    assert np.allclose(X[dup, 1], yc) and np.all(X[dup, 0] < a)
+    u = np.zeros_like(X)
+    u[(X[:, 1] > yc + h / 2) | dup, 1] = 1e-6
+    f = o.fe_force(u)
+    line = np.abs(X[:, 1] - yc) < h / 2
+    scale = np.abs(f).max()
+    assert np.abs(f[line & (X[:, 0] < a - 1.5 * h)]).max() <= 1e-12 * scale
+    assert np.abs(f[line & (X[:, 0] > a + 0.5 * h)]).max() > 1e-3 * scale
