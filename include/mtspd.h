@@ -193,6 +193,21 @@ mts_status mts_query(mts_solver *s, mts_info *out);
  * fixed order, so repeated calls give identical values. */
 mts_status mts_energy(mts_solver *s, mts_energy_info *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the values
+ * of mts_energy, enqueued on the solver's stream without allocating anything
+ * and without waiting.  dev_out (caller-owned device memory, 5 doubles)
+ * receives kinetic, strain_pd, strain_fe, external_work and n_broken (as a
+ * double), in that order, once the stream reaches the call; the values equal
+ * mts_energy's bit for bit.  The partial sums live in one static device buffer
+ * per GPU of 65,504 doubles (512 KiB, held by every GPU the library runs on
+ * until the process ends), enough for about 5.5 million PD nodes; a larger
+ * solver gets MTS_EINVAL.  Calls on one GPU share that buffer: calls whose
+ * work overlaps on the device (solvers on different streams of one GPU, with
+ * no ordering between them) race, so order them (one stream, or events).
+ * Errors: MTS_EINVAL (NULL argument, solver too large), MTS_EDEVICE. */
+mts_status mts_energy_noalloc(mts_solver *s, double *dev_out);
+
 /* HIP-event timing on the solver's stream while enabled.  MTS_KT_PD_SUBSTEP:
  * one event pair brackets the m back-to-back substep launches of a macro step
  * and *launches counts the substeps; the other groups count one launch group

@@ -72,7 +72,7 @@ class PoolInfo(C.Structure):
 
 
 EXPORTS = ["mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
-           "mts_query", "mts_energy", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
+           "mts_query", "mts_energy", "mts_energy_noalloc", "mts_profile", "mts_kernel_time", "mts_destroy", "mts_status_str", "mts_last_error",
            "mts_pool_create", "mts_pool_submit", "mts_pool_step", "mts_pool_poll", "mts_pool_read",
            "mts_pool_release", "mts_pool_query", "mts_pool_destroy"]
 
@@ -103,6 +103,7 @@ def load():
     lib.mts_read_bonds.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_uint8), C.c_int64, P(C.c_int64)]
     lib.mts_query.argtypes = [C.c_void_p, P(Info)]
     lib.mts_energy.argtypes = [C.c_void_p, P(EnergyInfo)]
+    lib.mts_energy_noalloc.argtypes = [C.c_void_p, C.c_void_p]
     lib.mts_profile.argtypes = [C.c_void_p, C.c_int32]
     lib.mts_kernel_time.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_double)]
     lib.mts_destroy.argtypes = [C.c_void_p]
@@ -121,7 +122,8 @@ def load():
     lib.mts_pool_destroy.argtypes = [C.c_void_p]
     lib.mts_pool_destroy.restype = None
     for f in ("mts_plan", "mts_create", "mts_create_in", "mts_advance", "mts_sync", "mts_read", "mts_read_device", "mts_write", "mts_read_bonds",
-              "mts_query", "mts_energy", "mts_profile", "mts_kernel_time", "mts_pool_create", "mts_pool_submit",
+              "mts_query", "mts_energy", "mts_energy_noalloc", "mts_profile", "mts_kernel_time", "mts_pool_create",
+              "mts_pool_submit",
               "mts_pool_step", "mts_pool_poll", "mts_pool_read", "mts_pool_release", "mts_pool_query"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -238,6 +240,16 @@ class Solver:
         o = EnergyInfo()
         _check(self.lib.mts_energy(self.h, C.byref(o)))
         return {k: getattr(o, k) for k, _ in EnergyInfo._fields_}
+
+    def energy_noalloc(self, out):
+        """mts_energy_noalloc: the five energy values written into `out`, a
+        float64 device tensor of at least 5 elements, on the solver's stream
+        (no allocation, no wait)."""
+        import torch
+        if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or out.numel() < 5:
+            raise ValueError("out must be a contiguous float64 device tensor of >= 5 elements")
+        _check(self.lib.mts_energy_noalloc(self.h, C.c_void_p(out.data_ptr())))
+        return out
 
     def read(self, what: int) -> np.ndarray:
         info = self.query()

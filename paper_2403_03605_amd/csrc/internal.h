@@ -150,6 +150,7 @@ struct Solver {
   int dim = 2;
   int64_t N = 0;
   hipStream_t stream = nullptr;
+  int device = 0;                // HIP device current at create
   DeviceArena arena;
   Params prm{};
   int precision = MTS_FP64;
@@ -322,6 +323,7 @@ mts_status read_device_impl(Solver &s, int32_t what, double *dev_out, int64_t ca
 // energies and broken-bond count of the current state (energy.hip)
 int64_t count_intact(Solver &s);
 void energy_impl(Solver &s, mts_energy_info *out);
+void energy_noalloc_impl(Solver &s, double *dev_out);  // partial sums in a static device buffer
 void query_impl(Solver &s, mts_info *o);
 // progress log on stderr when MTS_VERBOSE is set
 void vlog(const Solver &s, const char *fmt, ...);

@@ -213,6 +213,7 @@ void set_error(const char *fmt, ...) {
 
 void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   validate(pin);
+  MTS_HIP(hipGetDevice(&s->device));
   s->verbose = std::getenv("MTS_VERBOSE") != nullptr;
   if (const char *t = std::getenv("MTS_TILE")) s->tiled = std::atoi(t) != 0 ? 1 : 0;  // tuning: row order
   if (const char *t = std::getenv("MTS_PD_VARIANT")) s->pd_variant = std::atoi(t);  // tuning: loop shape
@@ -600,6 +601,16 @@ mts_status mts_energy(mts_solver *h, mts_energy_info *out) {
   if (!h || !out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
   try {
     energy_impl(h->s, out);
+    return MTS_OK;
+  } catch (...) {
+    return fail_from_exception();
+  }
+}
+
+mts_status mts_energy_noalloc(mts_solver *h, double *dev_out) {
+  if (!h || !dev_out) return (std::snprintf(g_err, sizeof g_err, "null argument"), MTS_EINVAL);
+  try {
+    energy_noalloc_impl(h->s, dev_out);
     return MTS_OK;
   } catch (...) {
     return fail_from_exception();
