@@ -168,9 +168,6 @@ def main():
     if args.serve:
         return serve_main(args, torch, mts, log)
     inst = mi.config(args.config) if args.precision is None else mi.config(args.config, precision=args.precision)
-    if args.precision is not None:  # name the precision the run uses
-        base, _, last = inst["name"].rpartition(" ")
-        inst["name"] = f"{base} {args.precision}" if last in ("fp64", "mixed") else f"{inst['name']} ({args.precision})"
     K = args.steps if args.steps is not None else inst["n_macro"]
     W = args.warmup
     stream = torch.cuda.Stream()

@@ -169,7 +169,17 @@ DT = {
 
 
 def config(k: int, **over) -> Dict:
-    """The five workloads: 0 small 2D, 1 plain FP64 2D, 2 mixed 2D, 3 mixed 3D."""
+    """The five workloads: 0 small 2D, 1 plain FP64 2D, 2 mixed 2D, 3 mixed 3D.
+    An overridden precision is reflected in the name."""
+    inst = _config(k, **over)
+    if "precision" in over and "name" not in over:
+        base, _, last = inst["name"].rpartition(" ")
+        if last in ("fp64", "mixed"):
+            inst["name"] = f"{base} {inst['precision']}"
+    return inst
+
+
+def _config(k: int, **over) -> Dict:
     if k == 0:
         kw = dict(nx=50, m=4, n_pd_steps=200, dt_pd=DT["plate50"], perturb=0.0, seed=SEED_BASE,
                   precision="fp64", name="plate 50x20 m=4 fp64")

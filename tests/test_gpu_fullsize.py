@@ -76,7 +76,7 @@ def _pure(k, precision):
     return inst
 
 
-@pytest.mark.parametrize("k,precision", [(1, "fp64"), (2, "fp64"), (2, "mixed"), (3, "mixed")])
+@pytest.mark.parametrize("k,precision", [(1, "fp64"), (2, "fp64"), (2, "mixed"), (3, "mixed"), (3, "fp64")])
 def test_fullsize_pure_pd_substeps(mts, k, precision):
     """20 substeps of the full lattice: FP64 within 1e-10 (max relative), mixed
     within 1e-4 (relative L2), element by element against the oracle."""

@@ -91,6 +91,8 @@ def _run_pair(mts, inst, n_macro, tol, check_every=1):
             e = _rel(s.read(gq), o.get(oq))
             worst = max(worst, e)
             assert e <= tol, (k, gq, e)
+        # damage (Eq. 5) from the same bond states: identical
+        assert np.array_equal(s.read(mts.DAMAGE), o.get(O.DAMAGE)), k
         if inst["mode"] == "coupled":
             for gq, oq in ((mts.FE_U, O.FE_U), (mts.FE_V, O.FE_V), (mts.LAMBDA, O.LAMBDA)):
                 e = _rel(s.read(gq), o.get(oq))
@@ -110,6 +112,36 @@ def test_coupled_trajectory_before_break(mts):
     inst = mi.config(0)
     s, o, worst = _run_pair(mts, inst, inst["n_macro"], 1e-10)
     print("coupled C1 worst rel diff before first break", worst)
+
+
+def test_coupled_through_rebuilds(mts):
+    """The 50x20 plate past its first breaks: while the bond states agree bit for
+    bit, the unit-load responses are rebuilt on both sides after the same macro
+    steps, and displacement, velocity, multipliers and damage keep agreeing
+    (1e-9 max relative; damage exactly)."""
+    inst = mi.config(0)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    rebuilt_same, worst = 0, 0.0
+    for k in range(inst["n_macro"]):
+        s.advance(1)
+        o.advance(1)
+        same = np.array_equal(s.bonds()[2], o.bonds()[2])
+        if not same:
+            break
+        if o.info()["n_broken"] == 0:
+            continue
+        for gq, oq in ((mts.PD_U, O.PD_U), (mts.PD_V, O.PD_V), (mts.FE_U, O.FE_U), (mts.FE_V, O.FE_V),
+                       (mts.LAMBDA, O.LAMBDA)):
+            e = _rel(s.read(gq), o.get(oq))
+            worst = max(worst, e)
+            assert e <= 1e-9, (k, gq, e)
+        assert np.array_equal(s.read(mts.DAMAGE), o.get(O.DAMAGE)), k
+        s.sync()
+        assert s.query()["n_rebuilds"] == o.info()["n_rebuilds"], k
+        rebuilt_same = o.info()["n_rebuilds"]
+    print("rebuilds with equal bond states", rebuilt_same, "worst", worst, "stopped at", k)
+    assert rebuilt_same >= 1
 
 
 def _tip(pos, phi, thresh=0.35):
@@ -202,7 +234,9 @@ def test_coupled_trajectory_3d(mts):
 
 def test_breaking_states_3d(mts):
     """3D impact with breaking: the bond states after 20 macro steps agree with
-    the oracle's except for a vanishing fraction (decisions at the threshold)."""
+    the oracle's (the FP64 stretch test takes the oracle's decision on equal
+    inputs; at most one decision in a thousand may flip where the trajectories'
+    rounding differences straddle the threshold)."""
     inst = mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=42, name="block12 breaking")
     s = mts.Solver(inst)
     o = Oracle(inst)
@@ -213,7 +247,7 @@ def test_breaking_states_3d(mts):
     nb = o.info()["n_broken"]
     diff = int((mug != muo).sum())
     print("3D broken", nb, "differing", diff)
-    assert nb > 0 and diff <= max(2, nb // 100)
+    assert nb > 0 and diff <= nb // 1000
 
 
 @pytest.mark.parametrize("weight,kernel", [("linear", "pmb"), ("constant", "pmb"), ("cubic", "exp")])
