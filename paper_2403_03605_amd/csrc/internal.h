@@ -178,6 +178,9 @@ struct Solver {
   Sell sell;                     // full lattice, row = node
   double *damage = nullptr;
   int32_t *region_flag = nullptr;  // device flag: a bond in the link region broke
+  int32_t *nonfinite_flag = nullptr;  // device flag (sticky): a non-finite PD velocity at a macro-step end
+  hipEvent_t nf_event = nullptr;   // after the copy of nonfinite_flag to pinned_flag[2] (end of mts_advance)
+  bool nf_recorded = false;
   uint8_t *in_region = nullptr;    // per node
   int32_t *layer = nullptr;        // per node: smallest h <= m-1 within h horizons of a constraint, else m
 
@@ -237,7 +240,7 @@ struct Solver {
   int nrhs = 8;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)
-  int32_t *pinned_flag = nullptr;  // 2 slots, host-pinned
+  int32_t *pinned_flag = nullptr;  // host-pinned: [0], [1] rebuild flag per slot, [2] non-finite flag
   uint64_t *mask_snap[2] = {nullptr, nullptr};  // full-lattice bond states at the end of a macro step
   hipEvent_t flag_event[2] = {nullptr, nullptr};
   bool pending = false;

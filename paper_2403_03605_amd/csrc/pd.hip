@@ -80,6 +80,7 @@ struct SubstepArgs {
   double sfac;
   const uint8_t *in_region;
   int32_t *region_flag;
+  int32_t *nonfinite;   // last substep: set when a new velocity is not finite
   const int32_t *rp;
   double *damage;       // written when non-null
   int breaking;
@@ -356,6 +357,7 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
     const double vn = v_o[d] + P.hdtP * (a_o[d] + an);
     A.a[tix] = an;
     A.v[tix] = vn;
+    if (A.nonfinite && !__builtin_isfinite(vn)) A.nonfinite[0] = 1;
     A.xu_out[(int64_t)i * 2 * DIM + DIM + d] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
   }
   if (A.damage && l == 0) {
@@ -882,6 +884,7 @@ static SubstepArgs substep_args(Solver &s, int j, int cur) {
   A.sfac = 1.0 - (double)j / (double)s.m;
   A.in_region = s.nc ? s.in_region : nullptr;
   A.region_flag = s.region_flag;
+  A.nonfinite = (j == s.m) ? s.nonfinite_flag : nullptr;
   A.rp = s.rp;
   A.damage = (j == s.m) ? s.damage : nullptr;
   A.breaking = s.breaking ? 1 : 0;

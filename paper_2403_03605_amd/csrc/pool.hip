@@ -52,6 +52,7 @@ void destroy_solver(Solver *s) {
   for (hipEvent_t e : s->flag_event)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  if (s->nf_event) (void)hipEventDestroy(s->nf_event);
   if (s->pinned_flag) (void)hipHostFree(s->pinned_flag);
   s->arena.free_all();
   delete s;

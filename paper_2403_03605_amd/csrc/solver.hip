@@ -269,6 +269,9 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   MTS_HIP(hipMemsetAsync(s->damage, 0, sizeof(double) * N, st));
   s->region_flag = ar.alloc<int32_t>(1);
   MTS_HIP(hipMemsetAsync(s->region_flag, 0, sizeof(int32_t), st));
+  s->nonfinite_flag = ar.alloc<int32_t>(1);
+  MTS_HIP(hipMemsetAsync(s->nonfinite_flag, 0, sizeof(int32_t), st));
+  MTS_HIP(hipEventCreateWithFlags(&s->nf_event, hipEventDisableTiming));
   build_neighbors(*s);
   vlog(*s, "neighbours: %lld nodes, %lld bonds, %d lanes per row", (long long)N, (long long)s->nnz, s->sell.L);
   pd_setup(*s);
@@ -278,8 +281,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
     coupling_setup(*s);
   }
   pd_predict_all(*s);
-  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
-  s->pinned_flag[0] = s->pinned_flag[1] = 0;
+  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 3 * sizeof(int32_t), hipHostMallocDefault));
+  s->pinned_flag[0] = s->pinned_flag[1] = s->pinned_flag[2] = 0;
   pd_damage(*s);
   s->n_intact0 = count_intact(*s);
   MTS_HIP(hipStreamSynchronize(st));
@@ -381,6 +384,10 @@ void resolve_pending(Solver &s) {
   const int slot = s.pending_slot;
   MTS_HIP(hipEventSynchronize(s.flag_event[slot]));
   s.pending = false;
+  if (s.pinned_flag[2]) {  // a velocity of that macro step was not finite: stop here
+    s.unstable = true;
+    return;
+  }
   if (s.pinned_flag[slot]) {
     s.pinned_flag[slot] = 0;
     coupling_rebuild(s, s.mask_snap[slot]);
@@ -388,10 +395,21 @@ void resolve_pending(Solver &s) {
   }
 }
 
+// The non-finite flag of the last macro step of an earlier mts_advance call,
+// when its copy to the host has completed (no wait).
+void poll_nonfinite(Solver &s) {
+  if (!s.nf_recorded) return;
+  const hipError_t q = hipEventQuery(s.nf_event);
+  if (q == hipErrorNotReady) return;
+  MTS_HIP(q);
+  if (s.pinned_flag[2]) s.unstable = true;
+}
+
 void advance_impl(Solver &s, int64_t n) {
   const bool coupled = s.p.mode == MTS_COUPLED;
   const bool track = coupled && s.m >= 2;
-  for (int64_t k = 0; k < n; k++) {
+  poll_nonfinite(s);
+  for (int64_t k = 0; k < n && !s.unstable; k++) {
     if (coupled && !s.fe_free_done) {
       hipEvent_t e0 = nullptr;
       s.prof_begin(MTS_KT_FE, &e0);
@@ -413,9 +431,11 @@ void advance_impl(Solver &s, int64_t n) {
       // the next macro step's substeps and any rebuild that reads them
       slot = (int)(s.macro_steps & 1);
       MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+      MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
       MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
     }
     resolve_pending(s);  // previous macro step's check
+    if (s.unstable) break;
     // the next macro step's FE free step joins this one's link launches when
     // another macro step of this call follows (the state between calls stays
     // that of a whole macro step) and no per-phase timing is taken
@@ -425,6 +445,11 @@ void advance_impl(Solver &s, int64_t n) {
       s.pending_slot = slot;
     }
     s.macro_steps++;
+  }
+  if (!s.unstable && n > 0) {
+    MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+    MTS_HIP(hipEventRecord(s.nf_event, s.stream));
+    s.nf_recorded = true;
   }
 }
 
@@ -557,6 +582,7 @@ mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_by
       (void)hipStreamSynchronize(h->s.stream);
       (void)hipGetLastError();
       if (h->s.pinned_flag) (void)hipHostFree(h->s.pinned_flag);
+      if (h->s.nf_event) (void)hipEventDestroy(h->s.nf_event);
       h->s.arena.free_all();
       delete h;
     }
@@ -570,6 +596,11 @@ mts_status mts_advance(mts_solver *h, int64_t n) {
   if (h->s.unstable) return (std::snprintf(g_err, sizeof g_err, "solver is unstable"), MTS_EUNSTABLE);
   try {
     advance_impl(h->s, n);
+    if (h->s.unstable) {
+      std::snprintf(g_err, sizeof g_err, "non-finite PD velocity at the end of a macro step (%lld macro steps enqueued)",
+                    (long long)h->s.macro_steps);
+      return MTS_EUNSTABLE;
+    }
     return MTS_OK;
   } catch (...) {
     return fail_from_exception();
@@ -581,6 +612,7 @@ mts_status mts_sync(mts_solver *h) {
   try {
     resolve_pending(h->s);
     MTS_HIP(hipStreamSynchronize(h->s.stream));
+    if (h->s.pinned_flag[2]) h->s.unstable = true;
     check_finite(h->s);
     if (h->s.unstable) {
       std::snprintf(g_err, sizeof g_err, "non-finite PD velocity");
@@ -864,6 +896,7 @@ void mts_destroy(mts_solver *h) {
   for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : s.flag_event)
     if (e) (void)hipEventDestroy(e);
+  if (s.nf_event) (void)hipEventDestroy(s.nf_event);
   if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
   s.arena.free_all();
   delete h;

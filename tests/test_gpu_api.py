@@ -133,3 +133,45 @@ def test_step_above_pd_stability_bound_rejected(mts):
     with pytest.raises(mts.MtsError) as e:
         mts.Solver(dict(inst, dt_pd=1.01 * bound))
     assert e.value.status == _lib.EINVAL
+
+
+def test_nonfinite_state_detected_at_macro_step_end(mts):
+    """A non-finite PD velocity (written from the host; no device fault is
+    involved) is flagged by the last substep of the macro step that sees it and
+    surfaces as MTS_EUNSTABLE: within the same mts_advance call when the
+    rebuild check runs (coupled, m >= 2), at the next call otherwise, and at
+    mts_sync in every mode.  The state stays unstable."""
+    import torch
+    inst = mi.config(0)
+    s = mts.Solver(inst)
+    s.advance(2)
+    s.sync()
+    v = s.read(mts.PD_V)
+    v[17, 1] = np.nan
+    s.write(mts.PD_V, v)
+    before = s.query()["macro_steps"]
+    with pytest.raises(mts.MtsError) as e:
+        s.advance(8)
+    assert e.value.status == 4  # MTS_EUNSTABLE
+    assert s.query()["macro_steps"] - before < 8   # stopped before the end of the call
+    with pytest.raises(mts.MtsError) as e:
+        s.advance(1)
+    assert e.value.status == 4
+    with pytest.raises(mts.MtsError) as e:
+        s.sync()
+    assert e.value.status == 4
+    s.close()
+
+    pure = mi.plate2d(30, 1, 40, 1e-7, perturb=1e-6, seed=62, mode="pure_pd", traction=5e6, name="pure30")
+    s = mts.Solver(pure)
+    s.advance(3)
+    s.sync()
+    v = s.read(mts.PD_V)
+    v[5, 0] = np.inf
+    s.write(mts.PD_V, v)
+    s.advance(2)                 # enqueued; the flag comes back with the call's last step
+    torch.cuda.synchronize()
+    with pytest.raises(mts.MtsError) as e:
+        s.advance(1)             # surfaces here, without a sync
+    assert e.value.status == 4
+    s.close()
