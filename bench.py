@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the MTS PD/FE solver on one MI355X.
 
-A step is one macro step of Algorithm 1 (one FE step at dt_FE, m fused PD
+A step is one macro step of Algorithm 1: one FE step at dt_FE, m fused PD
 substeps at dt_PD, the multiplier solve of Eq. 49 and the final update of
 Eq. 50, plus a rebuild of the unit-load responses when bonds inside their
-support break).  The default workload is the 400 x 160 FP64 plate with m = 10
-and 4000 PD steps (400 macro steps).  `value` counts directed bond slots
-evaluated per PD substep (the free problem) per second over the timed macro
-steps; setup (neighbour build, unit-load responses) is timed separately.
+support break.  The default workload is the 1000 x 400 plate (400,000 PD nodes,
+11.1 M bonds, m = 10, 5000 PD steps = 500 macro steps) in FP64: `value` is its
+rate in PD bond-updates/s, i.e. directed bond slots evaluated per PD substep of
+the free problem, per second, over the timed macro steps (inputs resident,
+setup timed separately).  The same JSON line carries:
+- the mixed form (FP32 bond arithmetic, FP64 integration and coupling) on the
+  identical seeded instance: its rate, the speed-up over FP64, and its error
+  against the FP64 run (displacement relative L2 up to the FP64 run's first
+  break, crack-tip distance after);
+- the served latency p50/p99 and aggregate rate of the seeded request stream
+  (256 plate solves, Poisson arrivals at 20 per second);
+- the bond pass's roofline (HBM bound) on two byte models and the counter
+  traffic;
+- the oracle's rate on the host's cores (one thread and all threads).
 
 Prints one JSON line.
 """
@@ -16,6 +26,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,9 +37,22 @@ METRIC = "PD bond-updates/s (FP64 vs mixed) at stated error; served p50/p99 late
 HBM_PEAK = 8.0e12
 
 
-def bytes_per_launch(info, inst):
-    """Algorithmic HBM bytes of one fused PD substep launch (layout of this build):
-    per bond slot: the slot record the library reports (FP64: coefficient 8 B +
+def reference_bytes(info, inst):
+    """Algorithmic HBM bytes of one bond-pass launch in the reference layout of
+    the method's data (neighbour index 4 B, stored reference bond vector xi of
+    d FP64 values (FP32 in the mixed form), one state bit per bond; per node the
+    row pointer 4 B, u, v, a read and written (48 d B), 1/m and alpha 16 B and
+    the damage 8/m B), every neighbour's displacement counted once."""
+    dim = info["dim"]
+    xi = (4 if info["precision"] == 1 else 8) * dim
+    per_bond = 4 + xi + 1.0 / 8.0
+    per_node = 4 + 48.0 * dim + 16 + 8.0 / inst["m"]
+    return info["nnz"] * per_bond + info["n_pd"] * per_node, per_bond, per_node
+
+
+def layout_bytes(info, inst):
+    """Algorithmic HBM bytes of one bond-pass launch in this build's layout:
+    per bond slot the slot record the library reports (FP64: coefficient 8 B +
     neighbour offset 4 B; mixed: 4 + 4 B, or 6 B when the neighbour records are
     staged in LDS and two slots share a 12-byte record) + bond-state bit 1/8 B;
     per node: position (8 dim), u read (8 dim), v and a read+write (32 dim),
@@ -68,56 +92,220 @@ def traffic_per_launch(inst):
     return w["bytes_per_launch"]
 
 
-def cpu_baseline(inst, seconds=15.0):
-    """The oracle as it stands, single thread, on the same seeded lattice in
-    pure-PD mode (the PD substep path: bond pass with breaking + Verlet)."""
-    import mts_inputs as mi
+def host_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inst, seconds=8.0):
+    """The oracle as it stands on the same seeded lattice in pure-PD mode (the
+    PD substep path: bond pass with breaking + Verlet), timed on one thread and
+    on all host threads (its OpenMP build: per-node loops, identical results)."""
     from oracle import Oracle
     sample = dict(inst)
     sample.update(mode="pure_pd", dom_lo=inst["pd_lo"], dom_hi=inst["pd_hi"], fe_n=(0, 0, 0), m=1)
-    o = Oracle(sample)
-    nnz = o.info()["nnz"]
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        o.advance(5)
-        n += 5
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    o.close()
-    return {"value": n * nnz / dt, "unit": "bond-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} PD substeps of the same {inst['pd_n'][0]}x{inst['pd_n'][1]} seeded lattice, "
-                      f"pure-PD mode (bond pass with breaking + Verlet), plain C FP64, 1 thread, {dt:.1f} s"}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or host_threads()
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    out = {}
+    for omp in (False, True):
+        o = Oracle(sample, openmp=omp)
+        nnz = o.info()["nnz"]
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            o.advance(1)
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+        o.close()
+        out[omp] = (n * nnz / dt, n, dt)
+    v1, n1, t1 = out[False]
+    vn, nn, tn = out[True]
+    return {"value": vn, "unit": "bond-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nn} PD substeps of the same {inst['pd_n'][0]}x{inst['pd_n'][1]} seeded lattice, pure-PD "
+                      f"mode (bond pass with breaking + Verlet), plain C FP64, OpenMP over nodes on {threads} "
+                      f"threads, {tn:.1f} s; one thread: {n1} substeps in {t1:.1f} s",
+            "single_thread_value": v1, "cpu_model": cpu_model(), "host_threads": host_threads()}
 
 
-def serve_main(args, torch, mts, log):
-    """Serving form: the seeded stream of plate solves (sizes 100x40 .. 800x320,
-    m in {4, 8, 10}, mixed precision) with Poisson arrivals at 20 per second,
-    admitted by device-memory budget and advanced together in the pool."""
+def serve_run(args, torch, log):
+    """The seeded stream of plate solves (sizes 100x40 .. 800x320, m in
+    {4, 8, 10}, mixed precision) with Poisson arrivals, admitted by device-memory
+    budget and advanced together in the pool."""
     from paper_2403_03605_amd.serving import serve, stream_requests
     reqs = stream_requests(args.serve_requests, rate=args.serve_rate)
     free, _total = torch.cuda.mem_get_info()
     budget = int(args.serve_budget_gib * (1 << 30)) if args.serve_budget_gib > 0 else int(0.9 * free)
-    log(f"serving {len(reqs)} requests, budget {budget / 2**30:.1f} GiB")
+    log(f"serving {len(reqs)} requests at {args.serve_rate:g}/s, budget {budget / 2**30:.1f} GiB")
     out = serve(reqs, budget, max_slots=64, use_graphs=not args.serve_no_graphs,
-                log=lambda m: log(m), builders=args.serve_builders)
+                log=(lambda m: log(m)) if args.serve_verbose else None, builders=args.serve_builders)
     sizes = {}
     for r in reqs:
-        sizes[f"{r['nx']}x{r['ny']}"] = sizes.get(f"{r['nx']}x{r['ny']}", 0) + 1
+        key = f"{r['nx']}x{r['ny']}"
+        sizes[key] = sizes.get(key, 0) + 1
+    out = {k: v for k, v in out.items() if k != "latencies_s"}
+    out.update(rate_per_s=args.serve_rate, budget_bytes=budget, graphs=not args.serve_no_graphs,
+               builders=args.serve_builders,
+               stream="plate solves 100x40..800x320 (nx uniform over 100..800 step 20), m in {4, 8, 10}, "
+                      "notch and height uniform in [0.2, 0.6], traction 0.5..2 MPa, 10 us of physical time each, "
+                      "mixed precision")
+    return out, sizes
+
+
+def serve_main(args, torch, log):
+    out, sizes = serve_run(args, torch, log)
     line = {
         "metric": "served p99 latency (s), with p50 and aggregate PD bond-updates/s",
         "value": out["p99_s"], "unit": "s", "n_gpus": 1, "steps": out["pool_steps"], "warmup": 0,
         "ms_per_step": out["span_s"] * 1e3 / max(out["pool_steps"], 1), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 bond math / f64 integration", "data": "synthetic",
-        "config": {"workload": f"serving stream: {len(reqs)} plate solves, Poisson {args.serve_rate:g}/s, "
-                               "10 us of physical time each",
-                   "budget_bytes": budget, "graphs": not args.serve_no_graphs,
-                   "builders": args.serve_builders},
-        "serving": {k: v for k, v in out.items() if k != "latencies_s"},
-        "request_sizes": sizes,
+        "config": {"workload": f"serving stream: {out['n_requests']} plate solves, Poisson {args.serve_rate:g}/s, "
+                               "10 us of physical time each"},
+        "serving": out, "request_sizes": sizes,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_form(mts, torch, inst, K, W, args, log):
+    """Warm-up on a throwaway solver, then K timed macro steps on a fresh solver
+    (no per-kernel events), then an event-timed pass for the bond pass's
+    roofline and the other phases.  Returns the form's record."""
+    stream = torch.cuda.Stream()
+    sh = stream.cuda_stream
+    log(f"workload {inst['name']}: {K} timed macro steps after {W} warm-up steps")
+    if W > 0:
+        w = mts.Solver(inst, stream=sh)
+        w.advance(W)
+        w.sync()
+        w.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = mts.Solver(inst, stream=sh)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    def timed(n):
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        s.advance(n)
+        ev1.record(stream)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+        return max(wall, gpu_ms / 1e3), wall, gpu_ms
+
+    elapsed, wall, gpu_ms = timed(K)
+    info = s.query()
+    value = K * inst["m"] * info["nnz"] / elapsed
+    log(f"timed: {K} macro steps in {elapsed:.3f} s -> {value:.4g} bond-updates/s")
+    rec = {"value": value, "ms_per_step": elapsed * 1e3 / K, "steps": K, "setup_s": setup_s,
+           "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3, "rebuilds": info["n_rebuilds"], "info": info}
+    if not args.no_profile:
+        Kp = min(K, args.profile_steps)
+        s.profile(True)
+        p_elapsed, _, _ = timed(Kp)
+        n_launch, ms = s.kernel_time(mts.KT_PD_SUBSTEP)
+        avg_s = ms / 1e3 / max(n_launch, 1)
+        b, per_bond, per_node = reference_bytes(info, inst)
+        bl, per_bond_l, per_node_l = layout_bytes(info, inst)
+        traffic = traffic_per_launch(inst)
+        roof = {"bound": "hbm", "achieved": b / avg_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": b / avg_s / HBM_PEAK, "traffic": traffic,
+                "kernel": "k_pd_substep", "launches": n_launch, "avg_launch_us": avg_s * 1e6,
+                "algorithmic_bytes_per_launch": b, "bytes_per_bond": per_bond, "bytes_per_node": per_node,
+                "byte_model": "reference layout: 4 B index + stored xi + state bit per bond; row pointer, "
+                              "u/v/a read and write, 1/m, alpha, damage per node",
+                "layout": {"achieved": bl / avg_s / 1e9, "frac": bl / avg_s / HBM_PEAK,
+                           "algorithmic_bytes_per_launch": bl, "bytes_per_bond": per_bond_l,
+                           "bytes_per_node": per_node_l,
+                           "byte_model": "this build: slot record (coefficient + neighbour offset) + state bit "
+                                         "per bond; node record [x, u], v, a, mass, constraint index per node"},
+                "traffic_GBps": traffic / avg_s / 1e9 if traffic else None,
+                "traffic_frac": traffic / avg_s / HBM_PEAK if traffic else None,
+                "kernel_bond_updates_per_s": info["nnz"] / avg_s,
+                "profiled_macro_steps": Kp,
+                "profiled_pass_bond_updates_per_s": Kp * inst["m"] * info["nnz"] / p_elapsed}
+        other = {}
+        for name, k in (("link", mts.KT_LINK), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA)):
+            n_l, ms_l = s.kernel_time(k)
+            other[name] = {"launch_groups": n_l, "total_ms": ms_l}
+        inv = s.query()["inverse_bytes"]
+        n_l, ms_l = other["lambda"]["launch_groups"], other["lambda"]["total_ms"]
+        other["lambda"]["inverse_bytes"] = inv
+        other["lambda"]["inverse_GBps_over_phase"] = (inv * n_l / (ms_l * 1e-3) / 1e9) if ms_l > 0 else None
+        other["bond_passes"] = {"launch_groups": Kp, "total_ms": ms}
+        roof["phases_per_macro_step_us"] = {k: v["total_ms"] * 1e3 / max(v["launch_groups"], 1)
+                                            for k, v in other.items()}
+        roof["other_phases"] = other
+        rec["roofline"] = roof
+    s.close()
+    return rec
+
+
+def _tip(pos, phi, thresh=0.35):
+    import numpy as np
+    idx = np.where(phi >= thresh)[0]
+    if idx.size == 0:
+        return None
+    return pos[idx[np.argmax(pos[idx, 0])]]
+
+
+def mixed_error(mts, torch, inst64, inst_mx, K, chunk, log):
+    """The mixed form against the FP64 run on the identical seeded instance:
+    displacement relative L2 at checkpoints every `chunk` macro steps up to the
+    FP64 run's first break, crack-tip distance (in dx) after it."""
+    import numpy as np
+    a = mts.Solver(inst64)
+    b = mts.Solver(inst_mx)
+    pos = inst64["pos"]
+    dx = inst64["dx"]
+    worst, last_pre, first_break, tip_worst, tips = 0.0, None, None, 0.0, 0
+    done = 0
+    while done < K:
+        n = min(chunk, K - done)
+        a.advance(n)
+        b.advance(n)
+        done += n
+        broken = a.energy()["n_broken"]
+        if broken == 0:
+            ua, ub = a.read(mts.PD_U), b.read(mts.PD_U)
+            e = float(np.sqrt(((ub - ua) ** 2).sum()) / max(np.sqrt((ua ** 2).sum()), 1e-300))
+            worst = max(worst, e)
+            last_pre = done
+        else:
+            if first_break is None:
+                first_break = done
+            ta, tb = _tip(pos, a.read(mts.DAMAGE)), _tip(pos, b.read(mts.DAMAGE))
+            if ta is not None and tb is not None:
+                tips += 1
+                tip_worst = max(tip_worst, float(np.linalg.norm(ta - tb)) / dx)
+    res = {"u_rel_l2_before_first_break": worst, "last_checkpoint_before_break_macro_step": last_pre,
+           "fp64_first_break_by_macro_step": first_break, "tip_distance_after_break_max_dx": tip_worst,
+           "tip_checkpoints": tips, "checkpoint_every_macro_steps": chunk, "macro_steps": K,
+           "bound": "u rel L2 <= 1e-4 before the first break, tip within 2 dx after",
+           "within_bound": bool(worst <= 1e-4 and tip_worst <= 2.0 + 1e-9)}
+    log(f"mixed vs fp64: rel L2 {worst:.3g} up to macro step {last_pre}, tip <= {tip_worst:.2f} dx over {tips} checks")
+    a.close()
+    b.close()
+    return res
 
 
 def main():
@@ -125,22 +313,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed macro steps (default: the workload's)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=1, help="workload index (0..3)")
+    ap.add_argument("--config", type=int, default=2, help="workload index (1: 400x160 plate, 2: 1000x400 plate, "
+                                                          "3: 100x100x20 block)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default=None,
-                    help="override the workload's precision (same seeded instance)")
+                    help="precision of the headline run (default: fp64 on the plates, mixed on the block)")
+    ap.add_argument("--no-companion", action="store_true",
+                    help="skip the other precision on the same instance (and the error check)")
+    ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="per oracle build (one thread, all threads)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
+    ap.add_argument("--profile-steps", type=int, default=100, help="macro steps of the event-timed pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
-    ap.add_argument("--serve", action="store_true",
-                    help="run the serving stream (Poisson arrivals of plate solves) through the pool instead")
+    ap.add_argument("--serve", action="store_true", help="only run the serving stream (its own JSON line)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0, help="pool budget (0: 90%% of free HBM)")
     ap.add_argument("--serve-no-graphs", action="store_true")
     ap.add_argument("--serve-builders", type=int, default=4, help="threads that build arrived requests")
-    ap.add_argument("--profile-steps", type=int, default=100, help="macro steps of the event-timed pass")
+    ap.add_argument("--serve-verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -166,98 +359,59 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.serve:
-        return serve_main(args, torch, mts, log)
-    inst = mi.config(args.config) if args.precision is None else mi.config(args.config, precision=args.precision)
+        return serve_main(args, torch, log)
+    default_prec = "mixed" if args.config == 3 else "fp64"
+    prec = args.precision or default_prec
+    inst = mi.config(args.config, precision=prec)
+    other = "mixed" if prec == "fp64" else "fp64"
     K = args.steps if args.steps is not None else inst["n_macro"]
     W = args.warmup
-    stream = torch.cuda.Stream()
-    sh = stream.cuda_stream
-    log(f"workload {inst['name']}: {K} timed macro steps after {W} warm-up steps")
 
-    if W > 0:  # warm-up on a throwaway solver of the same workload
-        with torch.cuda.stream(stream):
-            w = mts.Solver(inst, stream=sh)
-            w.advance(W)
-            w.sync()
-            w.close()
+    head = run_form(mts, torch, inst, K, W, args, log)
+    info = head.pop("info")
+    companion = None
+    if not args.no_companion:
+        inst2 = mi.config(args.config, precision=other)
+        c = run_form(mts, torch, inst2, K, W, args, log)
+        c.pop("info")
+        fp64_rec, mx_rec = (head, c) if prec == "fp64" else (c, head)
+        companion = {"precision": other, "workload": inst2["name"], **c,
+                     "mixed_speedup_vs_fp64": mx_rec["value"] / fp64_rec["value"]}
+        if not args.no_error_check:
+            i64 = inst if prec == "fp64" else inst2
+            imx = inst2 if prec == "fp64" else inst
+            try:
+                companion["mixed_error_vs_fp64"] = mixed_error(mts, torch, i64, imx, K, 25, log)
+            except Exception as e:  # reported, not fatal to the line
+                companion["mixed_error_vs_fp64"] = {"error": repr(e)}
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s = mts.Solver(inst, stream=sh)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    info = s.query()
-
-    def timed(n):
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        s.advance(n)
-        ev1.record(stream)
-        s.sync()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gpu_ms = ev0.elapsed_time(ev1)
-        return max(wall, gpu_ms / 1e3), wall, gpu_ms
-
-    # timed region: K macro steps, no per-kernel events
-    elapsed, wall, gpu_ms = timed(K)
-    info = s.query()
-    bond_updates = K * inst["m"] * info["nnz"]
-    value = bond_updates / elapsed
-    log(f"timed: {K} macro steps in {elapsed:.3f} s -> {value:.4g} bond-updates/s")
-
-    roof = None
-    if not args.no_profile:
-        # second timed region on the same solver with HIP events around every
-        # launch group (recorded on the solver's stream)
-        Kp = min(K, args.profile_steps)
-        s.profile(True)
-        p_elapsed, _, _ = timed(Kp)
-        n_launch, ms = s.kernel_time(mts.KT_PD_SUBSTEP)
-        avg_s = ms / 1e3 / max(n_launch, 1)
-        b, per_bond, per_node = bytes_per_launch(info, inst)
-        achieved = b / avg_s
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": traffic_per_launch(inst),
-                "kernel": "k_pd_substep", "launches": n_launch, "avg_launch_us": avg_s * 1e6,
-                "algorithmic_bytes_per_launch": b, "bytes_per_bond": per_bond,
-                "bytes_per_node": per_node,
-                "kernel_bond_updates_per_s": info["nnz"] / avg_s,
-                "profiled_macro_steps": Kp,
-                "profiled_pass_bond_updates_per_s": Kp * inst["m"] * info["nnz"] / p_elapsed}
-        other = {}
-        for name, k in (("link", mts.KT_LINK), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA)):
-            n_l, ms_l = s.kernel_time(k)
-            other[name] = {"launch_groups": n_l, "total_ms": ms_l}
-        # the multiplier solve streams the packed inverse once per macro step:
-        # its bytes over the whole phase's time bound the GEMV's rate from below
-        inv = s.query()["inverse_bytes"]
-        n_l, ms_l = other["lambda"]["launch_groups"], other["lambda"]["total_ms"]
-        other["lambda"]["inverse_bytes"] = inv
-        other["lambda"]["inverse_GBps_over_phase"] = (inv * n_l / (ms_l * 1e-3) / 1e9) if ms_l > 0 else None
-        roof["other_phases"] = other
-    info = s.query()
-    s.close()
+    serving = None
+    if not args.no_serving:
+        try:
+            serving, sizes = serve_run(args, torch, log)
+            serving["request_sizes"] = sizes
+        except Exception as e:  # reported, not fatal to the line
+            serving = {"error": repr(e)}
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, args.cpu_seconds)
 
-    dtype = "f64" if inst["precision"] == "fp64" else "f32 bond math / f64 integration"
+    dtype = "f64" if prec == "fp64" else "f32 bond math / f64 integration"
     line = {
-        "metric": METRIC, "value": value, "unit": "bond-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "metric": METRIC, "value": head["value"], "unit": "bond-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": inst["name"] + f", {K * inst['m']} PD steps ({K} macro steps)",
                    "pd_nodes": info["n_pd"], "bonds": info["nnz"], "m": inst["m"],
                    "fe_nodes": info["n_fe_nodes"], "constraints": info["n_constraints"],
-                   "dt_pd": inst["dt_pd"], "rebuilds": info["n_rebuilds"], "setup_s": setup_s,
+                   "dt_pd": inst["dt_pd"], "rebuilds": head["rebuilds"], "setup_s": head["setup_s"],
                    "source_digest": source_digest(),
-                   "gpu_event_ms": gpu_ms, "wall_ms": wall * 1e3},
-        "roofline": roof, "cpu_baseline": cpu,
+                   "gpu_event_ms": head["gpu_event_ms"], "wall_ms": head["wall_ms"]},
+        "roofline": head.get("roofline"),
+        "companion": companion,
+        "serving": serving,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -946,20 +946,30 @@ static int macro_step(orc_solver *s) {
    * free problem only (Sec. 2.5, note on broken bonds) */
   for (int j = 1; j <= m; j++) {
     double sfac = 1.0 - (double)j / (double)m; /* S_j = (1 - j/m) lambda_0 (reading R14) */
+    /* The loops over nodes below are independent per node (each node sums its
+     * own family and owns its row of bond states), so an OpenMP build gives
+     * identical results; without -fopenmp the pragmas are ignored. */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++)
       for (int d = 0; d < dim; d++) {
         int64_t t = i * dim + d;
         s->uP[t] = (s->uP[t] + s->dtP * s->vP[t]) + s->hdt2P * s->aP[t];
       }
+    int64_t broke_j = 0;
+    int region_j = 0;
+#pragma omp parallel for schedule(static) reduction(+ : broke_j) reduction(| : region_j)
     for (int64_t i = 0; i < N; i++) {
       double F[3];
       int64_t b = node_force(s, i, s->uP, s->mu, s->p.breaking, F);
       if (b) {
-        s->nbroken += b;
-        if (s->region[i]) region_broke = 1;
+        broke_j += b;
+        if (s->region[i]) region_j = 1;
       }
       for (int d = 0; d < dim; d++) fP[i * dim + d] = F[d];
     }
+    s->nbroken += broke_j;
+    if (region_j) region_broke = 1;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; i++) {
       int64_t q = coupled ? s->cidx[i] : -1;
       for (int d = 0; d < dim; d++) {

@@ -9,15 +9,21 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liborc.so")
+LIB_OMP = os.path.join(HERE, "liborc_omp.so")
 SRC = os.path.join(HERE, "mts_oracle.c")
 
 
-def build_oracle(force: bool = False) -> str:
-    """Compile the oracle with plain gcc, FP contraction off."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", LIB, SRC, "-lm"])
-    return LIB
+def build_oracle(force: bool = False, openmp: bool = False) -> str:
+    """Compile the oracle with plain gcc, FP contraction off.  openmp: the same
+    source with its per-node loops of the PD substep spread over threads
+    (identical results; used only to time the oracle on all host cores)."""
+    lib = LIB_OMP if openmp else LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        extra = ["-fopenmp"] if openmp else []
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", *extra,
+                               "-shared", "-o", lib + ".tmp", SRC, "-lm"])
+        os.replace(lib + ".tmp", lib)
+    return lib
 
 
 class _Problem(C.Structure):
@@ -53,13 +59,12 @@ class _Info(C.Structure):
 PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, DAMAGE, LAMBDA, PD_ALPHA, PD_MASS, FE_MASS, FE_X, H, \
     CONSTRAINT_NODES, FE_P, PD_P, GF, REGION, GF_NODES = range(19)
 
-_lib = None
+_libs = {}
 
 
-def _L():
-    global _lib
-    if _lib is None:
-        _lib = C.CDLL(build_oracle())
+def _L(openmp: bool = False):
+    if openmp not in _libs:
+        _lib = C.CDLL(build_oracle(openmp=openmp))
         P = C.POINTER
         _lib.orc_create.restype = C.c_void_p
         _lib.orc_create.argtypes = [P(_Problem)]
@@ -86,7 +91,8 @@ def _L():
                           P(C.c_int32), C.c_int64]
         _lib.orc_exp_moment.restype = C.c_double
         _lib.orc_exp_moment.argtypes = [C.c_int, C.c_double, C.c_double]
-    return _lib
+        _libs[openmp] = _lib
+    return _libs[openmp]
 
 
 def _dp(a):
@@ -161,10 +167,11 @@ def make_problem(inst: dict, setup_only: bool = False):
 class Oracle:
     """One oracle solve of an instance dict (from mts_inputs)."""
 
-    def __init__(self, inst: dict, setup_only: bool = False):
+    def __init__(self, inst: dict, setup_only: bool = False, openmp: bool = False):
         """setup_only: build weights, masses, FE mesh and the constraint set but
-        not the unit-load responses (for checks of large runs); cannot advance."""
-        self.lib = _L()
+        not the unit-load responses (for checks of large runs); cannot advance.
+        openmp: run on the OpenMP build (threads from OMP_NUM_THREADS)."""
+        self.lib = _L(openmp)
         self.inst = inst
         self._p, self._pos = make_problem(inst, setup_only)
         self.h = self.lib.orc_create(C.byref(self._p))

@@ -957,3 +957,19 @@ def test_fe_edge_traction_and_slit(coupled_small):
     scale = np.abs(f).max()
     assert np.abs(f[line & (X[:, 0] < a - 1.5 * h)]).max() <= 1e-12 * scale
     assert np.abs(f[line & (X[:, 0] > a + 0.5 * h)]).max() > 1e-3 * scale
+
+
+def test_openmp_build_identical():
+    """The OpenMP build of the oracle (used only to time it on all host cores)
+    gives bit-identical states: per-node sums, row-owned bond states."""
+    import os
+    os.environ.setdefault("OMP_NUM_THREADS", "4")
+    inst = mi.config(0)
+    a, b = Oracle(inst), Oracle(inst, openmp=True)
+    a.advance(inst["n_macro"])
+    b.advance(inst["n_macro"])
+    for q in (O.PD_U, O.PD_V, O.FE_U, O.LAMBDA, O.DAMAGE):
+        assert np.array_equal(a.get(q), b.get(q)), q
+    assert np.array_equal(a.bonds()[2], b.bonds()[2])
+    ia, ib = a.info(), b.info()
+    assert ia["n_broken"] == ib["n_broken"] > 0 and ia["n_rebuilds"] == ib["n_rebuilds"] > 0
