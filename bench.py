@@ -17,6 +17,7 @@ setup timed separately).  The same JSON line carries:
   (256 plate solves, Poisson arrivals at 20 per second);
 - the bond pass's roofline (HBM bound) on two byte models and the counter
   traffic;
+- the crack-branching plate of the paper's Sec. 4.1, MTS against pure PD;
 - the oracle's rate on the host's cores (one thread and all threads).
 
 Prints one JSON line.
@@ -308,6 +309,40 @@ def mixed_error(mts, torch, inst64, inst_mx, K, chunk, log):
     return res
 
 
+def branching_run(mts, torch, log):
+    """The crack-branching plate (100 x 40 mm glass, 50 mm notch, 12 MPa,
+    dx = 0.25 mm, 6e-5 s): the pure-PD model of the whole plate (400 x 160
+    nodes, 6000 steps of 1e-8 s) and the MTS model (220 x 120 PD nodes, Q4
+    elements of 1 mm, m = 10, 600 macro steps), each timed from a resident
+    state to the end of the run."""
+    import mts_inputs as mi
+    out = {}
+    for mode in ("pure_pd", "coupled"):
+        inst = mi.branching2d(400, mode)
+        t0 = time.perf_counter()
+        s = mts.Solver(inst)
+        s.sync()
+        setup = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(inst["n_macro"])
+        s.sync()
+        run = time.perf_counter() - t0
+        info = s.query()
+        e = s.energy()
+        tip = _tip(inst["pos"], s.read(mts.DAMAGE))
+        out[mode] = {"workload": inst["name"], "run_s": run, "setup_s": setup, "pd_nodes": info["n_pd"],
+                     "bonds": info["nnz"], "pd_steps": info["pd_steps"], "macro_steps": info["macro_steps"],
+                     "rebuilds": info["n_rebuilds"], "broken": e["n_broken"],
+                     "bond_updates_per_s": info["pd_steps"] * info["nnz"] / run,
+                     "tip_mm": None if tip is None else [float(tip[0] * 1e3), float(tip[1] * 1e3)]}
+        log(f"branching {mode}: {run:.3f} s, {info['n_rebuilds']} rebuilds, {e['n_broken']} broken")
+        s.close()
+    out["mts_speedup_vs_pure_pd"] = out["pure_pd"]["run_s"] / out["coupled"]["run_s"]
+    out["paper"] = "pure PD 1320 s vs MTS 863 s for the same 6e-5 s, RTX 3070, PeriFEM with implicit FE (context)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +356,7 @@ def main():
                     help="skip the other precision on the same instance (and the error check)")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default line")
+    ap.add_argument("--no-branching", action="store_true", help="skip the crack-branching comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="per oracle build (one thread, all threads)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
@@ -393,6 +429,13 @@ def main():
         except Exception as e:  # reported, not fatal to the line
             serving = {"error": repr(e)}
 
+    branching = None
+    if not args.no_branching:
+        try:
+            branching = branching_run(mts, torch, log)
+        except Exception as e:  # reported, not fatal to the line
+            branching = {"error": repr(e)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, args.cpu_seconds)
@@ -411,6 +454,7 @@ def main():
         "roofline": head.get("roofline"),
         "companion": companion,
         "serving": serving,
+        "branching": branching,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

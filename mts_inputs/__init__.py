@@ -157,6 +157,52 @@ def block3d(nx: int, ny: int, nz: int, m: int, n_pd_steps: int, dt_pd: float, *,
     return inst
 
 
+# Duran glass of the paper's crack-branching example (Sec. 4.1): critical
+# stretch given directly
+DURAN = dict(E=65e9, rho=2235.0, G0=0.0, s_crit=0.002689)
+
+
+def branching2d(nx: int = 400, mode: str = "coupled", *, m: int = 10, t_end: float = 6e-5,
+                precision: str = "fp64", perturb: float = 0.0, seed: int = SEED_BASE + 4,
+                traction: float = 12e6, name: Optional[str] = None) -> Dict:
+    """The crack-branching plate of the paper's Sec. 4.1: a 100 x 40 mm glass
+    plate with a 50 mm edge notch along y = 20 mm, traction on the upper and
+    lower edges, dx = 0.1 / nx (0.25 mm at nx = 400).
+
+    mode "pure_pd": PD nodes over the whole plate (nx x 0.4 nx), the traction
+    as a body force over a layer of width delta.  mode "coupled": a PD box of
+    55 x 30 mm (41.25 % of the plate) at x in [45, 100] mm, y in [5, 35] mm,
+    reaching the right edge, with an overlap band of 3 dx on its faces inside
+    the plate, and Q4 elements of 4 dx over the plate.  The PD step is 1e-8 s at
+    nx = 400 (scaled with dx), the FE step m times that; the run covers t_end."""
+    assert nx % 20 == 0
+    dx = 0.1 / nx
+    L, Hh = 0.1, 0.04
+    dt = 1e-8 * (400.0 / nx)
+    if mode == "pure_pd":
+        pd_lo, pd_hi = (0.0, 0.0), (L, Hh)
+        n = (nx, (2 * nx) // 5)
+        m_eff = 1
+    else:
+        pd_lo, pd_hi = (0.045, 0.005), (L, 0.035)
+        n = ((11 * nx) // 20, (3 * nx) // 10)
+        m_eff = m
+    fe_h = 4.0 * dx
+    n_pd_steps = int(round(t_end / dt))
+    inst = dict(
+        name=name or f"branching {n[0]}x{n[1]} {'pure PD' if mode == 'pure_pd' else f'm={m}'} {precision}",
+        dim=2, mode=mode, precision=precision, breaking=True,
+        pd_n=(n[0], n[1], 1), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.015,
+        perturb=perturb, seed=seed, dom_lo=(0.0, 0.0), dom_hi=(L, Hh),
+        fe_n=(int(round(L / fe_h)), int(round(Hh / fe_h)), 1) if mode != "pure_pd" else (0, 0, 0),
+        fe_h=fe_h, overlap=3.0 * dx, weight="cubic", cracks=[(0.02, 0.0, 0.05)],
+        thickness=1.0, kernel="pmb", l_over_delta=0.1, traction=traction, vel_bc=0.0,
+        m=m_eff, dt_pd=dt, n_macro=n_pd_steps // m_eff, **DURAN,
+    )
+    inst["pos"] = lattice_positions(n, pd_lo, dx, perturb, seed)
+    return inst
+
+
 # Step sizes (s): at most 0.8 of the smaller of the PD stability bound and the
 # explicit-FE bound divided by m, and below the Gershgorin FE bound / m.  The
 # bounds scale with dx for these layouts; the test suite re-derives them.

@@ -125,6 +125,12 @@ struct Sell {
   int32_t *halo_off = nullptr, *halo_ids = nullptr, *wg_start = nullptr;
   int64_t n_wg = 0;
   int32_t halo_max = 0;  // 0: no staging
+  // Workgroups whose staged lists hold a row of workgroup w, or whose rows w's
+  // list holds (a symmetric relation): dep_ids[dep_off[w] .. dep_off[w + 1]).
+  // Workgroup w of a substep may start once these finished the previous one.
+  int32_t *dep_off = nullptr, *dep_ids = nullptr;
+  int32_t max_deps = 0;
+  uint32_t *wg_flag = nullptr;  // per workgroup: the last substep it finished (epoch-numbered)
   int32_t wg_waves = 4;  // at most this many slices (wavefronts) per workgroup of the staged pass
   std::vector<int64_t> h_tile;  // host: spatial tile of each row (empty: rows not tiled)
   bool fp64_slots = false;      // slot records keep FP64 coefficients in the mixed form too
@@ -157,6 +163,7 @@ struct Solver {
   bool breaking = true;
   int m = 1;
   bool unstable = false;
+  bool wait_gave_up = false;     // a bounded wait of the subcycle kernel gave up (sticky)
   int64_t pd_steps = 0, macro_steps = 0, n_rebuilds = 0;
   int64_t n_intact0 = 0;  // intact bonds after setup (pre-crack cuts removed)
   std::vector<int64_t> h_node_tile;  // host: spatial tile of each node (empty: rows not tiled)
@@ -178,7 +185,8 @@ struct Solver {
   Sell sell;                     // full lattice, row = node
   double *damage = nullptr;
   int32_t *region_flag = nullptr;  // device flag: a bond in the link region broke
-  int32_t *nonfinite_flag = nullptr;  // device flag (sticky): a non-finite PD velocity at a macro-step end
+  int32_t *nonfinite_flag = nullptr;  // device, 2 ints (sticky): [0] a non-finite PD velocity at a
+                                      // macro-step end, [1] a bounded wait of the subcycle kernel gave up
   hipEvent_t nf_event = nullptr;   // after the copy of nonfinite_flag to pinned_flag[2] (end of mts_advance)
   bool nf_recorded = false;
   uint8_t *in_region = nullptr;    // per node
@@ -240,7 +248,7 @@ struct Solver {
   int nrhs = 8;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)
-  int32_t *pinned_flag = nullptr;  // host-pinned: [0], [1] rebuild flag per slot, [2] non-finite flag
+  int32_t *pinned_flag = nullptr;  // host-pinned: [0], [1] rebuild flag per slot, [2], [3] copies of nonfinite_flag
   uint64_t *mask_snap[2] = {nullptr, nullptr};  // full-lattice bond states at the end of a macro step
   hipEvent_t flag_event[2] = {nullptr, nullptr};
   bool pending = false;
@@ -253,6 +261,11 @@ struct Solver {
   int pd_variant = 0;              // bond-pass loop shape (chunk size, pipelining)
   bool halo = true;                // stage neighbour records in LDS when they fit
   int region_lanes = 0;            // lanes per row of the link region layout (0: automatic)
+  int subcycle = 0;                // run the m substeps of a macro step as one launch when it fits
+                                   // (opt-in: measured slower than one launch per substep)
+  uint32_t sub_epoch = 0;          // substeps finished by subcycle launches (workgroup flag numbering)
+  uint32_t spin_limit = 1u << 18;  // polls of a subcycle wait before it gives up (tests set it low)
+  int sub_capacity = -1;           // co-resident workgroups of the subcycle kernel (-1: not computed)
   int halo_waves = 0;              // wavefronts per workgroup of the staged pass (0: 8 for 3D mixed, else 4)
   double t_create0 = 0.0;
 
@@ -286,6 +299,7 @@ void bonds_to_csr_state(Solver &s, uint8_t *dev_out);
 void pd_setup(Solver &s);
 void pd_predict_all(Solver &s);
 void pd_substep(Solver &s, int j);
+bool pd_subcycle(Solver &s);  // all m substeps in one launch; false: not applicable, nothing enqueued
 void pd_damage(Solver &s);
 // batched substeps over several solvers of one form and lane count (pd.hip)
 size_t substep_entry_size();

@@ -383,6 +383,45 @@ void sell_build_halo(Solver &s, Sell &out) {
     ids.insert(ids.end(), set.begin(), set.end());
     off[w + 1] = (int32_t)ids.size();
   }
+  // Dependencies between workgroups: w depends on the owners of the nodes its
+  // list holds, and (symmetric closure) on the workgroups whose lists hold w's
+  // rows.  Rows outside this layout (link region) have no owner.
+  {
+    std::vector<int32_t> rows_h(out.n_rows);
+    MTS_HIP(hipMemcpyAsync(rows_h.data(), out.rows, sizeof(int32_t) * out.n_rows, hipMemcpyDeviceToHost, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> owner(s.N, -1);
+    for (int64_t w = 0; w < nwg; w++)
+      for (int64_t r = start[w] * S; r < std::min<int64_t>(start[w + 1] * S, out.n_rows); r++) owner[rows_h[r]] = (int32_t)w;
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    for (int64_t w = 0; w < nwg; w++)
+      for (int32_t h = off[w]; h < off[w + 1]; h++) {
+        const int32_t o = owner[ids[h]];
+        if (o >= 0 && o != w) {
+          pairs.push_back({(int32_t)w, o});
+          pairs.push_back({o, (int32_t)w});
+        }
+      }
+    std::sort(pairs.begin(), pairs.end());
+    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+    std::vector<int32_t> doff(nwg + 1, 0), dids(pairs.size());
+    for (size_t k = 0; k < pairs.size(); k++) {
+      doff[pairs[k].first + 1]++;
+      dids[k] = pairs[k].second;
+    }
+    for (int64_t w = 0; w < nwg; w++) {
+      out.max_deps = std::max(out.max_deps, doff[w + 1]);
+      doff[w + 1] += doff[w];
+    }
+    out.dep_off = s.arena.alloc<int32_t>(nwg + 1);
+    out.dep_ids = s.arena.alloc<int32_t>(std::max<size_t>(dids.size(), 1));
+    out.wg_flag = s.arena.alloc<uint32_t>(nwg);
+    MTS_HIP(hipMemcpyAsync(out.dep_off, doff.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice, st));
+    if (!dids.empty())
+      MTS_HIP(hipMemcpyAsync(out.dep_ids, dids.data(), sizeof(int32_t) * dids.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemsetAsync(out.wg_flag, 0, sizeof(uint32_t) * nwg, st));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
   out.n_wg = nwg;
   out.wg_start = s.arena.alloc<int32_t>(nwg + 1);
   MTS_HIP(hipMemcpyAsync(out.wg_start, start.data(), sizeof(int32_t) * (nwg + 1), hipMemcpyHostToDevice, st));

@@ -167,7 +167,22 @@ __device__ __forceinline__ void load_slot_chunk(const uint64_t *mask, const uint
   }
 }
 
-template <int DIM, int L, bool MX, int TM, bool HALO = false, bool PAIR = false>
+// A node record's 16-byte part, read either through the caches (ld32) or
+// coherently with every chiplet's writes (COH: two agent-scope loads, which
+// fetch from memory rather than from this chiplet's L2).
+template <bool COH>
+__device__ __forceinline__ double2 ld_rec(const double2 *base, uint32_t byte_off) {
+  if constexpr (COH) {
+    const uint64_t *p = reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(base) + byte_off);
+    const uint64_t a = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
+  } else {
+    return ld32(base, byte_off);
+  }
+}
+
+template <int DIM, int L, bool MX, int TM, bool HALO = false, bool PAIR = false, bool COH = false>
 __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params &P, const int64_t slice,
                                              const double2 *lds = nullptr, const SlotChunk<TM> *first = nullptr) {
   // MX: mixed form -- stretch, force and accumulation in FP32 on differences
@@ -198,7 +213,7 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
     double rec[2 * DIM];
 #pragma unroll
     for (int h = 0; h < DIM; h++) {
-      const double2 v2 = ld32(reinterpret_cast<const double2 *>(A.xu_in), (uint32_t)i * RB + 16u * h);
+      const double2 v2 = ld_rec<COH>(reinterpret_cast<const double2 *>(A.xu_in), (uint32_t)i * RB + 16u * h);
       rec[2 * h] = v2.x;
       rec[2 * h + 1] = v2.y;
     }
@@ -358,7 +373,12 @@ __device__ __forceinline__ void substep_body(const SubstepArgs &A, const Params 
     A.a[tix] = an;
     A.v[tix] = vn;
     if (A.nonfinite && !__builtin_isfinite(vn)) A.nonfinite[0] = 1;
-    A.xu_out[(int64_t)i * 2 * DIM + DIM + d] = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
+    const double un = (ui_[d] + P.dtP * vn) + P.hdt2P * an;
+    if constexpr (COH)  // written through to memory, where the other chiplets read it
+      __hip_atomic_store(reinterpret_cast<uint64_t *>(A.xu_out + (int64_t)i * 2 * DIM + DIM + d),
+                         (uint64_t)__double_as_longlong(un), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      A.xu_out[(int64_t)i * 2 * DIM + DIM + d] = un;
   }
   if (A.damage && l == 0) {
     const int fam = A.rp[i + 1] - A.rp[i];
@@ -377,14 +397,14 @@ __global__ __launch_bounds__(kBlock) void k_pd_substep(SubstepArgs A, Params P) 
 }
 
 // Copy workgroup wg's neighbour records into LDS (all NT threads; a barrier follows).
-template <int DIM, int NT>
+template <int DIM, int NT, bool COH = false>
 __device__ __forceinline__ void stage_halo(const SubstepArgs &A, int64_t wg, double2 *lds) {
   const int h0 = A.halo_off[wg], nh = A.halo_off[wg + 1] - h0;
   const double2 *src = reinterpret_cast<const double2 *>(A.xu_in);
   for (int h = threadIdx.x; h < nh; h += NT) {
     const uint32_t rb = (uint32_t)A.halo_ids[h0 + h] * (16u * DIM);
 #pragma unroll
-    for (int q = 0; q < DIM; q++) lds[h * DIM + q] = ld32(src, rb + 16u * q);
+    for (int q = 0; q < DIM; q++) lds[h * DIM + q] = ld_rec<COH>(src, rb + 16u * q);
   }
 }
 
@@ -416,6 +436,86 @@ __global__ __launch_bounds__(NW * 64, NW == 8 ? 4 : 1) void k_pd_substep_halo(Su
     __syncthreads();
     if (!active) return;
     substep_body<DIM, L, MX, 4, true, MX>(A, P, slice, lds);
+  }
+}
+
+// ---- the m substeps of a macro step in one launch (opt-in) ----
+//
+// Every workgroup of the staged pass stays resident for all m substeps of the
+// free problem and keeps its tile.  Substep j of tile w needs the predicted
+// displacements of substep j - 1 of every node its staged list holds, and it
+// overwrites (in the other record buffer) the rows that other tiles staged in
+// substep j - 1; both are covered by waiting until every tile in w's
+// dependency list (a symmetric relation, built with the layout) has finished
+// substep j - 1.  The node records are written and read coherently across the
+// chiplets (agent-scope accesses, which go to memory rather than to a
+// chiplet's own L2), so no cache-wide write-back or invalidation is needed:
+// each wavefront waits for its stores to complete, then one thread publishes
+// "finished substep j" as base + j in the tile's flag; a waiting tile polls
+// its dependencies' flags.  Every wait is bounded: after spin_limit polls it
+// sets the give-up flag and goes on, so the kernel always ends (the host then
+// reports the solve as failed).  The launch is cooperative, so every
+// workgroup is resident.
+struct SubcycleArgs {
+  SubstepArgs A;              // substep 1 (xu_in, xu_out swap every substep)
+  double *damage;             // written by substep m
+  int32_t *nonfinite;         // [0] non-finite velocity (substep m), [1] a wait gave up
+  const int32_t *dep_off, *dep_ids;
+  uint32_t *flags;            // per workgroup
+  uint32_t base;              // flag value after substep j: base + j
+  uint32_t spin_limit;
+  int m;
+};
+
+// Publish "this workgroup finished substep value - base" once every
+// wavefront's coherent record stores have completed.
+__device__ __forceinline__ void subcycle_publish(const SubcycleArgs &S, int b, uint32_t value) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(S.flags + b, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until every dependency of workgroup b published at least `target`
+// (lanes of the first wavefront poll one dependency each).
+__device__ __forceinline__ void subcycle_wait(const SubcycleArgs &S, int b, uint32_t target) {
+  if (threadIdx.x < WAVE) {
+    const int d0 = S.dep_off[b], nd = S.dep_off[b + 1] - d0;
+    for (int k = (int)threadIdx.x; k < nd; k += WAVE) {
+      const uint32_t *f = S.flags + S.dep_ids[d0 + k];
+      uint32_t polls = 0;
+      while ((int32_t)(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+        if (++polls > S.spin_limit ||
+            __hip_atomic_load(S.nonfinite + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          __hip_atomic_store(S.nonfinite + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIM, int L, bool MX, int NW>
+__global__ __launch_bounds__(NW * 64, NW == 8 ? 4 : 1) void k_pd_subcycle_halo(SubcycleArgs S, Params P) {
+  extern __shared__ double2 lds[];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  SubstepArgs A = S.A;
+  const int s0 = A.wg_start[b], w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const bool active = w < A.wg_start[b + 1] - s0;  // wave-uniform
+  const int64_t slice = s0 + w;
+  double *const buf0 = const_cast<double *>(A.xu_in), *const buf1 = A.xu_out;
+  for (int j = 1; j <= S.m; j++) {
+    A.xu_in = (j & 1) ? buf0 : buf1;
+    A.xu_out = (j & 1) ? buf1 : buf0;
+    A.sfac = 1.0 - (double)j / (double)S.m;
+    A.damage = j == S.m ? S.damage : nullptr;
+    A.nonfinite = j == S.m ? S.nonfinite : nullptr;
+    if (j > 1) subcycle_wait(S, b, S.base + (uint32_t)(j - 1));
+    stage_halo<DIM, NW * 64, true>(A, b, lds);
+    __syncthreads();
+    if (active) substep_body<DIM, L, MX, 4, true, MX, true>(A, P, slice, lds);
+    subcycle_publish(S, b, S.base + (uint32_t)j);
   }
 }
 
@@ -944,6 +1044,47 @@ void pd_substep(Solver &s, int j) {
   MTS_LAUNCH_CHECK();
   s.cur ^= 1;
   s.pd_steps++;
+}
+
+// All m substeps of the free problem as one launch of the staged pass, when
+// every workgroup of it can be resident at once; reads u[cur ^ 1] like
+// substep 1 and leaves cur flipped m times.
+bool pd_subcycle(Solver &s) {
+  if (!s.subcycle || s.sell.halo_max <= 0 || !s.sell.dep_off || s.m < 2) return false;
+  if ((s.precision == MTS_MIXED) != s.sell.pair_slots) return false;
+  const int L = s.sell.L;
+  const int nw = s.sell.wg_waves;
+  const size_t shm = (size_t)s.sell.halo_max * 16 * s.dim;
+  const void *fn = nullptr;
+#define MTS_SUBC(D, LL, MX)                                                                  \
+  fn = nw == 8 ? reinterpret_cast<const void *>(&k_pd_subcycle_halo<D, LL, MX, 8>)          \
+               : reinterpret_cast<const void *>(&k_pd_subcycle_halo<D, LL, MX, 4>)
+  MTS_BY_FORM(s.dim, s.precision == MTS_MIXED, L, MTS_SUBC);
+#undef MTS_SUBC
+  if (s.sub_capacity < 0) {
+    int per_cu = 0, n_cu = 0;
+    MTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nw * 64, shm));
+    MTS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s.device));
+    s.sub_capacity = per_cu * n_cu;
+  }
+  if (s.sell.n_wg > s.sub_capacity) return false;
+  SubcycleArgs S{};
+  S.A = substep_args(s, 1, s.cur);
+  S.damage = s.damage;
+  S.nonfinite = s.nonfinite_flag;
+  S.dep_off = s.sell.dep_off;
+  S.dep_ids = s.sell.dep_ids;
+  S.flags = s.sell.wg_flag;
+  S.base = s.sub_epoch;
+  S.spin_limit = s.spin_limit;
+  S.m = s.m;
+  void *args[] = {&S, &s.prm};
+  MTS_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)s.sell.n_wg), dim3((unsigned)(nw * 64)), args,
+                                     (unsigned)shm, s.stream));
+  s.sub_epoch += (uint32_t)s.m;
+  if (s.m & 1) s.cur ^= 1;
+  s.pd_steps += s.m;
+  return true;
 }
 
 // ---- batched substeps over several solvers (serving pool) ----

@@ -223,6 +223,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
     s->region_lanes = (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
   }
   if (const char *t = std::getenv("MTS_HALO_WAVES")) s->halo_waves = std::atoi(t) == 8 ? 8 : 4;  // tuning
+  if (const char *t = std::getenv("MTS_SUBCYCLE")) s->subcycle = std::atoi(t) != 0;  // one launch per macro step
+  if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
     const int L = std::atoi(e);
@@ -269,8 +271,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   MTS_HIP(hipMemsetAsync(s->damage, 0, sizeof(double) * N, st));
   s->region_flag = ar.alloc<int32_t>(1);
   MTS_HIP(hipMemsetAsync(s->region_flag, 0, sizeof(int32_t), st));
-  s->nonfinite_flag = ar.alloc<int32_t>(1);
-  MTS_HIP(hipMemsetAsync(s->nonfinite_flag, 0, sizeof(int32_t), st));
+  s->nonfinite_flag = ar.alloc<int32_t>(2);
+  MTS_HIP(hipMemsetAsync(s->nonfinite_flag, 0, 2 * sizeof(int32_t), st));
   MTS_HIP(hipEventCreateWithFlags(&s->nf_event, hipEventDisableTiming));
   build_neighbors(*s);
   vlog(*s, "neighbours: %lld nodes, %lld bonds, %d lanes per row", (long long)N, (long long)s->nnz, s->sell.L);
@@ -281,8 +283,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
     coupling_setup(*s);
   }
   pd_predict_all(*s);
-  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 3 * sizeof(int32_t), hipHostMallocDefault));
-  s->pinned_flag[0] = s->pinned_flag[1] = s->pinned_flag[2] = 0;
+  MTS_HIP(hipHostMalloc((void **)&s->pinned_flag, 4 * sizeof(int32_t), hipHostMallocDefault));
+  s->pinned_flag[0] = s->pinned_flag[1] = s->pinned_flag[2] = s->pinned_flag[3] = 0;
   pd_damage(*s);
   s->n_intact0 = count_intact(*s);
   MTS_HIP(hipStreamSynchronize(st));
@@ -384,8 +386,9 @@ void resolve_pending(Solver &s) {
   const int slot = s.pending_slot;
   MTS_HIP(hipEventSynchronize(s.flag_event[slot]));
   s.pending = false;
-  if (s.pinned_flag[2]) {  // a velocity of that macro step was not finite: stop here
-    s.unstable = true;
+  if (s.pinned_flag[3]) s.wait_gave_up = true;
+  if (s.pinned_flag[2] || s.pinned_flag[3]) {  // a velocity of that macro step was not finite: stop here
+    s.unstable = s.unstable || s.pinned_flag[2] != 0;
     return;
   }
   if (s.pinned_flag[slot]) {
@@ -403,13 +406,14 @@ void poll_nonfinite(Solver &s) {
   if (q == hipErrorNotReady) return;
   MTS_HIP(q);
   if (s.pinned_flag[2]) s.unstable = true;
+  if (s.pinned_flag[3]) s.wait_gave_up = true;
 }
 
 void advance_impl(Solver &s, int64_t n) {
   const bool coupled = s.p.mode == MTS_COUPLED;
   const bool track = coupled && s.m >= 2;
   poll_nonfinite(s);
-  for (int64_t k = 0; k < n && !s.unstable; k++) {
+  for (int64_t k = 0; k < n && !s.unstable && !s.wait_gave_up; k++) {
     if (coupled && !s.fe_free_done) {
       hipEvent_t e0 = nullptr;
       s.prof_begin(MTS_KT_FE, &e0);
@@ -421,7 +425,8 @@ void advance_impl(Solver &s, int64_t n) {
       // the m substep launches run back to back; one event pair brackets them
       hipEvent_t e0 = nullptr;
       s.prof_begin(MTS_KT_PD_SUBSTEP, &e0);
-      for (int j = 1; j <= s.m; j++) pd_substep(s, j);
+      if (!pd_subcycle(s))
+        for (int j = 1; j <= s.m; j++) pd_substep(s, j);
       s.prof_end(MTS_KT_PD_SUBSTEP, e0, s.m);
     }
     int slot = -1;
@@ -431,11 +436,11 @@ void advance_impl(Solver &s, int64_t n) {
       // the next macro step's substeps and any rebuild that reads them
       slot = (int)(s.macro_steps & 1);
       MTS_HIP(hipMemcpyAsync(s.pinned_flag + slot, s.region_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
-      MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+      MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
       MTS_HIP(hipEventRecord(s.flag_event[slot], s.stream));
     }
     resolve_pending(s);  // previous macro step's check
-    if (s.unstable) break;
+    if (s.unstable || s.wait_gave_up) break;
     // the next macro step's FE free step joins this one's link launches when
     // another macro step of this call follows (the state between calls stays
     // that of a whole macro step) and no per-phase timing is taken
@@ -446,8 +451,8 @@ void advance_impl(Solver &s, int64_t n) {
     }
     s.macro_steps++;
   }
-  if (!s.unstable && n > 0) {
-    MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+  if (!s.unstable && !s.wait_gave_up && n > 0) {
+    MTS_HIP(hipMemcpyAsync(s.pinned_flag + 2, s.nonfinite_flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
     MTS_HIP(hipEventRecord(s.nf_event, s.stream));
     s.nf_recorded = true;
   }
@@ -594,8 +599,15 @@ mts_status mts_advance(mts_solver *h, int64_t n) {
   if (!h) return (std::snprintf(g_err, sizeof g_err, "null solver"), MTS_EINVAL);
   if (n < 0) return (std::snprintf(g_err, sizeof g_err, "negative step count"), MTS_EINVAL);
   if (h->s.unstable) return (std::snprintf(g_err, sizeof g_err, "solver is unstable"), MTS_EUNSTABLE);
+  if (h->s.wait_gave_up)
+    return (std::snprintf(g_err, sizeof g_err, "a bounded wait of the subcycle kernel gave up"), MTS_EDEVICE);
   try {
     advance_impl(h->s, n);
+    if (h->s.wait_gave_up) {
+      std::snprintf(g_err, sizeof g_err, "a bounded wait of the subcycle kernel gave up (%lld macro steps enqueued)",
+                    (long long)h->s.macro_steps);
+      return MTS_EDEVICE;
+    }
     if (h->s.unstable) {
       std::snprintf(g_err, sizeof g_err, "non-finite PD velocity at the end of a macro step (%lld macro steps enqueued)",
                     (long long)h->s.macro_steps);
@@ -613,6 +625,11 @@ mts_status mts_sync(mts_solver *h) {
     resolve_pending(h->s);
     MTS_HIP(hipStreamSynchronize(h->s.stream));
     if (h->s.pinned_flag[2]) h->s.unstable = true;
+    if (h->s.pinned_flag[3]) h->s.wait_gave_up = true;
+    if (h->s.wait_gave_up) {
+      std::snprintf(g_err, sizeof g_err, "a bounded wait of the subcycle kernel gave up");
+      return MTS_EDEVICE;
+    }
     check_finite(h->s);
     if (h->s.unstable) {
       std::snprintf(g_err, sizeof g_err, "non-finite PD velocity");

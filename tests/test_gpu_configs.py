@@ -201,3 +201,56 @@ def test_block_m8(mts, precision, env):
     worst, _, _ = _compare(mts, inst, env)
     snaps = _oracle_run(inst)
     assert np.abs(snaps[-1]["u"]).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# Crack-branching plate (Sec. 4.1) at dx = 1 mm: the MTS model (55 x 30 mm PD
+# box reaching the plate's right edge, m = 10) and the pure-PD model of the
+# whole plate, each against the oracle through the first breaks
+# ---------------------------------------------------------------------------
+_BR = {}
+
+
+def _branch_oracle(mode, n_macro):
+    if mode not in _BR:
+        inst = mi.branching2d(100, mode, t_end=4e-5)
+        o = Oracle(inst)
+        snaps = []
+        for _ in range(n_macro):
+            o.advance(1 if mode == "coupled" else 10)
+            snaps.append({"u": o.get(O.PD_U), "v": o.get(O.PD_V), "phi": o.get(O.DAMAGE), "mu": o.bonds()[2],
+                          "broken": o.info()["n_broken"],
+                          "lam": o.get(O.LAMBDA) if mode == "coupled" else None})
+        o.close()
+        _BR[mode] = (inst, snaps)
+    return _BR[mode]
+
+
+@pytest.mark.parametrize("mode", ["coupled", "pure_pd"])
+def test_branching_plate(mts, mode):
+    n = 52 if mode == "coupled" else 50   # macro steps (coupled) or 10-step chunks (pure PD)
+    inst, snaps = _branch_oracle(mode, n)
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    pos, dx = inst["pos"], inst["dx"]
+    worst, same_after, tips = 0.0, 0, 0
+    for k, w in enumerate(snaps):
+        s.advance(1 if mode == "coupled" else 10)
+        mu = s.bonds()[2]
+        same = np.array_equal(mu, w["mu"])
+        if w["broken"] == 0 or same:
+            qs = (("u", mts.PD_U), ("v", mts.PD_V)) + ((("lam", mts.LAMBDA),) if mode == "coupled" else ())
+            for key, q in qs:
+                e = _rel(s.read(q), w[key])
+                worst = max(worst, e)
+                assert e <= (1e-10 if w["broken"] == 0 else 1e-9), (k, key, e)
+            assert np.array_equal(s.read(mts.DAMAGE), w["phi"]), k
+            same_after += w["broken"] > 0
+        else:
+            tg, to = _tip(pos, s.read(mts.DAMAGE)), _tip(pos, w["phi"])
+            tips += 1
+            assert np.linalg.norm(tg - to) <= dx * (1 + 1e-9), k
+    assert snaps[-1]["broken"] > 0
+    print(f"  worst {worst:.2e}, checks with equal bond states after breaking {same_after}, tip checks {tips}, "
+          f"oracle broken {snaps[-1]['broken']}", flush=True)
+    s.close()

@@ -23,7 +23,7 @@ def mts():
     return m
 
 
-KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT")
+KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT", "MTS_SUBCYCLE", "MTS_SPIN_LIMIT")
 
 
 def _run(mts, inst, n_macro, env):
@@ -107,3 +107,49 @@ def test_fe_passes_in_link_launches_bit_identical(mts, dim):
         assert np.array_equal(a.read(q), b.read(q)), q
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("case", ["plate50 fp64", "plate50 mixed", "block12 fp64", "block12 mixed"])
+def test_subcycle_launch_bit_identical(mts, case):
+    """The m substeps of a macro step as one launch (the opt-in subcycle
+    kernel: workgroups resident for the whole subcycle, each waiting only for
+    the tiles it shares nodes with) give the same trajectories and bond
+    states, bit for bit, as one launch per substep, through breaks."""
+    name, prec = case.split()
+    if name == "plate50":
+        inst = dict(mi.config(0, precision=prec), name=case)
+        n = 50
+    else:
+        inst = mi.block3d(12, 12, 6, 4, 80, 5e-8, perturb=1e-6, seed=42, precision=prec, name=case)
+        n = 20
+    print("case", inst["name"], flush=True)
+    ref, nb = _run(mts, inst, n, {"MTS_SUBCYCLE": "0"})
+    assert nb > 0
+    got, _ = _run(mts, inst, n, {"MTS_SUBCYCLE": "1"})
+    _same(ref, got)
+
+
+def test_subcycle_wait_gives_up_cleanly(mts):
+    """With the poll limit forced to zero the subcycle kernel's waits give up
+    at once: the kernel still ends, and the solver reports MTS_EDEVICE (sticky)
+    instead of results."""
+    inst = dict(mi.config(0), name="plate50 give-up")
+    saved = {k: os.environ.get(k) for k in KNOBS}
+    try:
+        for k in KNOBS:
+            os.environ.pop(k, None)
+        os.environ.update({"MTS_SUBCYCLE": "1", "MTS_SPIN_LIMIT": "0"})
+        s = mts.Solver(inst)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    with pytest.raises(mts.MtsError) as e:
+        s.advance(6)
+        s.sync()
+    assert e.value.status == 3  # MTS_EDEVICE
+    with pytest.raises(mts.MtsError):
+        s.advance(1)
+    s.close()
