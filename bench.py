@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=2, help="workload index (1: 400x160 plate, 2: 1000x400 plate, "
                                                           "3: 100x100x20 block)")
+    ap.add_argument("--fe-beta", type=float, default=0.0,
+                    help="Newmark beta of the FE step: 0 explicit, 0.25 implicit (average acceleration)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default=None,
                     help="precision of the headline run (default: fp64 on the plates, mixed on the block)")
     ap.add_argument("--no-companion", action="store_true",
@@ -399,6 +401,9 @@ def main():
     default_prec = "mixed" if args.config == 3 else "fp64"
     prec = args.precision or default_prec
     inst = mi.config(args.config, precision=prec)
+    if args.fe_beta:
+        inst["fe_beta"] = args.fe_beta
+        inst["name"] += f" implicit FE (beta {args.fe_beta:g})"
     other = "mixed" if prec == "fp64" else "fp64"
     K = args.steps if args.steps is not None else inst["n_macro"]
     W = args.warmup
@@ -408,6 +413,9 @@ def main():
     companion = None
     if not args.no_companion:
         inst2 = mi.config(args.config, precision=other)
+        if args.fe_beta:
+            inst2["fe_beta"] = args.fe_beta
+            inst2["name"] += f" implicit FE (beta {args.fe_beta:g})"
         c = run_form(mts, torch, inst2, K, W, args, log)
         c.pop("info")
         fp64_rec, mx_rec = (head, c) if prec == "fp64" else (c, head)

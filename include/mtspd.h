@@ -79,6 +79,11 @@ typedef struct mts_problem {
   double E, rho, G0, thickness, s_crit, l_over_delta;
   double traction, vel_bc;
   double dt_pd;         /* PD step (s) > 0; the FE step is m * dt_pd */
+  double fe_beta;       /* Newmark beta of the FE step (gamma = 1/2): 0 explicit (lumped mass),
+                           1/4 average acceleration, implicit: each FE step solves
+                           (M + beta dt_FE^2 K) a = f by conjugate gradients, which lifts the
+                           FE stability bound on dt_FE (Eq. 38; coupled mode, one solver, not
+                           the pool) */
 } mts_problem;
 
 typedef struct mts_info {

@@ -175,6 +175,10 @@ struct orc_solver {
   double D[6][6];
   double Ngp[8][8], dNgp[8][8][3]; /* per gauss point, per local node */
   double detJ;
+  /* implicit FE (Newmark beta > 0): Cholesky factor of the dense system matrix
+   * A = M + beta dt^2 K over all FE dofs (identity on prescribed and inactive dofs) */
+  double beta;
+  double *LA;
   /* coupling */
   int64_t nc, nl;
   int64_t *cn, *cel, *cidx;
@@ -337,6 +341,68 @@ int orc_fe_force(orc_solver *s, const double *u, double *f) {
       for (int d = 0; d < dim; d++) f[(int64_t)s->conn[e * s->nen + a] * dim + d] += fe[a * dim + d];
   }
   return 0;
+}
+
+/* Free (unprescribed, active) FE dof? */
+static int fe_free_dof(const orc_solver *s, int64_t t) {
+  return s->nact[t / s->dim] && !s->bc[t];
+}
+
+/* Implicit FE (Newmark, Eq. 38 with beta > 0): A = M + beta dt_FE^2 K on the
+ * free dofs, the identity on prescribed and inactive ones (their acceleration
+ * is zero), assembled column by column from the internal force and factored
+ * (Cholesky, A = L L^T). */
+static int build_fe_implicit(orc_solver *s) {
+  int64_t nF = s->nfe * s->dim;
+  double c = s->beta * s->dtF * s->dtF;
+  double *A = xcalloc((size_t)(nF * nF), sizeof(double));
+  double *e = xcalloc((size_t)nF, sizeof(double));
+  double *f = xcalloc((size_t)nF, sizeof(double));
+  s->LA = A;
+  if (!A || !e || !f) { free(e); free(f); return -1; }
+  for (int64_t j = 0; j < nF; j++) {
+    if (!fe_free_dof(s, j)) {
+      A[j * nF + j] = 1.0;
+      continue;
+    }
+    e[j] = 1.0;
+    orc_fe_force(s, e, f); /* column j of K */
+    e[j] = 0.0;
+    for (int64_t i = 0; i < nF; i++)
+      if (fe_free_dof(s, i)) A[i * nF + j] = c * f[i];
+    A[j * nF + j] += s->mF[j / s->dim];
+  }
+  free(e);
+  free(f);
+  for (int64_t j = 0; j < nF; j++) {
+    double d = A[j * nF + j];
+    for (int64_t k = 0; k < j; k++) d -= A[j * nF + k] * A[j * nF + k];
+    if (!(d > 0.0)) { set_err("implicit FE matrix not positive definite at row %lld", (long long)j); return -1; }
+    double ljj = sqrt(d);
+    A[j * nF + j] = ljj;
+    for (int64_t i = j + 1; i < nF; i++) {
+      double t = A[i * nF + j];
+      for (int64_t k = 0; k < j; k++) t -= A[i * nF + k] * A[j * nF + k];
+      A[i * nF + j] = t / ljj;
+    }
+  }
+  return 0;
+}
+
+/* x = A^-1 b through the Cholesky factor (x and b may alias). */
+static void fe_solve(const orc_solver *s, const double *b, double *x) {
+  int64_t nF = s->nfe * s->dim;
+  const double *L = s->LA;
+  for (int64_t i = 0; i < nF; i++) {
+    double t = b[i];
+    for (int64_t k = 0; k < i; k++) t -= L[i * nF + k] * x[k];
+    x[i] = t / L[i * nF + i];
+  }
+  for (int64_t i = nF - 1; i >= 0; i--) {
+    double t = x[i];
+    for (int64_t k = i + 1; k < nF; k++) t -= L[k * nF + i] * x[k];
+    x[i] = t / L[i * nF + i];
+  }
 }
 
 static int build_fe(orc_solver *s) {
@@ -692,6 +758,32 @@ static int build_y(orc_solver *s) {
       for (int d = 0; d < dim; d++) u[i * dim + d] = v[i * dim + d] = a[i * dim + d] = 0.0;
     }
   }
+  if (s->beta > 0.0) {
+    /* + gamma dt_FE G_F A^-1 G_F^T  (-G_F Ydot^FE of the implicit FE step) */
+    int64_t nF = s->nfe * dim;
+    double *x = xcalloc((size_t)nF, sizeof(double));
+    if (!x) { free(u); free(v); free(a); free(f); free(ball); free(slot); return -1; }
+    for (int64_t c = 0; c < nl; c++) {
+      int64_t qq = c / dim;
+      int dc = (int)(c % dim);
+      memset(x, 0, sizeof(double) * (size_t)nF);
+      for (int aq = 0; aq < s->nen; aq++) {
+        int64_t t = (int64_t)s->conn[s->cel[qq] * s->nen + aq] * dim + dc;
+        if (fe_free_dof(s, t)) x[t] += s->cw[qq * s->nen + aq];
+      }
+      fe_solve(s, x, x);
+      for (int64_t pq = 0; pq < s->nc; pq++)
+        for (int dp = 0; dp < dim; dp++) {
+          double g = 0.0;
+          for (int ap = 0; ap < s->nen; ap++) {
+            int64_t t = (int64_t)s->conn[s->cel[pq] * s->nen + ap] * dim + dp;
+            if (fe_free_dof(s, t)) g += s->cw[pq * s->nen + ap] * x[t];
+          }
+          s->H[(pq * dim + dp) * nl + c] += s->hdtF * g; /* gamma = 1/2 */
+        }
+    }
+    free(x);
+  } else
   /* + 1/2 dt_FE G_F M_F^-1 G_F^T  (-G_F Ydot^FE) */
   for (int64_t pq = 0; pq < s->nc; pq++)
     for (int64_t qq = 0; qq < s->nc; qq++) {
@@ -827,6 +919,9 @@ orc_solver *orc_create(const orc_problem *p) {
       return NULL;
     }
     if (build_fe(s)) { orc_destroy(s); return NULL; }
+    s->beta = p->fe_beta;
+    if (s->beta != 0.0 && !(s->beta == 0.25)) { set_err("fe_beta must be 0 or 1/4"); orc_destroy(s); return NULL; }
+    if (s->beta > 0.0 && build_fe_implicit(s)) { orc_destroy(s); return NULL; }
     /* constraints at every PD node of the overlap (reading R12) */
     for (int64_t i = 0; i < N; i++) if (s->alpha[i] > 0.0) s->nc++;
     s->nl = s->nc * dim;
@@ -892,6 +987,7 @@ void orc_destroy(orc_solver *s) {
   free(s->mF); free(s->uF); free(s->vF); free(s->aF); free(s->PF);
   free(s->cn); free(s->cidx); free(s->cel); free(s->cw); free(s->H); free(s->L); free(s->lam0);
   free(s->region);
+  free(s->LA);
   free(s);
 }
 
@@ -916,7 +1012,35 @@ static int macro_step(orc_solver *s) {
   int rc = -1;
   if (!fP || !ut || !vt || !at || !fF || !tF || !r || !lam || !W) goto out;
 
-  if (coupled) {
+  if (coupled && s->beta > 0.0) {
+    /* FE free problem (Eq. 47a) with the implicit Newmark step (Eq. 38,
+     * gamma = 1/2, beta = 1/4): predictors, then A a~ = P - K u* */
+    double b2 = (0.5 - s->beta) * s->dtF * s->dtF;
+    for (int64_t n = 0; n < s->nfe; n++) {
+      if (!s->nact[n]) continue;
+      for (int d = 0; d < dim; d++) {
+        int64_t t = n * dim + d;
+        if (s->bc[t]) ut[t] = s->uF[t] + s->dtF * s->p.vel_bc;
+        else ut[t] = (s->uF[t] + s->dtF * s->vF[t]) + b2 * s->aF[t];
+      }
+    }
+    orc_fe_force(s, ut, fF);
+    for (int64_t t = 0; t < s->nfe * dim; t++) at[t] = fe_free_dof(s, t) ? s->PF[t] - fF[t] : 0.0;
+    fe_solve(s, at, at);
+    for (int64_t n = 0; n < s->nfe; n++) {
+      if (!s->nact[n]) continue;
+      for (int d = 0; d < dim; d++) {
+        int64_t t = n * dim + d;
+        if (s->bc[t]) {
+          at[t] = 0.0;
+          vt[t] = s->p.vel_bc;
+        } else {
+          ut[t] = ut[t] + s->beta * s->dtF * s->dtF * at[t];
+          vt[t] = (s->vF[t] + s->hdtF * s->aF[t]) + s->hdtF * at[t];
+        }
+      }
+    }
+  } else if (coupled) {
     /* FE free problem (Eq. 47a, Newmark Eq. 38 with beta = 0) over dt_FE */
     for (int64_t n = 0; n < s->nfe; n++) {
       if (!s->nact[n]) continue;
@@ -1011,6 +1135,21 @@ static int macro_step(orc_solver *s) {
         int64_t n = s->conn[s->cel[q] * s->nen + a];
         for (int d = 0; d < dim; d++) tF[n * dim + d] += s->cw[q * s->nen + a] * lam[q * dim + d];
       }
+    if (s->beta > 0.0) {
+      /* implicit FE link response: A dA = -G_F^T lambda; da, gamma dt dA, beta dt^2 dA */
+      for (int64_t t = 0; t < s->nfe * dim; t++)
+        if (!fe_free_dof(s, t)) tF[t] = 0.0;
+      fe_solve(s, tF, tF);
+      for (int64_t n = 0; n < s->nfe; n++) {
+        if (!s->nact[n]) continue;
+        for (int d = 0; d < dim; d++) {
+          int64_t t = n * dim + d;
+          s->uF[t] = ut[t] - s->beta * s->dtF * s->dtF * tF[t];
+          s->vF[t] = vt[t] - s->hdtF * tF[t];
+          s->aF[t] = at[t] - tF[t];
+        }
+      }
+    } else
     for (int64_t n = 0; n < s->nfe; n++) {
       if (!s->nact[n]) continue;
       for (int d = 0; d < dim; d++) {

@@ -35,6 +35,8 @@ typedef struct {
   int32_t setup_only;         /* 1: weights, masses, FE mesh and constraint set only
                                  (no link region, no unit-load responses, no stepping);
                                  for checks of large runs against the constraint set */
+  double fe_beta;             /* Newmark beta of the FE step: 0 explicit, 1/4 average
+                                 acceleration (implicit, gamma = 1/2 in both) */
 } orc_problem;
 
 typedef struct {

@@ -41,6 +41,7 @@ class _Problem(C.Structure):
         ("thickness", C.c_double), ("s_crit", C.c_double), ("l_over_delta", C.c_double),
         ("traction", C.c_double), ("vel_bc", C.c_double), ("dt_pd", C.c_double),
         ("setup_only", C.c_int32),
+        ("fe_beta", C.c_double),
     ]
 
 
@@ -161,6 +162,7 @@ def make_problem(inst: dict, setup_only: bool = False):
         setattr(p, k, float(inst.get(k, 0.0)))
     p.s_crit = float(inst.get("s_crit", 0.0))
     p.setup_only = 1 if setup_only else 0
+    p.fe_beta = float(inst.get("fe_beta", 0.0))
     return p, pos
 
 

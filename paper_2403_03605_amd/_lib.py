@@ -39,6 +39,7 @@ class Problem(C.Structure):
         ("E", C.c_double), ("rho", C.c_double), ("G0", C.c_double), ("thickness", C.c_double),
         ("s_crit", C.c_double), ("l_over_delta", C.c_double),
         ("traction", C.c_double), ("vel_bc", C.c_double), ("dt_pd", C.c_double),
+        ("fe_beta", C.c_double),
     ]
 
 
@@ -165,7 +166,7 @@ def make_problem(inst: dict):
             arr[a] = float(inst[name][a])
     p.fe_h = float(inst.get("fe_h", 0.0))
     p.overlap = float(inst.get("overlap", 0.0))
-    for k in ("E", "rho", "G0", "thickness", "l_over_delta", "traction", "vel_bc", "dt_pd"):
+    for k in ("E", "rho", "G0", "thickness", "l_over_delta", "traction", "vel_bc", "dt_pd", "fe_beta"):
         setattr(p, k, float(inst.get(k, 0.0)))
     p.s_crit = float(inst.get("s_crit", 0.0))
     return p, pos

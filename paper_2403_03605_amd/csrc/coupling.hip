@@ -162,6 +162,12 @@ __global__ void k_add_hf(int64_t nc, int dim, int nen, int64_t nl, const int32_t
   for (int d = 0; d < dim; d++) H[(pq * dim + d) * nl + qq * dim + d] += hdtF * acc[d];
 }
 
+// H += HF (the implicit FE block, computed once)
+__global__ void k_add_dense(int64_t n, const double *HF, double *H) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) H[i] = H[i] + HF[i];
+}
+
 // r = G_F v~_F - G_P V_m  (right-hand side of Eq. 49, from Eq. 41)
 __global__ void k_rhs(int64_t nc, int dim, int nen, const int32_t *cn, const int32_t *cel, const int32_t *conn,
                       const double *cw, const double *vt, const double *vP, int64_t N, double *r) {
@@ -399,6 +405,8 @@ void coupling_setup(Solver &s) {
               }
             }
           }
+    if (s.fe_beta > 0.0)  // A^-1 of the implicit FE step couples every constraint
+      for (int64_t q = 0; q < s.nc; q++) parent[q] = 0;
     std::vector<int32_t> label(s.nc, -1);
     std::vector<std::vector<int32_t>> comps;
     for (int64_t q = 0; q < s.nc; q++) {
@@ -416,6 +424,10 @@ void coupling_setup(Solver &s) {
   for (int k = 0; k < 2; k++) {
     s.mask_snap[k] = ar.alloc<uint64_t>(s.sell.n_words);
     MTS_HIP(hipEventCreateWithFlags(&s.flag_event[k], hipEventDisableTiming));
+  }
+  if (s.fe_beta > 0.0) {
+    fe_implicit_hf(s);  // does not change when bonds break
+    vlog(s, "fe: implicit block of H done");
   }
   coupling_rebuild(s, s.sell.mask);
 }
@@ -452,9 +464,13 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   }
   MTS_HIP(hipStreamSynchronize(st));  // before the host colour table goes away
   s.arena.release(drcd);
-  dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
-  k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
-                                s.p.fe_n[1], s.H);
+  if (s.fe_beta > 0.0) {
+    k_add_dense<<<nb(nl * nl), 256, 0, st>>>(nl * nl, s.fe_HF, s.H);
+  } else {
+    dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
+    k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
+                                  s.p.fe_n[1], s.H);
+  }
   MTS_LAUNCH_CHECK();
   vlog(s, "coupling: unit-load responses done (%lld colour batches)", (long long)((s.n_colors + cpb - 1) / cpb));
   if (s.keep_h) {
@@ -468,7 +484,8 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
 
 bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe, int snap_slot) {
   coupling_lambda(s);
-  return coupling_link(s, fuse_next_fe, snap_slot);
+  if (s.fe_beta > 0.0) fe_implicit_correct(s);  // a full-mesh solve, not a ring pass
+  return coupling_link(s, fuse_next_fe && s.fe_beta == 0.0, snap_slot);
 }
 
 void coupling_lambda(Solver &s) {
@@ -488,8 +505,9 @@ bool coupling_link(Solver &s, bool fuse_next_fe, int snap_slot) {
   // the next macro step's FE free step (element forces, then the gather)
   // follows in the second and third (they read the FE state this step's
   // correction leaves).
+  const bool ring = s.n_ring && s.fe_beta == 0.0;  // the implicit correction ran before
   if (!s.rsell.n_rows) {
-    fe_correct(s);
+    if (ring) fe_correct(s);
     if (snap_slot >= 0) snapshot_masks(s, snap_slot);
     return false;
   }
@@ -501,7 +519,7 @@ bool coupling_link(Solver &s, bool fuse_next_fe, int snap_slot) {
   bool snapped = snap_slot < 0;
   for (int j = 1; j <= s.m; j++) {
     int side = kSideNone;
-    if (j == 1 && s.n_ring) side = kSideRing;
+    if (j == 1 && ring) side = kSideRing;
     if (fuse && j == 2) side = kSideElem;
     if (fuse && j == 3) side = kSideGather;
     if (side == kSideNone && !snapped) {  // the first launch with room saves the bond states

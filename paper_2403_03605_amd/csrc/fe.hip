@@ -314,6 +314,7 @@ void fe_setup(Solver &s) {
   k_fe_init<<<nb(nfe), 256, 0, st>>>(nfe, dim, s.nact, s.bc, s.PF, s.mF, p.vel_bc, s.vF, s.aF);
   MTS_LAUNCH_CHECK();
   MTS_HIP(hipStreamSynchronize(st));
+  if (s.fe_beta > 0.0) fe_implicit_setup(s);
 }
 
 FeElemArgs fe_elem_args(Solver &s, bool predict) {
@@ -387,6 +388,7 @@ FeRingArgs fe_ring_args(Solver &s) {
 }
 
 void fe_free_step(Solver &s) {
+  if (s.fe_beta > 0.0) return fe_implicit_free_step(s);
   hipStream_t st = s.stream;
   const FeElemArgs E = fe_elem_args(s, true);
   if (s.dim == 2) k_fe_elem_force<2, true><<<nb(s.ne), 256, 0, st>>>(E);
@@ -407,6 +409,7 @@ void fe_elem_forces_current(Solver &s) {
 }
 
 void fe_correct(Solver &s) {
+  if (s.fe_beta > 0.0) return fe_implicit_correct(s);
   if (!s.n_ring) return;
   k_fe_correct_ring<<<(unsigned)((s.n_ring * WAVE + 255) / 256), 256, 0, s.stream>>>(fe_ring_args(s));
   MTS_LAUNCH_CHECK();

@@ -203,6 +203,13 @@ struct Solver {
   double *xF = nullptr, *mF = nullptr, *PF = nullptr;
   double *uF = nullptr, *vF = nullptr, *aF = nullptr;
   double *ut = nullptr, *vt = nullptr, *at = nullptr, *fe_buf = nullptr;
+  // implicit FE step (fe_beta > 0)
+  double fe_beta = 0.0;
+  double *fe_Ke = nullptr;        // per element (nen dim)^2 stiffness, alpha-weighted
+  uint8_t *fe_free = nullptr;     // per dof: active and not prescribed
+  double *fe_inv_diag = nullptr;  // Jacobi preconditioner of M + beta dt^2 K
+  double *fe_HF = nullptr;        // nl x nl FE block (dt/2) G_F A^-1 G_F^T of H
+  struct FeImplicit *fe_impl = nullptr;  // conjugate-gradient buffers (host struct)
   void *fe_tab = nullptr;        // element tables (shape functions, derivatives, Hooke), device
   std::vector<int32_t> h_conn;
   std::vector<uint8_t> h_bc;
@@ -311,6 +318,12 @@ void substep_batch_launch(int dim, bool mixed, int L, const void *dev_tab, const
 void fe_setup(Solver &s);
 void fe_free_step(Solver &s);
 void fe_correct(Solver &s);
+// implicit FE step (fe_implicit.hip)
+void fe_implicit_setup(Solver &s);
+void fe_implicit_free_step(Solver &s);
+void fe_implicit_correct(Solver &s);  // after lambda_m
+void fe_implicit_hf(Solver &s);       // the FE block of H, once
+void fe_implicit_free(Solver &s);     // host buffers
 // coupling (coupling.hip)
 void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);

@@ -53,6 +53,7 @@ void destroy_solver(Solver *s) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->nf_event) (void)hipEventDestroy(s->nf_event);
+  fe_implicit_free(*s);
   if (s->pinned_flag) (void)hipHostFree(s->pinned_flag);
   s->arena.free_all();
   delete s;
@@ -389,6 +390,7 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
   if (n_macro < 1) return (set_error("n_macro must be >= 1"), MTS_EINVAL);
   if (p->dim != P->dim || p->precision != P->precision)
     return (set_error("request dim/precision differ from the pool's"), MTS_EINVAL);
+  if (p->fe_beta != 0.0) return (set_error("the pool runs the explicit FE step only (fe_beta = 0)"), MTS_EINVAL);
   mts_plan_info plan{};
   const mts_status pst = mts_plan(p, &plan);
   if (pst != MTS_OK) return pst;

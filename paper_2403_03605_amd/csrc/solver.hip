@@ -147,6 +147,7 @@ void validate(const mts_problem *p) {
     if (!(p->fe_h > 0.0) || !(p->overlap > 0.0)) throw ArgError{"coupled mode needs fe_h > 0 and overlap > 0"};
     if (p->weight_kind < 0 || p->weight_kind > 2) throw ArgError{"unknown weight_kind"};
   }
+  if (!(p->fe_beta == 0.0 || p->fe_beta == 0.25)) throw ArgError{"fe_beta must be 0 (explicit) or 1/4"};
   for (int64_t i = 0; i < p->n_pd * p->dim; i++)
     if (!std::isfinite(p->host_pd_pos[i])) throw ArgError{"non-finite node position"};
 }
@@ -240,6 +241,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   s->precision = pin->precision;
   s->breaking = pin->breaking != 0;
   s->m = pin->m;
+  s->fe_beta = pin->mode == MTS_COUPLED ? pin->fe_beta : 0.0;
   derive_params(*s);
   DeviceArena &ar = s->arena;
   hipStream_t st = s->stream;
@@ -444,7 +446,7 @@ void advance_impl(Solver &s, int64_t n) {
     // the next macro step's FE free step joins this one's link launches when
     // another macro step of this call follows (the state between calls stays
     // that of a whole macro step) and no per-phase timing is taken
-    if (coupled) s.fe_free_done = coupling_solve_and_correct(s, k + 1 < n && !s.profiling, slot);
+    if (coupled) s.fe_free_done = coupling_solve_and_correct(s, k + 1 < n && !s.profiling && s.fe_beta == 0.0, slot);
     if (track) {
       s.pending = true;
       s.pending_slot = slot;
@@ -588,6 +590,7 @@ mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_by
       (void)hipGetLastError();
       if (h->s.pinned_flag) (void)hipHostFree(h->s.pinned_flag);
       if (h->s.nf_event) (void)hipEventDestroy(h->s.nf_event);
+      fe_implicit_free(h->s);
       h->s.arena.free_all();
       delete h;
     }
@@ -915,6 +918,7 @@ void mts_destroy(mts_solver *h) {
     if (e) (void)hipEventDestroy(e);
   if (s.nf_event) (void)hipEventDestroy(s.nf_event);
   if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
+  fe_implicit_free(s);
   s.arena.free_all();
   delete h;
 }

@@ -254,3 +254,53 @@ def test_branching_plate(mts, mode):
     print(f"  worst {worst:.2e}, checks with equal bond states after breaking {same_after}, tip checks {tips}, "
           f"oracle broken {snaps[-1]['broken']}", flush=True)
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Implicit FE step (Newmark beta = 1/4, the paper's FE integrator)
+# ---------------------------------------------------------------------------
+def _implicit_cases():
+    c1 = dict(mi.config(0), name="plate 50x20 m=4 implicit FE")
+    c1["fe_beta"] = 0.25
+    # dt_FE = 16 x 1.5e-7 s: 3.2 times the explicit bound of its 5 mm elements
+    p40 = mi.plate2d(40, 16, 16 * 24, 1.5e-7, perturb=1e-6, seed=81, name="plate 40x16 m=16 implicit FE")
+    p40["fe_beta"] = 0.25
+    b12 = mi.block3d(12, 12, 6, 8, 8 * 16, 7.5e-8, perturb=1e-6, seed=82, material="steel",
+                     name="block 12x12x6 m=8 implicit FE")
+    b12["fe_beta"] = 0.25
+    return [c1, p40, b12]
+
+
+@pytest.mark.parametrize("inst", _implicit_cases(), ids=lambda x: x["name"])
+def test_implicit_fe(mts, inst):
+    """Coupled runs with the implicit FE step against the oracle (dense
+    Cholesky of M + beta dt^2 K where the library runs conjugate gradients):
+    PD and FE state, multipliers and damage within 1e-10 before the first
+    break, 1e-9 while the bond states agree, crack tip within dx after."""
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    o = Oracle(inst)
+    pos, dx = inst["pos"], inst["dx"]
+    worst, tips = 0.0, 0
+    n = inst["n_macro"]
+    for k in range(0, n, 2):
+        s.advance(2)
+        o.advance(2)
+        broken = o.info()["n_broken"]
+        same = np.array_equal(s.bonds()[2], o.bonds()[2])
+        if broken == 0 or same:
+            tol = 1e-10 if broken == 0 else 1e-9
+            for gq, oq in ((mts.PD_U, O.PD_U), (mts.PD_V, O.PD_V), (mts.FE_U, O.FE_U), (mts.FE_V, O.FE_V),
+                           (mts.FE_A, O.FE_A), (mts.LAMBDA, O.LAMBDA)):
+                e = _rel(s.read(gq), o.get(oq))
+                worst = max(worst, e)
+                assert e <= tol, (k, gq, e)
+            assert np.array_equal(s.read(mts.DAMAGE), o.get(O.DAMAGE)), k
+        else:
+            tg, to = _tip(pos, s.read(mts.DAMAGE)), _tip(pos, o.get(O.DAMAGE))
+            tips += 1
+            if tg is not None and to is not None:
+                assert np.linalg.norm(tg - to) <= dx * (1 + 1e-9), k
+    print(f"  worst {worst:.2e}, tip checks {tips}, oracle broken {o.info()['n_broken']}", flush=True)
+    assert np.abs(o.get(O.FE_U)).max() > 0
+    s.close()
