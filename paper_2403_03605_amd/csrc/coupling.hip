@@ -19,7 +19,7 @@
 namespace mts {
 
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
-                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs);
+                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, const int32_t *slice_layer);
 void link_records_init(Solver &s);
 void link_final_substep(Solver &s, int j, int k, bool add, int side, int snap_slot);
 void sell_regather_mask(Solver &s, Sell &out, const uint64_t *src_mask_full);
@@ -107,6 +107,42 @@ __global__ void k_slice_layer(const int32_t *rows, int64_t n_rows, int64_t n_sli
     if (r >= n_rows) break;
     int v = layer[rows[r]];
     h = v < h ? v : h;
+  }
+  slice_layer[s] = h;
+}
+
+// Layer of every slice of the link region with respect to the constraint
+// nodes loaded by one batch of unit loads: the smallest k <= m such that some
+// row of the slice lies within k horizons of a loaded node (m if none).  A
+// response that has run j substeps is still exactly zero beyond j - 1 such
+// horizons, so the batch's link substeps skip those slices.
+__global__ void k_batch_layer(const double *x, int64_t N, int dim, const int32_t *rows, int64_t n_rows,
+                              int64_t n_slices, int L, const int32_t *nodes, int n_nodes, double delta, int m,
+                              int32_t *slice_layer) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_slices) return;
+  const int S = WAVE / L;
+  double best = 1e300;
+  for (int j = 0; j < S; j++) {
+    const int64_t r = s * S + j;
+    if (r >= n_rows) break;
+    const int64_t i = rows[r];
+    for (int q = 0; q < n_nodes; q++) {
+      const int64_t c = nodes[q];
+      const double d0 = x[i] - x[c];
+      const double d1 = x[N + i] - x[N + c];
+      double r2 = d0 * d0 + d1 * d1;
+      if (dim == 3) {
+        const double d2 = x[2 * N + i] - x[2 * N + c];
+        r2 = r2 + d2 * d2;
+      }
+      best = r2 < best ? r2 : best;
+    }
+  }
+  int h = m;
+  for (int k = m - 1; k >= 0; k--) {
+    const double hk = (double)k * delta;
+    if (best <= hk * hk * (1.0 + 1e-9)) h = k;
   }
   slice_layer[s] = h;
 }
@@ -349,6 +385,25 @@ void coupling_setup(Solver &s) {
     MTS_HIP(hipStreamSynchronize(st));
   }
   s.nrhs = dim == 2 ? 8 : 6;
+  {
+    // loaded constraint nodes of every batch of unit loads (colours bt * cpb ..)
+    const int cpb = s.nrhs / dim;
+    const int64_t nbatch = (s.n_colors + cpb - 1) / cpb;
+    std::vector<int32_t> boff(nbatch + 1, 0), bnodes;
+    std::vector<std::vector<int32_t>> members(s.n_colors);
+    for (int64_t q = 0; q < s.nc; q++) members[color[q]].push_back(s.h_cn[q]);
+    for (int64_t bt = 0; bt < nbatch; bt++) {
+      for (int64_t c = bt * cpb; c < std::min<int64_t>((bt + 1) * cpb, s.n_colors); c++)
+        bnodes.insert(bnodes.end(), members[c].begin(), members[c].end());
+      boff[bt + 1] = (int32_t)bnodes.size();
+    }
+    s.h_batch_off = boff;
+    s.batch_nodes = ar.alloc<int32_t>(std::max<size_t>(bnodes.size(), 1));
+    if (!bnodes.empty())
+      MTS_HIP(hipMemcpyAsync(s.batch_nodes, bnodes.data(), sizeof(int32_t) * bnodes.size(), hipMemcpyHostToDevice, st));
+    s.batch_layer = ar.alloc<int32_t>(std::max<int64_t>(s.rsell.n_slices, 1));
+    MTS_HIP(hipStreamSynchronize(st));
+  }
   size_t wsz = (size_t)s.nrhs * dim * N;
   s.Wu[0] = ar.alloc<double>(wsz);
   s.Wu[1] = ar.alloc<double>(wsz);
@@ -453,9 +508,16 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   MTS_HIP(hipMemcpyAsync(drcd, rcd.data(), sizeof(int32_t) * rcd.size(), hipMemcpyHostToDevice, st));
   for (int64_t bt = 0; bt < nbatch; bt++) {
     const int32_t *rc = &rcd[bt * 32], *rd = &rcd[bt * 32 + 16];
+    if (s.rsell.n_slices) {
+      const int32_t b0 = s.h_batch_off[bt], nbn = s.h_batch_off[bt + 1] - b0;
+      k_batch_layer<<<nb(s.rsell.n_slices), 256, 0, st>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
+                                                         s.rsell.n_slices, s.rsell.L, s.batch_nodes + b0, nbn,
+                                                         s.prm.delta, s.m, s.batch_layer);
+      MTS_LAUNCH_CHECK();
+    }
     int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
     for (int j = 1; j <= s.m; j++) {
-      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.ccolor, rc, rd, s.nrhs);
+      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.ccolor, rc, rd, s.nrhs, s.batch_layer);
       k ^= 1;
     }
     k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drcd + bt * 32, drcd + bt * 32 + 16,

@@ -252,6 +252,9 @@ struct Solver {
   int64_t n_colors = 0;
   int32_t *ccolor = nullptr;     // colour of each constraint
   int32_t *owner = nullptr;      // n_colors * nc: loaded constraint of that colour reaching q, or -1
+  std::vector<int32_t> h_batch_off;  // per batch of unit loads: range of batch_nodes
+  int32_t *batch_nodes = nullptr;    // PD node ids of the constraints loaded by each batch
+  int32_t *batch_layer = nullptr;    // per link-region slice: layer w.r.t. the current batch's loads
   int nrhs = 8;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)

@@ -1128,7 +1128,7 @@ static void launch_link(Solver &s, LinkArgs &A) {
 // One substep j of the unit-load responses over the region rows.
 // u_in/u_out/v/a: [N][nrhs][dim].
 void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v, double *a, const int32_t *ccolor,
-                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs) {
+                  const int32_t *rhs_color, const int32_t *rhs_dir, int nrhs, const int32_t *slice_layer) {
   if (!s.rsell.n_rows) return;
   LinkArgs A{};
   A.xrec = s.xu[0];
@@ -1137,7 +1137,7 @@ void link_substep(Solver &s, int j, const double *u_in, double *u_out, double *v
   A.n_slices = s.rsell.n_slices;
   A.T = s.rsell.T;
   A.rows = s.rsell.rows;
-  A.slice_layer = s.rsell.slice_layer;
+  A.slice_layer = slice_layer ? slice_layer : s.rsell.slice_layer;
   A.jmax = j - 1;
   A.col = s.rsell.col;
   A.coef = s.rsell.coef;
