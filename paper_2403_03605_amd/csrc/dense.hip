@@ -383,15 +383,30 @@ __global__ void k_negate(double *a, int64_t n) {
 // its half-wavefront by recursive halving (a fixed order: deterministic).
 __device__ __forceinline__ double pick(bool hi, double a, double b) { return hi ? b : a; }
 
+// Largest |entry| of every packed tile (one wavefront per tile).
+__global__ void k_tile_absmax(const double *packed, int64_t n_tiles, double *out) {
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (tile >= n_tiles) return;
+  const double *src = packed + tile * TS * TS;
+  double m = 0.0;
+  for (int q = lane; q < TS * TS; q += WAVE) m = fmax(m, fabs(src[q]));
+  for (int off = WAVE / 2; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, WAVE));
+  if (lane == 0) out[tile] = m;
+}
+
 __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
                                                    const int64_t *off, const int32_t *idx, const double *r,
-                                                   int64_t n_tiles, double *rowpart, double *colpart) {
+                                                   const int32_t *kept, const int64_t *n_kept, double *rowpart,
+                                                   double *colpart) {
+  const int64_t n_tiles = *n_kept;
   __shared__ double xs[4][2][TS];  // per wavefront: x_I, x_J
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
   const int h = lane >> 5, c0 = 2 * (lane & 31);
   const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
   const int64_t stride = (int64_t)gridDim.x * 4;
-  for (int64_t tile = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + w)); tile < n_tiles; tile += stride) {
+  for (int64_t k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + w)); k < n_tiles; k += stride) {
+    const int64_t tile = kept[k];
     const double2 *src = reinterpret_cast<const double2 *>(packed + tile * TS * TS);
     double2 e[8];
 #pragma unroll
@@ -575,14 +590,56 @@ void sym_blocks_build(Solver &s) {
     vlog(s, "coupling: block %lld of %lld inverted (%lld dofs)", (long long)(c + 1), (long long)B.n_comp,
          (long long)n);
   }
+  sym_blocks_prune(s);
+}
+
+// The tiles each multiplier solve reads.  The inverse of H decays
+// exponentially with the distance between constraints (H couples constraints
+// within twice the response reach); a tile whose largest entry is at most
+// kInvDrop of the largest entry of its component adds at most
+// (dofs) x kInvDrop x max|H^-1| x max|r| to any multiplier, far below the
+// rounding of the product itself (dofs x eps relative), so it is skipped.
+// Skipped tiles keep zero partial sums, so the fixed-order reduction is
+// unchanged.  MTS_INV_DROP=0 keeps every tile.
+void sym_blocks_prune(Solver &s) {
+  constexpr double kInvDrop = 1e-18;
+  auto &B = s.sym;
+  hipStream_t st = s.stream;
+  if (!B.n_tiles) return;
+  if (!B.tile_max) B.tile_max = s.arena.alloc<double>((size_t)B.n_tiles);
+  if (!B.kept) B.kept = s.arena.alloc<int32_t>((size_t)B.n_tiles);
+  if (!B.n_kept_dev) B.n_kept_dev = s.arena.alloc<int64_t>(1);
+  k_tile_absmax<<<(unsigned)B.n_tiles, WAVE, 0, st>>>(B.packed, B.n_tiles, B.tile_max);
+  MTS_LAUNCH_CHECK();
+  std::vector<double> tm((size_t)B.n_tiles);
+  std::vector<int32_t> meta((size_t)B.n_tiles * 3);
+  MTS_HIP(hipMemcpyAsync(tm.data(), B.tile_max, sizeof(double) * tm.size(), hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipMemcpyAsync(meta.data(), B.tile_meta, sizeof(int32_t) * meta.size(), hipMemcpyDeviceToHost, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  std::vector<double> cmax((size_t)B.n_comp, 0.0);
+  for (int64_t t = 0; t < B.n_tiles; t++) cmax[meta[t * 3]] = std::max(cmax[meta[t * 3]], tm[t]);
+  std::vector<int32_t> kept;
+  for (int64_t t = 0; t < B.n_tiles; t++)
+    if (!B.prune || meta[t * 3 + 1] == meta[t * 3 + 2] || tm[t] > kInvDrop * cmax[meta[t * 3]])
+      kept.push_back((int32_t)t);
+  B.n_kept = (int64_t)kept.size();
+  MTS_HIP(hipMemcpyAsync(B.kept, kept.data(), sizeof(int32_t) * kept.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.n_kept_dev, &B.n_kept, sizeof(int64_t), hipMemcpyHostToDevice, st));
+  // skipped tiles contribute zero partial sums
+  MTS_HIP(hipMemsetAsync(B.rowpart, 0, sizeof(double) * B.n_tiles * TS, st));
+  MTS_HIP(hipMemsetAsync(B.colpart, 0, sizeof(double) * B.n_tiles * TS, st));
+  MTS_HIP(hipStreamSynchronize(st));
+  vlog(s, "coupling: the multiplier solve reads %lld of %lld tiles", (long long)B.n_kept, (long long)B.n_tiles);
 }
 
 void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   auto &B = s.sym;
   if (!B.n_tiles) return;
   // four tiles per workgroup at a time; up to eight resident workgroups per CU
+  // the grid covers every tile; the count of kept tiles is read on the device
   const unsigned g = (unsigned)std::min<int64_t>((B.n_tiles + 3) / 4, 256 * 8);
-  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.n_tiles, B.rowpart, B.colpart);
+  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.kept, B.n_kept_dev, B.rowpart,
+                                       B.colpart);
   MTS_LAUNCH_CHECK();
   k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
                                                         B.rowpart, B.colpart, y, y2);

@@ -242,6 +242,14 @@ struct Solver {
     double *pblk = nullptr;         // inverse of the current 256-wide pivot block
     int64_t n_rows = 0;             // block rows over all components
     int32_t *row_comp = nullptr, *row_block = nullptr;
+    // tiles the multiplier solve reads: every diagonal tile and every tile
+    // whose largest entry exceeds kInvDrop of its component's largest entry
+    int32_t *kept = nullptr;        // tile ids, ascending
+    int64_t n_kept = 0;
+    int64_t *n_kept_dev = nullptr;  // the same count on the device (launches read it, so a
+                                    // captured solve stays valid when a rebuild changes it)
+    double *tile_max = nullptr;     // per tile: largest |entry| of the inverse
+    bool prune = true;
   } sym;
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;
@@ -343,6 +351,7 @@ enum { kSideNone = 0, kSideRing = 1, kSideElem = 2, kSideGather = 3, kSideSnap =
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
 void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2 = nullptr);
+void sym_blocks_prune(Solver &s);  // the tiles the solve reads
 // solver construction and helpers shared with the serving pool (solver.hip)
 void create_impl(const mts_problem *pin, void *stream, Solver *s);
 mts_status fail_from_exception();

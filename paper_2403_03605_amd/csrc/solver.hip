@@ -225,6 +225,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   }
   if (const char *t = std::getenv("MTS_HALO_WAVES")) s->halo_waves = std::atoi(t) == 8 ? 8 : 4;  // tuning
   if (const char *t = std::getenv("MTS_SUBCYCLE")) s->subcycle = std::atoi(t) != 0;  // one launch per macro step
+  if (const char *t = std::getenv("MTS_INV_DROP")) s->sym.prune = std::atoi(t) != 0;  // tests: read every tile
   if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
@@ -871,7 +872,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->dim = s.dim;
   o->precision = s.precision;
   o->dt_bound_pd = s.dt_bound_pd;
-  o->inverse_bytes = s.sym.n_tiles * 64 * 64 * (int64_t)sizeof(double);
+  o->inverse_bytes = (s.sym.kept ? s.sym.n_kept : s.sym.n_tiles) * 64 * 64 * (int64_t)sizeof(double);
   o->slot_bytes = s.sell.pair_slots ? 6.0 : s.precision == MTS_MIXED ? 8.0 : 12.0;
 }
 
