@@ -84,6 +84,12 @@ typedef struct mts_problem {
                            (M + beta dt_FE^2 K) a = f by conjugate gradients, which lifts the
                            FE stability bound on dt_FE (Eq. 38; coupled mode, one solver, not
                            the pool) */
+  double traction_x;    /* uniform traction (Pa, +x) on the FE face x = dom_hi[0], weighted by
+                           alpha like the y-face traction (Eq. 34 P^FE): the end load of the
+                           beam of Sec. 3.2 (coupled mode, one solver, not the pool) */
+  int32_t clamp_x0;     /* 1: every displacement component of the FE nodes on the face
+                           x = dom_lo[0] is held at zero (the fixed end of that beam); needs
+                           vel_bc = 0 (coupled mode, one solver, not the pool) */
 } mts_problem;
 
 typedef struct mts_info {

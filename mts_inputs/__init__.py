@@ -203,6 +203,51 @@ def branching2d(nx: int = 400, mode: str = "coupled", *, m: int = 10, t_end: flo
     return inst
 
 
+# Elastic beam of the paper's error study (Sec. 3.2): E = 6.5 GPa, rho = 2235,
+# no breaking (the critical stretch is nominal).
+BEAM = dict(E=6.5e9, rho=2235.0, G0=0.0, s_crit=1.0)
+
+
+def beam3d(dx: float = 0.05, *, weight: str = "cubic", overlap_cells: int = 3, m: int = 1,
+           dt_fe: float = 2.5e-5, t_end: float = 0.025, fe_beta: float = 0.0, mode: str = "coupled",
+           precision: str = "fp64", traction: float = 4e6, name: Optional[str] = None) -> Dict:
+    """The 1 x 1 x 10 m beam of the paper's Sec. 3.2: fixed at x = 0, a uniform
+    traction (+x) on the end x = 10 m, Hex8 elements of size dx over the beam,
+    PD nodes (cell-centred, spacing dx) over 4 < x < 6 with an overlap of
+    overlap_cells * dx on the two faces inside the beam, horizon 3.03 dx,
+    exponential micromodulus with l = delta / 16.  The FE step is dt_fe, the
+    PD step dt_fe / m; the run covers t_end.  mode "pure_fe": the undecomposed
+    FE model (no PD nodes), the paper's reference.  The tracked point A is the
+    FE node at the centre of the loaded end (`beam_node_a`)."""
+    L, W = 10.0, 1.0
+    n_len, n_w, n_pd = int(round(L / dx)), int(round(W / dx)), int(round(2.0 / dx))
+    assert n_w % 2 == 0 and abs(n_len * dx - L) < 1e-9 * L
+    pd_lo, pd_hi = (4.0, 0.0, 0.0), (6.0, W, W)
+    inst = dict(
+        name=name or f"beam {n_len}x{n_w}x{n_w} {weight} lO={overlap_cells}dx m={m} "
+                     f"{'implicit' if fe_beta else 'explicit'} FE {precision}",
+        dim=3, mode=mode, precision=precision, breaking=False,
+        pd_n=(n_pd, n_w, n_w), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.03,
+        perturb=0.0, seed=SEED_BASE + 5, dom_lo=(0.0, 0.0, 0.0), dom_hi=(L, W, W),
+        fe_n=(n_len, n_w, n_w), fe_h=dx, overlap=overlap_cells * dx, weight=weight, cracks=[],
+        thickness=1.0, kernel="exp", l_over_delta=1.0 / 16.0, traction=0.0, vel_bc=0.0,
+        traction_x=traction, clamp_x0=True, fe_beta=fe_beta,
+        m=m, dt_pd=dt_fe / m, n_macro=int(round(t_end / dt_fe)), **BEAM,
+    )
+    if mode == "pure_fe":
+        inst["pos"] = np.zeros((0, 3))
+    else:
+        inst["pos"] = lattice_positions((n_pd, n_w, n_w), pd_lo, dx)
+    return inst
+
+
+def beam_node_a(inst: Dict) -> int:
+    """FE node id of the beam's tracked point A, the centre of the loaded end
+    (grid node ids run x fastest, then y, then z)."""
+    nx, ny, nz = inst["fe_n"]
+    return ((nz // 2) * (ny + 1) + ny // 2) * (nx + 1) + nx
+
+
 # Step sizes (s): at most 0.8 of the smaller of the PD stability bound and the
 # explicit-FE bound divided by m, and below the Gershgorin FE bound / m.  The
 # bounds scale with dx for these layouts; the test suite re-derives them.

@@ -5,9 +5,9 @@
  *
  * TEST INFRASTRUCTURE ONLY: plain FP64 loops, no blocking, no reordering.
  * Each function names the passage of the paper it follows.  Where the paper is
- * silent the reading taken is stated next to the code (readings R1..R26 of the
- * design notes).  Built with -O2 -ffp-contract=off so that every expression is
- * evaluated exactly as written.
+ * silent the reading taken is stated next to the code, numbered R1, R2, ...
+ * Built with -O2 -ffp-contract=off so that every expression is evaluated
+ * exactly as written.
  */
 #include "mts_oracle.h"
 
@@ -179,6 +179,7 @@ struct orc_solver {
    * A = M + beta dt^2 K over all FE dofs (identity on prescribed and inactive dofs) */
   double beta;
   double *LA;
+  double *febuf;              /* per-element internal forces of orc_fe_force (ne * nen * dim) */
   /* coupling */
   int64_t nc, nl;
   int64_t *cn, *cel, *cidx;
@@ -204,6 +205,7 @@ static void *xcalloc(size_t n, size_t sz) {
  * alpha = 1 once l1 >= l^O, i.e. outside the PD box. */
 static double alpha_at(const orc_solver *s, const double *x) {
   if (s->p.mode == ORC_PURE_PD) return 0.0;
+  if (s->p.mode == ORC_PURE_FE) return 1.0;
   double l1 = 0.0;
   for (int a = 0; a < s->dim; a++) {
     double d = s->o2lo[a] - x[a];
@@ -320,13 +322,21 @@ static void btsig(const orc_solver *s, int g, const double *sig, double scale, d
 /* Internal force K_F u = sum_e sum_gp alpha B^T D B u detJ t  (Eq. 27, Eq. 34). */
 int orc_fe_force(orc_solver *s, const double *u, double *f) {
   int dim = s->dim;
-  memset(f, 0, sizeof(double) * (size_t)(s->nfe * dim));
-  double ue[24], fe[24], eps[6], sig[6];
+  int nd = s->nen * dim;
+  if (!s->febuf) {
+    s->febuf = xcalloc((size_t)(s->ne * nd), sizeof(double));
+    if (!s->febuf) return -1;
+  }
+  /* element forces are independent, so an OpenMP build computes them in
+   * parallel; the scatter below adds them in ascending element order either way */
+#pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < s->ne; e++) {
+    double ue[24], eps[6], sig[6];
+    double *fe = s->febuf + e * nd;
+    for (int t = 0; t < nd; t++) fe[t] = 0.0;
     if (!s->eact[e]) continue;
     for (int a = 0; a < s->nen; a++)
       for (int d = 0; d < dim; d++) ue[a * dim + d] = u[(int64_t)s->conn[e * s->nen + a] * dim + d];
-    for (int t = 0; t < s->nen * dim; t++) fe[t] = 0.0;
     for (int g = 0; g < s->ngp; g++) {
       double al = s->gpa[e * s->ngp + g];
       if (al == 0.0) continue;
@@ -337,6 +347,11 @@ int orc_fe_force(orc_solver *s, const double *u, double *f) {
       }
       btsig(s, g, sig, al * s->detJ * s->p.thickness, fe);
     }
+  }
+  memset(f, 0, sizeof(double) * (size_t)(s->nfe * dim));
+  for (int64_t e = 0; e < s->ne; e++) {
+    if (!s->eact[e]) continue;
+    const double *fe = s->febuf + e * nd;
     for (int a = 0; a < s->nen; a++)
       for (int d = 0; d < dim; d++) f[(int64_t)s->conn[e * s->nen + a] * dim + d] += fe[a * dim + d];
   }
@@ -560,6 +575,38 @@ static int build_fe(orc_solver *s) {
             }
           }
         }
+  }
+  /* Uniform traction (+x) on the face x = dom_hi, alpha-weighted as above: the
+   * end load of the beam of Sec. 3.2. */
+  if (p->traction_x != 0.0) {
+    double q = 1.0 / sqrt(3.0);
+    int64_t ex = nx - 1;
+    for (int64_t ez = 0; ez < (dim == 3 ? nz : 1); ez++)
+      for (int64_t ey = 0; ey < ny; ey++) {
+        int64_t e = (ez * ny + ey) * nx + ex;
+        if (!s->eact[e]) continue;
+        int ngp2 = dim == 2 ? 2 : 4;
+        for (int g = 0; g < ngp2; g++) {
+          double xi[3] = {1.0, (g & 1) ? q : -q, (g & 2) ? q : -q};
+          double xg[3] = {p->dom_hi[0], p->dom_lo[1] + (double)ey * h + (xi[1] + 1.0) * (h / 2.0),
+                          dim == 3 ? p->dom_lo[2] + (double)ez * h + (xi[2] + 1.0) * (h / 2.0) : 0.0};
+          double al = alpha_at(s, xg);
+          double jac = dim == 2 ? h / 2.0 : (h / 2.0) * (h / 2.0);
+          for (int a = 0; a < s->nen; a++) {
+            double Na = shape(dim, a, xi);
+            if (Na == 0.0) continue;
+            int64_t n = s->conn[e * s->nen + a];
+            s->PF[n * dim] += al * Na * p->traction_x * jac * p->thickness;
+          }
+        }
+      }
+  }
+  /* Clamped face x = dom_lo: every component held at zero (the beam's fixed
+   * end); with vel_bc = 0 a flagged dof keeps u = v = a = 0. */
+  if (p->clamp_x0) {
+    for (int64_t n = 0; n < s->nfe; n++)
+      if (s->nact[n] && fabs(s->xF[n * dim] - p->dom_lo[0]) < 1e-9 * h)
+        for (int d = 0; d < dim; d++) s->bc[n * dim + d] = 1;
   }
   /* Prescribed velocity on the face x = dom_lo (x component). */
   if (p->vel_bc != 0.0) {
@@ -827,7 +874,13 @@ static int build_y(orc_solver *s) {
 /* ------------------------------------------------------------------------- */
 orc_solver *orc_create(const orc_problem *p) {
   if (p->dim != 2 && p->dim != 3) { set_err("dim must be 2 or 3"); return NULL; }
-  if (p->n_pd <= 0 || !p->pos) { set_err("no PD nodes"); return NULL; }
+  if (p->mode != ORC_COUPLED && p->mode != ORC_PURE_PD && p->mode != ORC_PURE_FE) { set_err("bad mode"); return NULL; }
+  if (p->mode != ORC_PURE_FE && (p->n_pd <= 0 || !p->pos)) { set_err("no PD nodes"); return NULL; }
+  if (p->mode == ORC_PURE_PD && (p->traction_x != 0.0 || p->clamp_x0)) {
+    set_err("traction_x and clamp_x0 act on the FE mesh");
+    return NULL;
+  }
+  if (p->clamp_x0 && p->vel_bc != 0.0) { set_err("clamp_x0 needs vel_bc = 0"); return NULL; }
   if (p->m < 1) { set_err("m must be >= 1"); return NULL; }
   if (!(p->dx > 0.0) || !(p->horizon_factor >= 1.0)) { set_err("bad dx / horizon"); return NULL; }
   if (!(p->dt_pd > 0.0)) { set_err("dt_pd must be > 0"); return NULL; }
@@ -835,10 +888,10 @@ orc_solver *orc_create(const orc_problem *p) {
   if (!s) return NULL;
   s->p = *p;
   int dim = s->dim = p->dim;
-  int64_t N = s->N = p->n_pd;
+  int64_t N = s->N = p->mode == ORC_PURE_FE ? 0 : p->n_pd; /* the FE-only model has no PD nodes */
   s->x = xcalloc((size_t)(N * dim), sizeof(double));
   if (!s->x) { orc_destroy(s); return NULL; }
-  memcpy(s->x, p->pos, sizeof(double) * (size_t)(N * dim));
+  if (N) memcpy(s->x, p->pos, sizeof(double) * (size_t)(N * dim));
   s->nu = dim == 2 ? 1.0 / 3.0 : 0.25;
   s->delta = p->horizon_factor * p->dx;
   s->d2 = s->delta * s->delta;
@@ -914,7 +967,7 @@ orc_solver *orc_create(const orc_problem *p) {
     }
   } else {
     if (p->fe_n[0] < 1 || p->fe_n[1] < 1 || (dim == 3 && p->fe_n[2] < 1) || !(p->fe_h > 0.0)) {
-      set_err("coupled mode needs an FE mesh");
+      set_err("coupled and FE-only modes need an FE mesh");
       orc_destroy(s);
       return NULL;
     }
@@ -988,6 +1041,7 @@ void orc_destroy(orc_solver *s) {
   free(s->cn); free(s->cidx); free(s->cel); free(s->cw); free(s->H); free(s->L); free(s->lam0);
   free(s->region);
   free(s->LA);
+  free(s->febuf);
   free(s);
 }
 
@@ -997,7 +1051,9 @@ void orc_destroy(orc_solver *s) {
 static int macro_step(orc_solver *s) {
   int dim = s->dim, m = s->p.m;
   int64_t N = s->N;
-  int coupled = s->p.mode == ORC_COUPLED;
+  /* the FE-only model takes the coupled path with no constraints: the FE free
+   * step is then the whole step */
+  int coupled = s->p.mode != ORC_PURE_PD;
   int64_t nF = coupled ? s->nfe * dim : 1;
   int region_broke = 0;
   double *fP = xcalloc((size_t)(N * dim), sizeof(double));
@@ -1237,7 +1293,7 @@ int orc_info_get(orc_solver *s, orc_info *o) {
       w += s->PP[i * dim + d] * s->uP[i * dim + d];
     }
   o->e_pd = orc_pd_energy(s, s->uP);
-  if (s->p.mode == ORC_COUPLED) {
+  if (s->p.mode != ORC_PURE_PD) {
     double *f = xcalloc((size_t)(s->nfe * dim), sizeof(double));
     if (!f) return -1;
     orc_fe_force(s, s->uF, f);
@@ -1361,7 +1417,7 @@ double orc_dt_bound(orc_solver *s, int which) {
     }
     return best;
   }
-  if (s->p.mode != ORC_COUPLED) return INFINITY;
+  if (s->p.mode == ORC_PURE_PD) return INFINITY;
   int64_t n = s->nfe * dim;
   if (which == 2) {
     double *rowsum = xcalloc((size_t)n, sizeof(double));

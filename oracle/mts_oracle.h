@@ -16,7 +16,8 @@
 extern "C" {
 #endif
 
-enum { ORC_COUPLED = 0, ORC_PURE_PD = 1 };
+enum { ORC_COUPLED = 0, ORC_PURE_PD = 1,
+       ORC_PURE_FE = 2 /* the FE mesh alone with alpha = 1 (the undecomposed FE model of Sec. 3.2) */ };
 enum { ORC_W_CUBIC = 0, ORC_W_LINEAR = 1, ORC_W_CONSTANT = 2 };
 enum { ORC_K_PMB = 0, ORC_K_EXP = 1 };
 
@@ -37,6 +38,10 @@ typedef struct {
                                  for checks of large runs against the constraint set */
   double fe_beta;             /* Newmark beta of the FE step: 0 explicit, 1/4 average
                                  acceleration (implicit, gamma = 1/2 in both) */
+  double traction_x;          /* uniform traction (+x) on the FE face x = dom_hi: the end
+                                 load of the beam of Sec. 3.2 */
+  int32_t clamp_x0;           /* 1: every component of the FE nodes on x = dom_lo held at
+                                 zero (the beam's fixed end); needs vel_bc = 0 */
 } orc_problem;
 
 typedef struct {

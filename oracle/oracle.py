@@ -42,6 +42,8 @@ class _Problem(C.Structure):
         ("traction", C.c_double), ("vel_bc", C.c_double), ("dt_pd", C.c_double),
         ("setup_only", C.c_int32),
         ("fe_beta", C.c_double),
+        ("traction_x", C.c_double),
+        ("clamp_x0", C.c_int32),
     ]
 
 
@@ -125,6 +127,7 @@ def exp_moment(n, delta, l):
     return _L().orc_exp_moment(n, delta, l)
 
 
+_MODE = {"coupled": 0, "pure_pd": 1, "pure_fe": 2}
 _WEIGHT = {"cubic": 0, "linear": 1, "constant": 2}
 _KERNEL = {"pmb": 0, "exp": 1}
 
@@ -134,7 +137,7 @@ def make_problem(inst: dict, setup_only: bool = False):
     p = _Problem()
     dim = int(inst["dim"])
     p.dim = dim
-    p.mode = 1 if inst.get("mode", "coupled") == "pure_pd" else 0
+    p.mode = _MODE[inst.get("mode", "coupled")]
     p.breaking = 1 if inst.get("breaking", True) else 0
     p.weight_kind = _WEIGHT[inst.get("weight", "cubic")]
     p.kernel = _KERNEL[inst.get("kernel", "pmb")]
@@ -163,6 +166,8 @@ def make_problem(inst: dict, setup_only: bool = False):
     p.s_crit = float(inst.get("s_crit", 0.0))
     p.setup_only = 1 if setup_only else 0
     p.fe_beta = float(inst.get("fe_beta", 0.0))
+    p.traction_x = float(inst.get("traction_x", 0.0))
+    p.clamp_x0 = 1 if inst.get("clamp_x0", False) else 0
     return p, pos
 
 

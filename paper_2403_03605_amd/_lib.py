@@ -40,6 +40,8 @@ class Problem(C.Structure):
         ("s_crit", C.c_double), ("l_over_delta", C.c_double),
         ("traction", C.c_double), ("vel_bc", C.c_double), ("dt_pd", C.c_double),
         ("fe_beta", C.c_double),
+        ("traction_x", C.c_double),
+        ("clamp_x0", C.c_int32),
     ]
 
 
@@ -169,6 +171,8 @@ def make_problem(inst: dict):
     for k in ("E", "rho", "G0", "thickness", "l_over_delta", "traction", "vel_bc", "dt_pd", "fe_beta"):
         setattr(p, k, float(inst.get(k, 0.0)))
     p.s_crit = float(inst.get("s_crit", 0.0))
+    p.traction_x = float(inst.get("traction_x", 0.0))
+    p.clamp_x0 = 1 if inst.get("clamp_x0", False) else 0
     return p, pos
 
 

@@ -114,11 +114,12 @@ __global__ void k_fe_gp_alpha(Params P, MeshGeo G, int64_t ne, int ngp, double *
 // (element, local node) list is in ascending element order.
 __global__ void k_fe_node_setup(Params P, MeshGeo G, int64_t nfe, int nen, int ngp, const int32_t *n2e_ptr,
                                 const int32_t *n2e, const double *gpa, const uint8_t *eact, double T,
-                                double dom_hi_y, double thick, double *mF, double *PF, uint8_t *nact, const FeTables *tab) {
+                                double dom_hi_y, double Tx, double dom_hi_x, double thick, double *mF, double *PF,
+                                uint8_t *nact, const FeTables *tab) {
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nfe) return;
   int dim = P.dim;
-  double m = 0.0, py = 0.0;
+  double m = 0.0, py = 0.0, px = 0.0;
   int act = 0;
   double q = 1.0 / sqrt(3.0);
   for (int t = n2e_ptr[n]; t < n2e_ptr[n + 1]; t++) {
@@ -152,9 +153,30 @@ __global__ void k_fe_node_setup(Params P, MeshGeo G, int64_t nfe, int nen, int n
       }
     }
   }
+  // uniform traction (+x) on the face x = dom_hi: elements of the last column, face xi = +1
+  if (Tx != 0.0) {
+    for (int t = n2e_ptr[n]; t < n2e_ptr[n + 1]; t++) {
+      int64_t e = n2e[t] / nen;
+      int a = n2e[t] % nen;
+      if (!eact[e]) continue;
+      int64_t ex = e % G.ne[0], ey = (e / G.ne[0]) % G.ne[1], ez = e / (G.ne[0] * G.ne[1]);
+      if (ex != G.ne[0] - 1) continue;
+      int ngp2 = dim == 2 ? 2 : 4;
+      for (int g = 0; g < ngp2; g++) {
+        double xi[3] = {1.0, (g & 1) ? q : -q, (g & 2) ? q : -q};
+        double xg[3] = {dom_hi_x, G.lo[1] + (double)ey * G.h + (xi[1] + 1.0) * (G.h / 2.0),
+                        dim == 3 ? G.lo[2] + (double)ez * G.h + (xi[2] + 1.0) * (G.h / 2.0) : 0.0};
+        double al = alpha_fe(P, xg);
+        double jac = dim == 2 ? G.h / 2.0 : (G.h / 2.0) * (G.h / 2.0);
+        double Na = shape_fn(dim, a, xi);
+        if (Na == 0.0) continue;
+        px += al * Na * Tx * jac * thick;
+      }
+    }
+  }
   mF[n] = m;
   nact[n] = (uint8_t)act;
-  for (int d = 0; d < dim; d++) PF[n * dim + d] = (d == 1) ? py : 0.0;
+  for (int d = 0; d < dim; d++) PF[n * dim + d] = (d == 1) ? py : (d == 0) ? px : 0.0;
 }
 
 __global__ void k_fe_init(int64_t nfe, int dim, const uint8_t *nact, const uint8_t *bc, const double *PF,
@@ -254,6 +276,16 @@ void fe_setup(Solver &s) {
     for (int a = 0; a < nen; a++) n2e[fill[s.h_conn[e * nen + a]]++] = (int32_t)(e * nen + a);
   // prescribed x-velocity on the face x = dom_lo (grid column i = 0 and its slit copies)
   s.h_bc.assign((size_t)(nfe * dim), 0);
+  if (p.clamp_x0) {  // fixed face x = dom_lo: every component (vel_bc = 0, so flagged dofs stay at rest)
+    for (int64_t k = 0; k < gz; k++)
+      for (int64_t j = 0; j < gy; j++) {
+        int64_t g = (k * gy + j) * gx;
+        for (int d = 0; d < dim; d++) {
+          s.h_bc[g * dim + d] = 1;
+          if (dup[g] >= 0) s.h_bc[dup[g] * dim + d] = 1;
+        }
+      }
+  }
   if (p.vel_bc != 0.0) {
     for (int64_t k = 0; k < gz; k++)
       for (int64_t j = 0; j < gy; j++) {
@@ -309,7 +341,8 @@ void fe_setup(Solver &s) {
   k_fe_gp_alpha<<<nb(s.ne), 256, 0, st>>>(s.prm, G, s.ne, s.ngp, s.gpa, s.eact);
   MTS_LAUNCH_CHECK();
   k_fe_node_setup<<<nb(nfe), 256, 0, st>>>(s.prm, G, nfe, nen, s.ngp, s.n2e_ptr, s.n2e, s.gpa, s.eact, p.traction,
-                                           p.dom_hi[1], p.thickness, s.mF, s.PF, s.nact, tab);
+                                           p.dom_hi[1], p.traction_x, p.dom_hi[0], p.thickness, s.mF, s.PF, s.nact,
+                                           tab);
   MTS_LAUNCH_CHECK();
   k_fe_init<<<nb(nfe), 256, 0, st>>>(nfe, dim, s.nact, s.bc, s.PF, s.mF, p.vel_bc, s.vF, s.aF);
   MTS_LAUNCH_CHECK();

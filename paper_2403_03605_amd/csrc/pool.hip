@@ -391,6 +391,8 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
   if (p->dim != P->dim || p->precision != P->precision)
     return (set_error("request dim/precision differ from the pool's"), MTS_EINVAL);
   if (p->fe_beta != 0.0) return (set_error("the pool runs the explicit FE step only (fe_beta = 0)"), MTS_EINVAL);
+  if (p->traction_x != 0.0 || p->clamp_x0)
+    return (set_error("the pool serves y-face tractions and the x-velocity load only"), MTS_EINVAL);
   mts_plan_info plan{};
   const mts_status pst = mts_plan(p, &plan);
   if (pst != MTS_OK) return pst;

@@ -148,6 +148,11 @@ void validate(const mts_problem *p) {
     if (p->weight_kind < 0 || p->weight_kind > 2) throw ArgError{"unknown weight_kind"};
   }
   if (!(p->fe_beta == 0.0 || p->fe_beta == 0.25)) throw ArgError{"fe_beta must be 0 (explicit) or 1/4"};
+  if (!std::isfinite(p->traction_x)) throw ArgError{"non-finite traction_x"};
+  if (p->clamp_x0 != 0 && p->clamp_x0 != 1) throw ArgError{"clamp_x0 must be 0 or 1"};
+  if (p->mode != MTS_COUPLED && (p->traction_x != 0.0 || p->clamp_x0))
+    throw ArgError{"traction_x and clamp_x0 act on the FE mesh (coupled mode)"};
+  if (p->clamp_x0 && p->vel_bc != 0.0) throw ArgError{"clamp_x0 needs vel_bc = 0"};
   for (int64_t i = 0; i < p->n_pd * p->dim; i++)
     if (!std::isfinite(p->host_pd_pos[i])) throw ArgError{"non-finite node position"};
 }

@@ -88,6 +88,9 @@ def _create_status(inst):
 @pytest.mark.parametrize("bad", [
     dict(m=0), dict(dt_pd=0.0), dict(horizon_factor=0.5), dict(dim=1),
     dict(pos=np.zeros((0, 2))),                      # empty lattice
+    dict(fe_beta=0.5),                               # only explicit or average acceleration
+    dict(clamp_x0=True, vel_bc=1.0),                 # a clamped face moves with no velocity
+    dict(mode="pure_pd", traction_x=1e6),            # end traction acts on the FE mesh
 ])
 def test_create_rejects_bad_descriptions_before_device_use(bad):
     """Degenerate or inconsistent descriptions are rejected with MTS_EINVAL by

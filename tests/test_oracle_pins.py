@@ -962,6 +962,60 @@ def test_fe_edge_traction_and_slit(coupled_small):
     assert np.abs(f[line & (X[:, 0] > a + 0.5 * h)]).max() > 1e-3 * scale
 
 
+@pytest.fixture(scope="module")
+def beam_fe():
+    """The beam of Sec. 3.2 as the undecomposed FE model (the paper's reference),
+    coarse (dx = 0.25 m: 40 x 4 x 4 Hex8), run over one bar-wave round trip."""
+    inst = mi.beam3d(0.25, mode="pure_fe", dt_fe=5e-5, t_end=0.014)
+    return inst, Oracle(inst)
+
+
+def test_beam_end_traction_and_clamp(beam_fe):
+    """End load and fixed end of the beam (Sec. 3.2): a uniform traction on a
+    bilinear face gives node loads P h^2 x {1/4 corner, 1/2 edge, 1 interior}
+    summing to P times the face area, in +x only, on the face x = 10 m only;
+    the clamped face x = 0 keeps every component at zero."""
+    inst, o = beam_fe
+    X, P = o.get(O.FE_X), o.get(O.FE_P)
+    T, h = inst["traction_x"], inst["fe_h"]
+    end = X[:, 0] == inst["dom_hi"][0]
+    assert P[end, 0].sum() == pytest.approx(T * 1.0 * 1.0, rel=1e-14)
+    assert np.all(P[~end] == 0.0) and np.all(P[:, 1:] == 0.0)
+    on_edge = lambda c: (c == 0.0) | (c == 1.0)  # noqa: E731
+    k = on_edge(X[end, 1]).astype(int) + on_edge(X[end, 2]).astype(int)
+    assert np.allclose(P[end, 0] / (T * h * h), np.array([1.0, 0.5, 0.25])[k], rtol=1e-14)
+    assert o.info()["n_pd"] == 0 and o.info()["n_constraints"] == 0
+
+
+def test_beam_fe_only_bar_wave(beam_fe):
+    """A suddenly applied end load on a fixed-free bar: the end displacement
+    first peaks when the wave reflected at the fixed end returns, at t = 2L/c
+    with c = sqrt(E/rho), at twice the static value PL/E (the dynamic
+    overshoot of a step load, 1D wave theory); kinetic plus strain energy equals
+    the work of the constant load (the central-difference step conserves energy
+    to O(dt^2)).  3D Poisson coupling and the coarse mesh hold the peak a few
+    per cent under 2PL/E."""
+    inst, o = beam_fe
+    A = mi.beam_node_a(inst)
+    X = o.get(O.FE_X)
+    assert np.allclose(X[A], (10.0, 0.5, 0.5))
+    L, E, rho, T = 10.0, inst["E"], inst["rho"], inst["traction_x"]
+    dt = inst["m"] * inst["dt_pd"]
+    ua, bal = [], []
+    for k in range(inst["n_macro"]):
+        o.advance(1)
+        ua.append(o.get(O.FE_U)[A, 0])
+        if k % 20 == 19:
+            inf = o.info()
+            bal.append((inf["e_kin"] + inf["e_fe"] - inf["w_ext"]) / inf["w_ext"])
+    ua = np.array(ua)
+    assert abs(ua.max() / (2 * T * L / E) - 1.0) < 0.04
+    assert abs((np.argmax(ua) + 1) * dt / (2 * L / math.sqrt(E / rho)) - 1.0) < 0.03
+    assert np.abs(bal).max() < 5e-3
+    clamped = X[:, 0] == 0.0
+    assert np.all(o.get(O.FE_U)[clamped] == 0.0) and np.all(o.get(O.FE_V)[clamped] == 0.0)
+
+
 def test_openmp_build_identical():
     """The OpenMP build of the oracle (used only to time it on all host cores)
     gives bit-identical states: per-node sums, row-owned bond states."""
