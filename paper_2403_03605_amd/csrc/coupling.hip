@@ -116,29 +116,35 @@ __global__ void k_slice_layer(const int32_t *rows, int64_t n_rows, int64_t n_sli
 // row of the slice lies within k horizons of a loaded node (m if none).  A
 // response that has run j substeps is still exactly zero beyond j - 1 such
 // horizons, so the batch's link substeps skip those slices.
-__global__ void k_batch_layer(const double *x, int64_t N, int dim, const int32_t *rows, int64_t n_rows,
-                              int64_t n_slices, int L, const int32_t *nodes, int n_nodes, double delta, int m,
-                              int32_t *slice_layer) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(WAVE) void k_batch_layer(const double *x, int64_t N, int dim, const int32_t *rows,
+                                                       int64_t n_rows, int64_t n_slices, int L, const int32_t *nodes,
+                                                       int n_nodes, double delta, int m, int32_t *slice_layer) {
+  // one wavefront per slice: the lanes split the (row, loaded node) pairs and
+  // the smallest squared distance is combined across the wavefront (min is exact)
+  const int64_t s = blockIdx.x;
   if (s >= n_slices) return;
+  const int lane = (int)threadIdx.x;
   const int S = WAVE / L;
+  const int nr = (int)std::min<int64_t>(S, n_rows - s * S);
   double best = 1e300;
-  for (int j = 0; j < S; j++) {
-    const int64_t r = s * S + j;
-    if (r >= n_rows) break;
-    const int64_t i = rows[r];
-    for (int q = 0; q < n_nodes; q++) {
-      const int64_t c = nodes[q];
-      const double d0 = x[i] - x[c];
-      const double d1 = x[N + i] - x[N + c];
-      double r2 = d0 * d0 + d1 * d1;
-      if (dim == 3) {
-        const double d2 = x[2 * N + i] - x[2 * N + c];
-        r2 = r2 + d2 * d2;
-      }
-      best = r2 < best ? r2 : best;
+  for (int e = lane; e < nr * n_nodes; e += WAVE) {
+    const int64_t i = rows[s * S + e / n_nodes];
+    const int64_t c = nodes[e % n_nodes];
+    const double d0 = x[i] - x[c];
+    const double d1 = x[N + i] - x[N + c];
+    double r2 = d0 * d0 + d1 * d1;
+    if (dim == 3) {
+      const double d2 = x[2 * N + i] - x[2 * N + c];
+      r2 = r2 + d2 * d2;
     }
+    best = r2 < best ? r2 : best;
   }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const double t = __shfl_xor(best, o, WAVE);
+    best = t < best ? t : best;
+  }
+  if (lane != 0) return;
   int h = m;
   for (int k = m - 1; k >= 0; k--) {
     const double hk = (double)k * delta;
@@ -510,7 +516,7 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     const int32_t *rc = &rcd[bt * 32], *rd = &rcd[bt * 32 + 16];
     if (s.rsell.n_slices) {
       const int32_t b0 = s.h_batch_off[bt], nbn = s.h_batch_off[bt + 1] - b0;
-      k_batch_layer<<<nb(s.rsell.n_slices), 256, 0, st>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
+      k_batch_layer<<<(unsigned)s.rsell.n_slices, WAVE, 0, st>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
                                                          s.rsell.n_slices, s.rsell.L, s.batch_nodes + b0, nbn,
                                                          s.prm.delta, s.m, s.batch_layer);
       MTS_LAUNCH_CHECK();
