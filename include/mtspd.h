@@ -105,6 +105,10 @@ typedef struct mts_info {
   double slot_bytes;     /* bytes of slot record the bond pass reads per bond slot: 12 (FP64
                             coefficient and neighbour offset), 8 (mixed), 6 (mixed with
                             neighbour records staged in LDS: two slots per 12-byte record) */
+  int64_t n_rebuild_columns; /* unit-load columns (constraint nodes) recomputed by the rebuilds
+                                after setup: a rebuild recomputes only the constraints whose
+                                response support holds a node with a changed bond (Algorithm 1,
+                                update of Y); the others are unchanged bit for bit */
 } mts_info;
 
 /* Energies of the current state (J, per unit thickness in 2D) and the bonds

@@ -54,7 +54,7 @@ class Info(C.Structure):
         ("pd_steps", C.c_int64), ("macro_steps", C.c_int64), ("n_rebuilds", C.c_int64), ("n_colors", C.c_int64),
         ("device_bytes", C.c_int64), ("dim", C.c_int32), ("precision", C.c_int32),
         ("dt_bound_pd", C.c_double), ("inverse_bytes", C.c_int64),
-        ("slot_bytes", C.c_double),
+        ("slot_bytes", C.c_double), ("n_rebuild_columns", C.c_int64),
     ]
 
 

@@ -13,6 +13,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <unordered_map>
 
@@ -166,8 +167,10 @@ __global__ void k_set_cidx(const int32_t *cn, int64_t nc, int32_t *cidx) {
 // H[(q, d'), (p, dir)] = velocity d' of RHS b at node q (responses node-major,
 // [N][nrhs][dim]) for the loaded constraint p of RHS b that owns q (the only
 // loaded node whose response can reach q).
+// csel (or nullptr for all): only the columns of the constraints this rebuild loaded.
 __global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32_t *cn, const int32_t *owner,
-                          const int32_t *rhs_color, const int32_t *rhs_dir, const double *Wv, double *H) {
+                          const int32_t *rhs_color, const int32_t *rhs_dir, const double *Wv, const uint8_t *csel,
+                          double *H) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
   int64_t node = cn[q];
@@ -175,7 +178,7 @@ __global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32
     int c = rhs_color[b];
     if (c < 0) continue;
     int32_t p = owner[(int64_t)c * nc + q];
-    if (p < 0) continue;
+    if (p < 0 || (csel && !csel[p])) continue;
     for (int d = 0; d < dim; d++)
       H[(q * dim + d) * nl + (int64_t)p * dim + rhs_dir[b]] = Wv[(node * nrhs + b) * dim + d];
   }
@@ -184,10 +187,10 @@ __global__ void k_extract(int64_t nc, int dim, int64_t nl, int nrhs, const int32
 // + 1/2 dt_FE G_F M_F^-1 G_F^T (prescribed-velocity dofs do not respond).
 __global__ void k_add_hf(int64_t nc, int dim, int nen, int64_t nl, const int32_t *cel, const int32_t *conn,
                          const double *cw, const double *mF, const uint8_t *bc, double hdtF, int64_t ne0,
-                         int64_t ne1, double *H) {
+                         int64_t ne1, const uint8_t *csel, double *H) {
   int64_t pq = (int64_t)blockIdx.y * blockDim.y + threadIdx.y;
   int64_t qq = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pq >= nc || qq >= nc) return;
+  if (pq >= nc || qq >= nc || (csel && !csel[qq])) return;
   int64_t ep = cel[pq], eq = cel[qq];
   int64_t dx = ep % ne0 - eq % ne0, dy = (ep / ne0) % ne1 - (eq / ne0) % ne1, dz = ep / (ne0 * ne1) - eq / (ne0 * ne1);
   if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return;
@@ -204,10 +207,35 @@ __global__ void k_add_hf(int64_t nc, int dim, int nen, int64_t nl, const int32_t
   for (int d = 0; d < dim; d++) H[(pq * dim + d) * nl + qq * dim + d] += hdtF * acc[d];
 }
 
-// H += HF (the implicit FE block, computed once)
-__global__ void k_add_dense(int64_t n, const double *HF, double *H) {
+// H += HF (the implicit FE block, computed once); csel: only those columns
+__global__ void k_add_dense(int64_t n, int64_t nl, int dim, const uint8_t *csel, const double *HF, double *H) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) H[i] = H[i] + HF[i];
+  if (i < n && (!csel || csel[(i % nl) / dim])) H[i] = H[i] + HF[i];
+}
+
+// Columns of the constraints in csel set to zero (before they are recomputed).
+__global__ void k_zero_cols(int64_t nl, int dim, const uint8_t *csel, double *H) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nl * nl && csel[(i % nl) / dim]) H[i] = 0.0;
+}
+
+// Nodes whose row of the full layout holds a bond whose state differs between
+// two masks (one wavefront per slice; bit j * L + l of a word belongs to row j).
+__global__ __launch_bounds__(WAVE) void k_dirty_nodes(const int64_t *word_off, int64_t n_slices, const int32_t *rows,
+                                                      int64_t n_rows, int L, const uint64_t *a, const uint64_t *b,
+                                                      uint8_t *dirty) {
+  const int64_t s = blockIdx.x;
+  if (s >= n_slices) return;
+  const int S = WAVE / L;
+  for (int64_t w = word_off[s] + threadIdx.x; w < word_off[s + 1]; w += WAVE) {
+    uint64_t d = a[w] ^ b[w];
+    while (d) {
+      const int bit = __builtin_ctzll(d);
+      d &= d - 1;
+      const int64_t r = s * S + bit / L;
+      if (r < n_rows) dirty[rows[r]] = 1;
+    }
+  }
 }
 
 // r = G_F v~_F - G_P V_m  (right-hand side of Eq. 49, from Eq. 41)
@@ -404,6 +432,20 @@ void coupling_setup(Solver &s) {
       boff[bt + 1] = (int32_t)bnodes.size();
     }
     s.h_batch_off = boff;
+    // constraints by cell of the response reach, to find those near a changed bond
+    s.h_ccolor = color;
+    s.own_r = own;
+    s.h_ccells.clear();
+    for (int64_t q = 0; q < s.nc; q++) {
+      int64_t c[3] = {0, 0, 0};
+      for (int a = 0; a < dim; a++) c[a] = (int64_t)std::floor(s.pos[(int64_t)s.h_cn[q] * dim + a] / own);
+      s.h_ccells[(c[2] * 1000003LL + c[1]) * 1000003LL + c[0]].push_back((int32_t)q);
+    }
+    s.built_mask = ar.alloc<uint64_t>(std::max<int64_t>(s.sell.n_words, 1));
+    s.dirty = ar.alloc<uint8_t>(N);
+    s.ccolor_sub = ar.alloc<int32_t>(std::max<int64_t>(s.nc, 1));
+    s.csel = ar.alloc<uint8_t>(std::max<int64_t>(s.nc, 1));
+    s.built_valid = false;
     s.batch_nodes = ar.alloc<int32_t>(std::max<size_t>(bnodes.size(), 1));
     if (!bnodes.empty())
       MTS_HIP(hipMemcpyAsync(s.batch_nodes, bnodes.data(), sizeof(int32_t) * bnodes.size(), hipMemcpyHostToDevice, st));
@@ -494,53 +536,141 @@ void coupling_setup(Solver &s) {
 }
 
 // Unit-load responses on the given bond states (full-lattice layout), H, and its inverse.
+// After the first build a rebuild recomputes only the columns of the
+// constraints whose response reach holds a node with a bond changed since the
+// last build: every other column would come out bit for bit the same (its
+// link run sees the same bond states, and the loads of one colour never reach
+// a common node), so H, and its inverse, equal those of a full rebuild.
 void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   const int dim = s.dim;
   hipStream_t st = s.stream;
   const int64_t nl = s.nl;
   sell_regather_mask(s, s.rsell, full_mask);
-  MTS_HIP(hipMemsetAsync(s.H, 0, sizeof(double) * nl * nl, st));
   const int cpb = s.nrhs / dim;  // colours per batch
-  const int64_t nbatch = (s.n_colors + cpb - 1) / cpb;
-  // colour and direction of every RHS of every batch, copied once
+  const bool first = !s.built_valid;
+  bool all = first || !s.incremental;
+  std::vector<int32_t> sel;  // constraints to recompute when not all
+  if (!all) {
+    MTS_HIP(hipMemsetAsync(s.dirty, 0, (size_t)s.N, st));
+    if (s.sell.n_slices) {
+      k_dirty_nodes<<<(unsigned)s.sell.n_slices, WAVE, 0, st>>>(s.sell.word_off, s.sell.n_slices, s.sell.rows,
+                                                                s.sell.n_rows, s.sell.L, s.built_mask, full_mask,
+                                                                s.dirty);
+      MTS_LAUNCH_CHECK();
+    }
+    std::vector<uint8_t> dirty((size_t)s.N);
+    MTS_HIP(hipMemcpyAsync(dirty.data(), s.dirty, (size_t)s.N, hipMemcpyDeviceToHost, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    std::vector<uint8_t> mark((size_t)s.nc, 0);
+    const double r2max = s.own_r * s.own_r;
+    const int zr = dim == 3 ? 1 : 0;
+    for (int64_t i = 0; i < s.N; i++) {
+      if (!dirty[i]) continue;
+      const double *xi = &s.pos[(size_t)i * dim];
+      int64_t c[3] = {0, 0, 0};
+      for (int a = 0; a < dim; a++) c[a] = (int64_t)std::floor(xi[a] / s.own_r);
+      for (int dz = -zr; dz <= zr; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+          for (int dxx = -1; dxx <= 1; dxx++) {
+            auto it = s.h_ccells.find(((c[2] + dz) * 1000003LL + (c[1] + dy)) * 1000003LL + (c[0] + dxx));
+            if (it == s.h_ccells.end()) continue;
+            for (int32_t q : it->second) {
+              if (mark[q]) continue;
+              double r2 = 0.0;
+              for (int a = 0; a < dim; a++) {
+                const double t = s.pos[(size_t)s.h_cn[q] * dim + a] - xi[a];
+                r2 += t * t;
+              }
+              if (r2 <= r2max) mark[q] = 1;
+            }
+          }
+    }
+    for (int64_t q = 0; q < s.nc; q++)
+      if (mark[q]) sel.push_back((int32_t)q);
+    if ((int64_t)sel.size() == s.nc) all = true;
+  }
+  // batches of cpb colours: their RHS (colour, direction) and loaded PD nodes
+  std::vector<int32_t> bcol, boff{0}, bnodes;
+  if (all) {
+    for (int64_t c = 0; c < s.n_colors; c++) bcol.push_back((int32_t)c);
+  } else {
+    std::map<int32_t, std::vector<int32_t>> members;  // colour -> loaded PD nodes
+    for (int32_t q : sel) members[s.h_ccolor[q]].push_back(s.h_cn[q]);
+    for (auto &kv : members) bcol.push_back(kv.first);
+    int64_t k = 0;
+    for (auto &kv : members) {
+      bnodes.insert(bnodes.end(), kv.second.begin(), kv.second.end());
+      if (++k % cpb == 0 || k == (int64_t)members.size()) boff.push_back((int32_t)bnodes.size());
+    }
+  }
+  const int64_t nbatch = ((int64_t)bcol.size() + cpb - 1) / cpb;
   std::vector<int32_t> rcd((size_t)std::max<int64_t>(nbatch, 1) * 32, -1);
   for (int64_t bt = 0; bt < nbatch; bt++)
     for (int b = 0; b < s.nrhs; b++) {
       const int64_t c = bt * cpb + b / dim;
-      rcd[bt * 32 + b] = c < s.n_colors ? (int32_t)c : -1;
+      rcd[bt * 32 + b] = c < (int64_t)bcol.size() ? bcol[c] : -1;
       rcd[bt * 32 + 16 + b] = b % dim;
     }
   int32_t *drcd = s.arena.alloc<int32_t>(rcd.size());
   MTS_HIP(hipMemcpyAsync(drcd, rcd.data(), sizeof(int32_t) * rcd.size(), hipMemcpyHostToDevice, st));
+  int32_t *dnodes = nullptr;
+  const int32_t *load_color = s.ccolor;
+  const uint8_t *csel = nullptr;
+  if (all) {
+    MTS_HIP(hipMemsetAsync(s.H, 0, sizeof(double) * nl * nl, st));
+  } else {
+    std::vector<int32_t> sub((size_t)s.nc, -1);
+    std::vector<uint8_t> cs((size_t)s.nc, 0);
+    for (int32_t q : sel) {
+      sub[q] = s.h_ccolor[q];
+      cs[q] = 1;
+    }
+    MTS_HIP(hipMemcpyAsync(s.ccolor_sub, sub.data(), sizeof(int32_t) * s.nc, hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemcpyAsync(s.csel, cs.data(), (size_t)s.nc, hipMemcpyHostToDevice, st));
+    dnodes = s.arena.alloc<int32_t>(std::max<size_t>(bnodes.size(), 1));
+    if (!bnodes.empty())
+      MTS_HIP(hipMemcpyAsync(dnodes, bnodes.data(), sizeof(int32_t) * bnodes.size(), hipMemcpyHostToDevice, st));
+    load_color = s.ccolor_sub;
+    csel = s.csel;
+    k_zero_cols<<<nb(nl * nl), 256, 0, st>>>(nl, dim, csel, s.H);
+    MTS_LAUNCH_CHECK();
+  }
   for (int64_t bt = 0; bt < nbatch; bt++) {
     const int32_t *rc = &rcd[bt * 32], *rd = &rcd[bt * 32 + 16];
     if (s.rsell.n_slices) {
-      const int32_t b0 = s.h_batch_off[bt], nbn = s.h_batch_off[bt + 1] - b0;
+      const int32_t *bn = all ? s.batch_nodes + s.h_batch_off[bt] : dnodes + boff[bt];
+      const int32_t nbn = all ? s.h_batch_off[bt + 1] - s.h_batch_off[bt] : boff[bt + 1] - boff[bt];
       k_batch_layer<<<(unsigned)s.rsell.n_slices, WAVE, 0, st>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
-                                                         s.rsell.n_slices, s.rsell.L, s.batch_nodes + b0, nbn,
-                                                         s.prm.delta, s.m, s.batch_layer);
+                                                                 s.rsell.n_slices, s.rsell.L, bn, nbn, s.prm.delta,
+                                                                 s.m, s.batch_layer);
       MTS_LAUNCH_CHECK();
     }
     int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
     for (int j = 1; j <= s.m; j++) {
-      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, s.ccolor, rc, rd, s.nrhs, s.batch_layer);
+      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, load_color, rc, rd, s.nrhs, s.batch_layer);
       k ^= 1;
     }
     k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drcd + bt * 32, drcd + bt * 32 + 16,
-                                        s.Wv, s.H);
+                                        s.Wv, csel, s.H);
     MTS_LAUNCH_CHECK();
   }
-  MTS_HIP(hipStreamSynchronize(st));  // before the host colour table goes away
-  s.arena.release(drcd);
   if (s.fe_beta > 0.0) {
-    k_add_dense<<<nb(nl * nl), 256, 0, st>>>(nl * nl, s.fe_HF, s.H);
+    k_add_dense<<<nb(nl * nl), 256, 0, st>>>(nl * nl, nl, dim, csel, s.fe_HF, s.H);
   } else {
     dim3 blk(16, 16), grd((unsigned)((s.nc + 15) / 16), (unsigned)((s.nc + 15) / 16));
     k_add_hf<<<grd, blk, 0, st>>>(s.nc, dim, s.nen, nl, s.cel, s.conn, s.cw, s.mF, s.bc, s.prm.hdtF, s.p.fe_n[0],
-                                  s.p.fe_n[1], s.H);
+                                  s.p.fe_n[1], csel, s.H);
   }
   MTS_LAUNCH_CHECK();
-  vlog(s, "coupling: unit-load responses done (%lld colour batches)", (long long)((s.n_colors + cpb - 1) / cpb));
+  MTS_HIP(hipMemcpyAsync(s.built_mask, full_mask, sizeof(uint64_t) * s.sell.n_words, hipMemcpyDeviceToDevice, st));
+  MTS_HIP(hipStreamSynchronize(st));  // before the host tables go away
+  s.arena.release(drcd);
+  if (dnodes) s.arena.release(dnodes);
+  s.built_valid = true;
+  const int64_t ncols = all ? s.nc : (int64_t)sel.size();
+  if (!first) s.n_rebuild_cols += ncols;
+  vlog(s, "coupling: unit-load responses of %lld of %lld constraints done (%lld colour batches)", (long long)ncols,
+       (long long)s.nc, (long long)nbatch);
   if (s.keep_h) {
     if (!s.Hcopy) s.Hcopy = s.arena.alloc<double>((size_t)nl * nl);
     MTS_HIP(hipMemcpyAsync(s.Hcopy, s.H, sizeof(double) * nl * nl, hipMemcpyDeviceToDevice, st));

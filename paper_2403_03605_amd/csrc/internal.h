@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <string>
 #include <map>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mtspd.h"
@@ -263,6 +264,18 @@ struct Solver {
   std::vector<int32_t> h_batch_off;  // per batch of unit loads: range of batch_nodes
   int32_t *batch_nodes = nullptr;    // PD node ids of the constraints loaded by each batch
   int32_t *batch_layer = nullptr;    // per link-region slice: layer w.r.t. the current batch's loads
+  // rebuilds recompute only the columns whose response support holds a node
+  // with a bond changed since the last build (the rest are unchanged bit for bit)
+  bool incremental = true;
+  uint64_t *built_mask = nullptr;    // full-lattice bond states of the last build
+  bool built_valid = false;
+  uint8_t *dirty = nullptr;          // per PD node: a bond of its row changed since the last build
+  int32_t *ccolor_sub = nullptr;     // colour of each recomputed constraint, -1 for the others
+  uint8_t *csel = nullptr;           // per constraint: recomputed by this rebuild
+  std::vector<int32_t> h_ccolor;     // host copy of the colours
+  std::unordered_map<int64_t, std::vector<int32_t>> h_ccells;  // constraints by cell of size own_r
+  double own_r = 0.0;                // reach of a response (with half a horizon of slack)
+  int64_t n_rebuild_cols = 0;
   int nrhs = 8;
   bool keep_h = false;
   double *Hcopy = nullptr;       // H before inversion (kept when small, for inspection)

@@ -231,6 +231,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   if (const char *t = std::getenv("MTS_HALO_WAVES")) s->halo_waves = std::atoi(t) == 8 ? 8 : 4;  // tuning
   if (const char *t = std::getenv("MTS_SUBCYCLE")) s->subcycle = std::atoi(t) != 0;  // one launch per macro step
   if (const char *t = std::getenv("MTS_INV_DROP")) s->sym.prune = std::atoi(t) != 0;  // tests: read every tile
+  if (const char *t = std::getenv("MTS_FULL_REBUILD")) s->incremental = std::atoi(t) == 0;  // tests: every column
   if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
@@ -558,6 +559,7 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
       bytes += 4 * rhs * d * p->n_pd * 8 + 2 * 2 * d * p->n_pd * 8;  // link responses, final-update records
       bytes += slots * 40;                            // link region layout (at most every slot)
       bytes += ne * 8 * 8 * 8 + nfe * 8 * 24 + nc * 64 * 8;  // FE mesh and state, coupling tables
+      bytes += slots / 8 + p->n_pd + nc * 8;          // last build's bond states, changed-node and column flags
     }
     bytes += bytes / 8;
     out->device_bytes_estimate = bytes;
@@ -872,6 +874,7 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->pd_steps = s.pd_steps;
   o->macro_steps = s.macro_steps;
   o->n_rebuilds = s.n_rebuilds;
+  o->n_rebuild_columns = s.n_rebuild_cols;
   o->n_colors = s.n_colors;
   o->device_bytes = (int64_t)s.arena.live;
   o->dim = s.dim;
