@@ -95,31 +95,49 @@ __global__ __launch_bounds__(256) void k_tile_inverse(const double *packed, int6
     }
     for (int e = t; e < TS * SB; e += blockDim.x) Vs[e / SB][e % SB] = M[e / SB][o + e % SB];
     __syncthreads();
-    for (int e = t; e < TS * SB; e += blockDim.x) {
-      const int i = e / SB, kk = e % SB;
-      double w = 0.0;
+    {
+      // panel W = V B^-1 (64 x 16), one 16 x 16 output tile per wavefront
+      const int lane = t & (WAVE - 1), w = t >> 6;
+      const int lr = lane & 15, lk = lane >> 4;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < SB; q++) w += Vs[i][q] * Bi[q][kk];
-      Ws[i][kk] = w;
+      for (int k4 = 0; k4 < SB; k4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * w + lr][k4 + lk], Bi[k4 + lk][lr], acc, 0, 0, 0);
+#pragma unroll
+      for (int g = 0; g < 4; g++) Ws[16 * w + 4 * g + lk][lr] = acc[g];
     }
     __syncthreads();
+    // rank-16 update A_IJ - A_IK P A_KJ = M - V W^T on the matrix cores: each
+    // lane owns the 16 entries of the 16 x 16 output layout (rows 16 w + 4 g + lk,
+    // columns 16 t + lr), so the update is in place
+    {
+      const int lane = t & (WAVE - 1), w = t >> 6;
+      const int lr = lane & 15, lk = lane >> 4;
+      d4 acc[4];
 #pragma unroll
-    for (int a = 0; a < 4; a++)
+      for (int tt = 0; tt < 4; tt++)
 #pragma unroll
-      for (int bb = 0; bb < 4; bb++) {
-        const int r = r0 + a, c = c0 + bb;
-        const bool rin = r >= o && r < o + SB, cin = c >= o && c < o + SB;
-        double v;
-        if (rin && cin) v = -Bi[r - o][c - o];  // A_KK <- -P
-        else if (cin) v = Ws[r][c - o];         // A_IK <- A_IK P
-        else if (rin) v = Ws[c][r - o];         // A_KJ <- P A_KJ = (A_JK P)^T
-        else {
-          v = M[r][c];
+        for (int g = 0; g < 4; g++) acc[tt][g] = M[16 * w + 4 * g + lk][16 * tt + lr];
 #pragma unroll
-          for (int q = 0; q < SB; q++) v -= Vs[r][q] * Ws[c][q];  // A_IJ - A_IK P A_KJ
-        }
-        M[r][c] = v;
+      for (int k4 = 0; k4 < SB; k4 += 4) {
+        const double a = -Vs[16 * w + lr][k4 + lk];
+#pragma unroll
+        for (int tt = 0; tt < 4; tt++)
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Ws[16 * tt + lr][k4 + lk], acc[tt], 0, 0, 0);
       }
+#pragma unroll
+      for (int tt = 0; tt < 4; tt++)
+#pragma unroll
+        for (int g = 0; g < 4; g++) {
+          const int r = 16 * w + 4 * g + lk, c = 16 * tt + lr;
+          const bool rin = r >= o && r < o + SB, cin = c >= o && c < o + SB;
+          double v = acc[tt][g];
+          if (rin && cin) v = -Bi[r - o][c - o];  // A_KK <- -P
+          else if (cin) v = Ws[r][c - o];         // A_IK <- A_IK P
+          else if (rin) v = Ws[c][r - o];         // A_KJ <- P A_KJ = (A_JK P)^T
+          M[r][c] = v;
+        }
+    }
     __syncthreads();
   }
   // the sweep left -A^-1; P is its negated symmetric part (symmetric P keeps
