@@ -18,6 +18,8 @@ setup timed separately).  The same JSON line carries:
 - the bond pass's roofline (HBM bound) on two byte models and the counter
   traffic;
 - the crack-branching plate of the paper's Sec. 4.1, MTS against pure PD;
+- the per-step times of the efficiency study's plate (Table 2, the cases that
+  run the PD step explicitly), split as the paper splits them;
 - the oracle's rate on the host's cores (one thread and all threads).
 
 Prints one JSON line.
@@ -343,6 +345,54 @@ def branching_run(mts, torch, log):
     return out
 
 
+# the paper's Table 2 cases that run explicit PD (cases 1 and 2 are implicit PD)
+TABLE2_CASES = [(3, 5e-4, 0.2, 2), (4, 5e-4, 0.1, 2), (5, 5e-4, 0.1, 5), (6, 2.5e-4, 1.0, 1), (7, 2.5e-4, 0.1, 10)]
+TABLE2_PAPER_MS = {3: (95.9, 44.7), 4: (86.9, 41.0), 5: (208.7, 39.2), 6: (253.0, 253.0), 7: (552.9, 50.6)}
+
+
+def table2_run(mts, torch, log, pd_steps=400):
+    """The efficiency study's mode-I plate (Table 2) in the cases that run the
+    PD step explicitly: per FE step and per PD step, wall time of pd_steps PD
+    steps from a resident state, and the split into PD substeps (the paper's
+    t^U), FE step (t^K) and multipliers with the final update (t^lambda) from
+    a second, event-timed pass."""
+    import mts_inputs as mi
+    out = []
+    for case, dx, frac, m in TABLE2_CASES:
+        inst = mi.efficiency2d(dx, pd_frac=frac, m=m, n_macro=pd_steps // m)
+        s = mts.Solver(inst)
+        s.advance(max(2, 20 // m))
+        s.sync()
+        k = pd_steps // m
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(k)
+        s.sync()
+        wall = (time.perf_counter() - t0) * 1e3 / k
+        s.profile(True)
+        s.advance(k)
+        s.sync()
+        ph = {}
+        for name, kt in (("pd_substeps", mts.KT_PD_SUBSTEP), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA),
+                         ("link", mts.KT_LINK)):
+            n, ms = s.kernel_time(kt)
+            ph[name] = ms / k
+        s.profile(False)
+        info = s.query()
+        paper = TABLE2_PAPER_MS[case]
+        rec = {"case": case, "workload": inst["name"], "dx_mm": dx * 1e3, "pd_area": frac, "m": m,
+               "pd_nodes": info["n_pd"], "bonds": info["nnz"], "fe_beta": inst["fe_beta"],
+               "ms_per_fe_step": wall, "ms_per_pd_step": wall / m,
+               "phases_ms_per_fe_step": {"t_U_pd_substeps": ph["pd_substeps"], "t_K_fe": ph["fe"],
+                                         "t_lambda_multipliers_and_update": ph["lambda"] + ph["link"]},
+               "paper_ms_per_fe_step": paper[0], "paper_ms_per_pd_step": paper[1]}
+        out.append(rec)
+        log(f"table 2 case {case}: {wall:.3f} ms per FE step ({wall / m:.4f} per PD step)")
+        s.close()
+    return {"cases": out, "paper": "Table 2 per-step times, RTX 3070, PeriFEM with an assembled stiffness "
+                                   "(context, another discretisation and machine)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +409,7 @@ def main():
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream in the default line")
     ap.add_argument("--no-branching", action="store_true", help="skip the crack-branching comparison")
+    ap.add_argument("--no-table2", action="store_true", help="skip the efficiency study's per-step times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="per oracle build (one thread, all threads)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing pass")
@@ -444,6 +495,13 @@ def main():
         except Exception as e:  # reported, not fatal to the line
             branching = {"error": repr(e)}
 
+    table2 = None
+    if not args.no_table2:
+        try:
+            table2 = table2_run(mts, torch, log)
+        except Exception as e:  # reported, not fatal to the line
+            table2 = {"error": repr(e)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, args.cpu_seconds)
@@ -463,6 +521,7 @@ def main():
         "companion": companion,
         "serving": serving,
         "branching": branching,
+        "table2": table2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

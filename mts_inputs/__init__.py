@@ -203,6 +203,46 @@ def branching2d(nx: int = 400, mode: str = "coupled", *, m: int = 10, t_end: flo
     return inst
 
 
+def efficiency2d(dx: float = 5e-4, *, pd_frac: float = 0.1, m: int = 2, fe_beta: float = 0.25,
+                 n_macro: int = 100, precision: str = "fp64", perturb: float = 0.0,
+                 seed: int = SEED_BASE + 6, name: Optional[str] = None) -> Dict:
+    """The mode-I plate of the paper's efficiency study (Sec. 3.3, Table 2),
+    turned by 90 degrees so that the notch is horizontal: a 40 x 100 mm plate
+    (x by y) with a 10 mm edge notch along y = 50 mm from x = 0, 16 MPa on the
+    faces y = 0 and y = 100 mm, E = 72 GPa, rho = 2235 kg/m^3, G0 = 204 J/m^2,
+    exponential micromodulus with l = delta / 10, PD step 5e-9 s.  pd_frac:
+    0.1 (a 20 x 20 mm PD box at the notch), 0.2 (a 40 x 20 mm strip across the
+    plate) or 1.0 (pure PD over the plate, the traction as a body force within
+    delta of the loaded faces).  Q4 elements of 4 dx, implicit FE step by
+    default (the paper's choice for this study)."""
+    W, H = 0.04, 0.1
+    pure = pd_frac >= 1.0
+    if pure:
+        pd_lo, pd_hi = (0.0, 0.0), (W, H)
+    elif abs(pd_frac - 0.2) < 1e-9:
+        pd_lo, pd_hi = (0.0, 0.04), (W, 0.06)
+    elif abs(pd_frac - 0.1) < 1e-9:
+        pd_lo, pd_hi = (0.0, 0.04), (0.02, 0.06)
+    else:
+        raise ValueError(pd_frac)
+    n = (int(round((pd_hi[0] - pd_lo[0]) / dx)), int(round((pd_hi[1] - pd_lo[1]) / dx)))
+    fe_h = 4.0 * dx
+    inst = dict(
+        name=name or (f"efficiency plate {n[0]}x{n[1]} pure PD {precision}" if pure else
+                      f"efficiency plate PD {int(round(100 * pd_frac))}% m={m} {precision}"),
+        dim=2, mode="pure_pd" if pure else "coupled", precision=precision, breaking=True,
+        pd_n=(n[0], n[1], 1), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.015,
+        perturb=perturb, seed=seed, dom_lo=pd_lo if pure else (0.0, 0.0), dom_hi=pd_hi if pure else (W, H),
+        fe_n=(0, 0, 0) if pure else (int(round(W / fe_h)), int(round(H / fe_h)), 1), fe_h=fe_h,
+        overlap=3.0 * dx, weight="cubic", cracks=[(0.05, 0.0, 0.01)],
+        thickness=1.0, kernel="exp", l_over_delta=0.1, traction=16e6, vel_bc=0.0,
+        fe_beta=0.0 if pure else fe_beta, m=1 if pure else m, dt_pd=5e-9, n_macro=n_macro,
+        E=72e9, rho=2235.0, G0=204.0,
+    )
+    inst["pos"] = lattice_positions(n, pd_lo, dx, perturb, seed)
+    return inst
+
+
 # Elastic beam of the paper's error study (Sec. 3.2): E = 6.5 GPa, rho = 2235,
 # no breaking (the critical stretch is nominal).
 BEAM = dict(E=6.5e9, rho=2235.0, G0=0.0, s_crit=1.0)

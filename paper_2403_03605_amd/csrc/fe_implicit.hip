@@ -310,6 +310,144 @@ __global__ void k_hf_extract(int64_t nc, int dim, int nen, int64_t nl, int R, in
 }  // namespace
 
 // Buffers of the implicit step (allocated on first use by fe_implicit_setup).
+// At least this many iterations per solve: where the step is small A is
+// nearly its diagonal and r.z falls below the tolerance after one or two
+// iterations while dofs of small weighted mass (near the PD-only box) still
+// carry a relative error of 1e-4; eight iterations bring them to rounding.
+constexpr int kCgMinIters = 8;
+
+// One-RHS conjugate gradients in three launches per iteration.  Dot products
+// keep the fixed order of k_dot_part / k_dot_final: per-workgroup tree sums of
+// the products, then a strided sum over the workgroups and a tree over the
+// threads, which every workgroup that needs the total recomputes for itself
+// (the same sum in the same order, so every workgroup gets the same value).
+// A device flag ends the iterations once r.z <= tol r0.z0 (after at least
+// kCgMinIters): the kernels of later iterations return at once.
+struct Cg1 {
+  int64_t ndof, nblk;
+  const double *inv_diag;
+  double *x, *r, *z, *p, *q;
+  double *part_pq, *part_rz0, *part_rz[2];
+  int32_t *state;  // [0] done, [1] iterations run
+  double tol;
+};
+
+__device__ inline double block_tree(double v, double *lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) lds[threadIdx.x] += lds[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double out = lds[0];
+  __syncthreads();
+  return out;
+}
+
+__device__ inline double total_of(const double *part, int64_t nblk, double *lds) {
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < nblk; k += kT) s += part[k];
+  return block_tree(s, lds);
+}
+
+// x = 0, r = b, z = p = D^-1 b, partial sums of r.z; clears the flag
+__global__ __launch_bounds__(kT) void k_cg1_init(Cg1 C, const double *b) {
+  __shared__ double lds[kT];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < C.ndof) {
+    const double zi = b[t] * C.inv_diag[t];
+    C.x[t] = 0.0;
+    C.r[t] = b[t];
+    C.z[t] = zi;
+    C.p[t] = zi;
+    v = b[t] * zi;
+  }
+  const double sum = block_tree(v, lds);
+  if (threadIdx.x == 0) {
+    C.part_rz0[blockIdx.x] = sum;
+    C.part_rz[0][blockIdx.x] = sum;
+    if (blockIdx.x == 0) {
+      C.state[0] = 0;
+      C.state[1] = 0;
+    }
+  }
+}
+
+// q = A p and partial sums of p.q
+__global__ __launch_bounds__(kT) void k_cg1_apply(Cg1 C, ApplyArgs A) {
+  __shared__ double lds[kT];
+  if (C.state[0]) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < C.ndof) {
+    double y;
+    if (!A.freedof[t]) {
+      y = C.p[t];
+    } else {
+      const int dim = A.dim, nen = A.nen, nd = nen * dim;
+      const int64_t n = t / dim;
+      const int dd = (int)(t % dim);
+      double acc = 0.0;
+      for (int k = A.n2e_ptr[n]; k < A.n2e_ptr[n + 1]; k++) {
+        const int64_t e = A.n2e[k] / nen;
+        const int la = A.n2e[k] % nen;
+        if (!A.eact[e]) continue;
+        const double *Krow = A.Ke + e * nd * nd + (int64_t)(la * dim + dd) * nd;
+        for (int bb = 0; bb < nen; bb++) {
+          const int64_t nb = A.conn[e * nen + bb];
+          for (int db = 0; db < dim; db++) acc += Krow[bb * dim + db] * C.p[nb * dim + db];
+        }
+      }
+      y = A.mF[n] * C.p[t] + A.ks * acc;
+    }
+    C.q[t] = y;
+    v = C.p[t] * y;
+  }
+  const double sum = block_tree(v, lds);
+  if (threadIdx.x == 0) C.part_pq[blockIdx.x] = sum;
+}
+
+// x += alpha p, r -= alpha q, z = D^-1 r, partial sums of the new r.z
+__global__ __launch_bounds__(kT) void k_cg1_step(Cg1 C, int cur) {
+  __shared__ double lds[kT];
+  if (C.state[0]) return;
+  const double pq = total_of(C.part_pq, C.nblk, lds);
+  const double rz = total_of(C.part_rz[cur], C.nblk, lds);
+  const double al = pq > 0.0 ? rz / pq : 0.0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < C.ndof) {
+    C.x[t] = C.x[t] + al * C.p[t];
+    const double rn = C.r[t] - al * C.q[t];
+    C.r[t] = rn;
+    const double zn = rn * C.inv_diag[t];
+    C.z[t] = zn;
+    v = rn * zn;
+  }
+  const double sum = block_tree(v, lds);
+  if (threadIdx.x == 0) C.part_rz[cur ^ 1][blockIdx.x] = sum;
+}
+
+// p = z + beta p; the flag once r.z <= tol r0.z0
+__global__ __launch_bounds__(kT) void k_cg1_dir(Cg1 C, int cur) {
+  __shared__ double lds[kT];
+  if (C.state[0]) return;
+  const double rzn = total_of(C.part_rz[cur ^ 1], C.nblk, lds);
+  const double rzo = total_of(C.part_rz[cur], C.nblk, lds);
+  const double be = rzo > 0.0 ? rzn / rzo : 0.0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < C.ndof) C.p[t] = C.z[t] + be * C.p[t];
+  if (blockIdx.x == 0) {
+    const double rz0 = total_of(C.part_rz0, C.nblk, lds);
+    if (threadIdx.x == 0) {
+      const int done_its = C.state[1] + 1;
+      C.state[1] = done_its;
+      if (done_its >= kCgMinIters && rzn <= C.tol * rz0) C.state[0] = 1;
+    }
+  }
+}
+
 struct FeImplicit {
   int R = 0;  // RHS capacity of the CG buffers
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *b = nullptr;
@@ -317,6 +455,10 @@ struct FeImplicit {
   double *us = nullptr;
   std::vector<double> h_rz0, h_rz;
   int64_t iters_last = 0;
+  // one-RHS solver (the per-step solves)
+  double *part_pq1 = nullptr, *part_rz0 = nullptr, *part_rz1[2] = {nullptr, nullptr};
+  int32_t *state = nullptr, *h_state = nullptr;  // device flag and iteration count; pinned host copy
+  int64_t iters1_last = 0;
 };
 
 void fe_implicit_setup(Solver &s) {
@@ -362,6 +504,15 @@ FeImplicit &cg_buffers(Solver &s, int R) {
   F.rz[1] = ar.alloc<double>(R);
   F.pq = ar.alloc<double>(R);
   if (!F.us) F.us = ar.alloc<double>(ndof);
+  if (!F.state) {
+    const size_t nb = (size_t)nbk(ndof);
+    F.part_pq1 = ar.alloc<double>(nb);
+    F.part_rz0 = ar.alloc<double>(nb);
+    F.part_rz1[0] = ar.alloc<double>(nb);
+    F.part_rz1[1] = ar.alloc<double>(nb);
+    F.state = ar.alloc<int32_t>(2);
+    MTS_HIP(hipHostMalloc((void **)&F.h_state, 2 * sizeof(int32_t), hipHostMallocDefault));
+  }
   F.R = R;
   return F;
 }
@@ -437,6 +588,53 @@ void cg_solve(Solver &s, FeImplicit &F, int R) {
   F.iters_last = it;
 }
 
+// One right-hand side (x <- A^-1 b): three launches per iteration, the
+// convergence flag read by the host after as many iterations as the previous
+// solve needed plus one (at least kCgMinIters), then every eight.
+void cg_solve1(Solver &s, FeImplicit &F) {
+  const int64_t ndof = s.nfe * s.dim;
+  hipStream_t st = s.stream;
+  const unsigned g = nbk(ndof);
+  Cg1 C{};
+  C.ndof = ndof;
+  C.nblk = g;
+  C.inv_diag = s.fe_inv_diag;
+  C.x = F.x;
+  C.r = F.r;
+  C.z = F.z;
+  C.p = F.p;
+  C.q = F.q;
+  C.part_pq = F.part_pq1;
+  C.part_rz0 = F.part_rz0;
+  C.part_rz[0] = F.part_rz1[0];
+  C.part_rz[1] = F.part_rz1[1];
+  C.state = F.state;
+  C.tol = 1e-28;
+  const ApplyArgs A = apply_args(s, 1, F.p, F.q, 1.0, s.fe_beta * s.prm.dtF * s.prm.dtF, nullptr);
+  k_cg1_init<<<g, kT, 0, st>>>(C, F.b);
+  MTS_LAUNCH_CHECK();
+  int cur = 0;
+  int64_t it = 0, batch = std::max<int64_t>(kCgMinIters, F.iters1_last + 1);
+  const int64_t max_it = 4000;
+  for (;;) {
+    for (int64_t k = 0; k < batch; k++, it++) {
+      k_cg1_apply<<<g, kT, 0, st>>>(C, A);
+      MTS_LAUNCH_CHECK();
+      k_cg1_step<<<g, kT, 0, st>>>(C, cur);
+      MTS_LAUNCH_CHECK();
+      k_cg1_dir<<<g, kT, 0, st>>>(C, cur);
+      MTS_LAUNCH_CHECK();
+      cur ^= 1;
+    }
+    MTS_HIP(hipMemcpyAsync(F.h_state, F.state, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    MTS_HIP(hipStreamSynchronize(st));
+    if (F.h_state[0]) break;
+    if (it >= max_it) throw ArgError{"implicit FE: conjugate gradients did not converge"};
+    batch = 8;
+  }
+  F.iters1_last = F.h_state[1];
+}
+
 }  // namespace
 
 void fe_implicit_free_step(Solver &s) {
@@ -448,7 +646,7 @@ void fe_implicit_free_step(Solver &s) {
   MTS_LAUNCH_CHECK();
   k_fe_apply<<<nbk(ndof), kT, 0, st>>>(apply_args(s, 1, s.ut, F.b, 0.0, -1.0, s.PF));  // b = P - K u*
   MTS_LAUNCH_CHECK();
-  cg_solve(s, F, 1);
+  cg_solve1(s, F);
   k_fe_impl_post<<<nbk(ndof), kT, 0, st>>>(ndof, s.fe_free, s.bc, s.vF, s.aF, F.x, c, s.prm.hdtF, s.p.vel_bc, s.ut,
                                             s.vt, s.at);
   MTS_LAUNCH_CHECK();
@@ -460,7 +658,7 @@ void fe_implicit_correct(Solver &s) {
   FeImplicit &F = cg_buffers(s, 1);
   k_fe_gft<<<nbk(ndof), kT, 0, st>>>(ndof, s.dim, s.nen, s.fe_free, s.f2c_ptr, s.f2c, s.cw, s.lam0, F.b);
   MTS_LAUNCH_CHECK();
-  cg_solve(s, F, 1);
+  cg_solve1(s, F);
   const double c = s.fe_beta * s.prm.dtF * s.prm.dtF;
   k_fe_impl_corr<<<nbk(ndof), kT, 0, st>>>(ndof, F.x, c, s.prm.hdtF, s.ut, s.vt, s.at, s.uF, s.vF, s.aF);
   MTS_LAUNCH_CHECK();
@@ -484,6 +682,7 @@ void fe_implicit_hf(Solver &s) {
 }
 
 void fe_implicit_free(Solver &s) {
+  if (s.fe_impl && s.fe_impl->h_state) (void)hipHostFree(s.fe_impl->h_state);
   delete s.fe_impl;
   s.fe_impl = nullptr;
 }

@@ -304,3 +304,47 @@ def test_implicit_fe(mts, inst):
     print(f"  worst {worst:.2e}, tip checks {tips}, oracle broken {o.info()['n_broken']}", flush=True)
     assert np.abs(o.get(O.FE_U)).max() > 0
     s.close()
+
+
+def _efficiency_cases():
+    # the mode-I plate of the efficiency study (Table 2) at dx = 1.25 mm, run
+    # past the first breaks at the notch (the stress wave reaches it after ~9 us)
+    return [mi.efficiency2d(1.25e-3, pd_frac=0.1, m=2, n_macro=1400),
+            mi.efficiency2d(1.25e-3, pd_frac=0.2, m=5, n_macro=600),
+            mi.efficiency2d(1.25e-3, pd_frac=1.0, n_macro=3000)]
+
+
+@pytest.mark.parametrize("inst", _efficiency_cases(), ids=lambda x: x["name"])
+def test_efficiency_plate(mts, inst):
+    """The efficiency study's plate (exponential micromodulus, implicit FE step,
+    pure PD with the body-force load) against the oracle: state within 1e-10
+    before the first break, 1e-9 while the bond states agree, crack tip within
+    dx after."""
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    o = Oracle(inst, openmp=True)
+    pos, dx = inst["pos"], inst["dx"]
+    coupled = inst["mode"] == "coupled"
+    qs = [(mts.PD_U, O.PD_U), (mts.PD_V, O.PD_V)]
+    if coupled:
+        qs += [(mts.FE_U, O.FE_U), (mts.FE_V, O.FE_V), (mts.LAMBDA, O.LAMBDA)]
+    worst, tips, stride = 0.0, 0, 20
+    for k in range(0, inst["n_macro"], stride):
+        s.advance(stride)
+        o.advance(stride)
+        broken = o.info()["n_broken"]
+        if broken == 0 or np.array_equal(s.bonds()[2], o.bonds()[2]):
+            tol = 1e-10 if broken == 0 else 1e-9
+            for gq, oq in qs:
+                e = _rel(s.read(gq), o.get(oq))
+                worst = max(worst, e)
+                assert e <= tol, (k, gq, e)
+            assert np.array_equal(s.read(mts.DAMAGE), o.get(O.DAMAGE)), k
+        else:
+            tg, to = _tip(pos, s.read(mts.DAMAGE)), _tip(pos, o.get(O.DAMAGE))
+            tips += 1
+            if tg is not None and to is not None:
+                assert np.linalg.norm(tg - to) <= dx * (1 + 1e-9), k
+    print(f"  worst {worst:.2e}, tip checks {tips}, oracle broken {o.info()['n_broken']}", flush=True)
+    assert o.info()["n_broken"] > 0
+    s.close()
