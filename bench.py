@@ -417,6 +417,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     ap.add_argument("--serve", action="store_true", help="only run the serving stream (its own JSON line)")
+    ap.add_argument("--branching", action="store_true", help="only run the crack-branching comparison (its own line)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0, help="pool budget (0: 90%% of free HBM)")
@@ -449,6 +450,17 @@ def main():
     torch.cuda.set_device(0)
     if args.serve:
         return serve_main(args, torch, log)
+    if args.branching:
+        br = branching_run(mts, torch, log)
+        c = br["coupled"]
+        print(json.dumps({
+            "metric": "crack-branching plate: run time of the MTS model (s), with the pure-PD model beside it",
+            "value": c["run_s"], "unit": "s", "n_gpus": 1, "steps": c["macro_steps"], "warmup": 0,
+            "ms_per_step": c["run_s"] * 1e3 / c["macro_steps"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "crack-branching plate 100 x 40 mm, dx 0.25 mm, 6e-5 s"},
+            "branching": br}), flush=True)
+        return
     default_prec = "mixed" if args.config == 3 else "fp64"
     prec = args.precision or default_prec
     inst = mi.config(args.config, precision=prec)
