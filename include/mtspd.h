@@ -100,8 +100,10 @@ typedef struct mts_info {
   int32_t dim, precision;
   double dt_bound_pd;    /* PD stability bound of the step (create rejects dt_pd above it) */
   int64_t inverse_bytes; /* bytes of the packed inverse of H that each multiplier solve
-                            (Eq. 49) reads: 64 x 64 FP64 lower tiles of every
-                            component block; 0 in pure-PD mode */
+                            (Eq. 49) reads: the kept 64 x 64 lower tiles of every component
+                            block, 32 KiB each in FP64 or 16 KiB for tiles whose entries are
+                            all at most 2^-29 of the component's largest (stored in FP32);
+                            0 in pure-PD mode */
   double slot_bytes;     /* bytes of slot record the bond pass reads per bond slot: 12 (FP64
                             coefficient and neighbour offset), 8 (mixed), 6 (mixed with
                             neighbour records staged in LDS: two slots per 12-byte record) */

@@ -413,10 +413,41 @@ __global__ void k_tile_absmax(const double *packed, int64_t n_tiles, double *out
   if (lane == 0) out[tile] = m;
 }
 
+// Listed tiles rewritten in FP32 (round to nearest) into the first half of
+// their own slot: one workgroup per tile reads the whole tile before writing.
+__global__ __launch_bounds__(256) void k_tiles_to_f32(double *packed, const int32_t *tiles) {
+  double v[TS * TS / 256];
+  double *tp = packed + (int64_t)tiles[blockIdx.x] * TS * TS;
+#pragma unroll
+  for (int q = 0; q < TS * TS / 256; q++) v[q] = tp[q * 256 + threadIdx.x];
+  __syncthreads();
+  float *dst = reinterpret_cast<float *>(tp);
+#pragma unroll
+  for (int q = 0; q < TS * TS / 256; q++) dst[q * 256 + threadIdx.x] = (float)v[q];
+}
+
+// Eight 16-byte pieces of a tile for this lane: pairs of entries (row 2 q + h,
+// columns c0, c0 + 1), from the FP64 tile or from its FP32 copy in the first
+// half of the same slot (converted exactly to FP64).
+__device__ __forceinline__ void load_pairs(const double *tile, bool f32, int q0, int lane, double2 e[8]) {
+  if (f32) {
+    const float2 *src = reinterpret_cast<const float2 *>(tile);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const float2 v = src[(q0 + q) * WAVE + lane];
+      e[q] = double2{(double)v.x, (double)v.y};
+    }
+  } else {
+    const double2 *src = reinterpret_cast<const double2 *>(tile);
+#pragma unroll
+    for (int q = 0; q < 8; q++) e[q] = src[(q0 + q) * WAVE + lane];
+  }
+}
+
 __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
                                                    const int64_t *off, const int32_t *idx, const double *r,
-                                                   const int32_t *kept, const int64_t *n_kept, double *rowpart,
-                                                   double *colpart) {
+                                                   const int32_t *kept, const uint8_t *kept_f32,
+                                                   const int64_t *n_kept, double *rowpart, double *colpart) {
   const int64_t n_tiles = *n_kept;
   __shared__ double xs[4][2][TS];  // per wavefront: x_I, x_J
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
@@ -425,10 +456,10 @@ __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, cons
   const int64_t stride = (int64_t)gridDim.x * 4;
   for (int64_t k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + w)); k < n_tiles; k += stride) {
     const int64_t tile = kept[k];
-    const double2 *src = reinterpret_cast<const double2 *>(packed + tile * TS * TS);
+    const bool f32 = __builtin_amdgcn_readfirstlane((int)kept_f32[k]) != 0;
+    const double *tp = packed + tile * TS * TS;
     double2 e[8];
-#pragma unroll
-    for (int q = 0; q < 8; q++) e[q] = src[q * WAVE + lane];
+    load_pairs(tp, f32, 0, lane, e);
     const int comp = tile_meta[tile * 3 + 0], I = tile_meta[tile * 3 + 1], J = tile_meta[tile * 3 + 2];
     const int64_t base = off[comp], n = off[comp + 1] - base;
     {
@@ -456,10 +487,7 @@ __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, cons
         cs1 += e[q].y * xr;
         p[q] = e[q].x * xj0 + e[q].y * xj1;
       }
-      if (qt < 3) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) e[q] = src[(8 * (qt + 1) + q) * WAVE + lane];
-      }
+      if (qt < 3) load_pairs(tp, f32, 8 * (qt + 1), lane, e);
       // recursive halving over the 32 lanes of the half-wavefront
       double p4[4], p2[2];
 #pragma unroll
@@ -618,9 +646,14 @@ void sym_blocks_build(Solver &s) {
 // (dofs) x kInvDrop x max|H^-1| x max|r| to any multiplier, far below the
 // rounding of the product itself (dofs x eps relative), so it is skipped.
 // Skipped tiles keep zero partial sums, so the fixed-order reduction is
-// unchanged.  MTS_INV_DROP=0 keeps every tile.
+// unchanged.  A kept tile whose largest entry is at most 2^-29 of its
+// component's largest is stored in FP32: rounding then moves an entry by at
+// most 2^-54 of the component's largest entry, half a unit in the last place
+// of that entry in FP64, and the products and sums stay in FP64 in the same
+// order.  MTS_INV_DROP=0 keeps every tile, in FP64.
 void sym_blocks_prune(Solver &s) {
   constexpr double kInvDrop = 1e-18;
+  const double kF32 = std::ldexp(1.0, -29);
   auto &B = s.sym;
   hipStream_t st = s.stream;
   if (!B.n_tiles) return;
@@ -636,18 +669,39 @@ void sym_blocks_prune(Solver &s) {
   MTS_HIP(hipStreamSynchronize(st));
   std::vector<double> cmax((size_t)B.n_comp, 0.0);
   for (int64_t t = 0; t < B.n_tiles; t++) cmax[meta[t * 3]] = std::max(cmax[meta[t * 3]], tm[t]);
-  std::vector<int32_t> kept;
-  for (int64_t t = 0; t < B.n_tiles; t++)
-    if (!B.prune || meta[t * 3 + 1] == meta[t * 3 + 2] || tm[t] > kInvDrop * cmax[meta[t * 3]])
+  std::vector<int32_t> kept, to32;
+  std::vector<uint8_t> f32;
+  for (int64_t t = 0; t < B.n_tiles; t++) {
+    const double cm = cmax[meta[t * 3]];
+    const bool diag = meta[t * 3 + 1] == meta[t * 3 + 2];
+    if (!B.prune || diag || tm[t] > kInvDrop * cm) {
       kept.push_back((int32_t)t);
+      // FP32 only in its normal range (no subnormal entries above the drop)
+      const bool low = B.prune && !diag && tm[t] <= kF32 * cm && kInvDrop * cm >= 1e-30 && cm <= 1e30;
+      f32.push_back(low ? 1 : 0);
+      if (low) to32.push_back((int32_t)t);
+    }
+  }
   B.n_kept = (int64_t)kept.size();
+  B.n_kept32 = (int64_t)to32.size();
+  if (!B.kept_f32) B.kept_f32 = s.arena.alloc<uint8_t>((size_t)B.n_tiles);
   MTS_HIP(hipMemcpyAsync(B.kept, kept.data(), sizeof(int32_t) * kept.size(), hipMemcpyHostToDevice, st));
+  MTS_HIP(hipMemcpyAsync(B.kept_f32, f32.data(), f32.size(), hipMemcpyHostToDevice, st));
+  if (!to32.empty()) {
+    int32_t *d32 = s.arena.alloc<int32_t>(to32.size());
+    MTS_HIP(hipMemcpyAsync(d32, to32.data(), sizeof(int32_t) * to32.size(), hipMemcpyHostToDevice, st));
+    k_tiles_to_f32<<<(unsigned)to32.size(), 256, 0, st>>>(B.packed, d32);
+    MTS_LAUNCH_CHECK();
+    MTS_HIP(hipStreamSynchronize(st));
+    s.arena.release(d32);
+  }
   MTS_HIP(hipMemcpyAsync(B.n_kept_dev, &B.n_kept, sizeof(int64_t), hipMemcpyHostToDevice, st));
   // skipped tiles contribute zero partial sums
   MTS_HIP(hipMemsetAsync(B.rowpart, 0, sizeof(double) * B.n_tiles * TS, st));
   MTS_HIP(hipMemsetAsync(B.colpart, 0, sizeof(double) * B.n_tiles * TS, st));
   MTS_HIP(hipStreamSynchronize(st));
-  vlog(s, "coupling: the multiplier solve reads %lld of %lld tiles", (long long)B.n_kept, (long long)B.n_tiles);
+  vlog(s, "coupling: the multiplier solve reads %lld of %lld tiles (%lld in FP32)", (long long)B.n_kept,
+       (long long)B.n_tiles, (long long)B.n_kept32);
 }
 
 void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
@@ -656,8 +710,8 @@ void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
   // four tiles per workgroup at a time; up to eight resident workgroups per CU
   // the grid covers every tile; the count of kept tiles is read on the device
   const unsigned g = (unsigned)std::min<int64_t>((B.n_tiles + 3) / 4, 256 * 8);
-  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.kept, B.n_kept_dev, B.rowpart,
-                                       B.colpart);
+  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.kept, B.kept_f32, B.n_kept_dev,
+                                       B.rowpart, B.colpart);
   MTS_LAUNCH_CHECK();
   k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
                                                         B.rowpart, B.colpart, y, y2);

@@ -250,6 +250,10 @@ struct Solver {
     int64_t *n_kept_dev = nullptr;  // the same count on the device (launches read it, so a
                                     // captured solve stays valid when a rebuild changes it)
     double *tile_max = nullptr;     // per tile: largest |entry| of the inverse
+    // kept tiles whose largest entry is at most 2^-29 of their component's
+    // largest are stored in FP32, in place in the first half of their slot
+    uint8_t *kept_f32 = nullptr;    // per kept entry: 1 if stored in FP32
+    int64_t n_kept32 = 0;
     bool prune = true;
   } sym;
   std::vector<int32_t> h_cn;

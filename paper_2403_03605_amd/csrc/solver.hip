@@ -880,7 +880,8 @@ void mts::query_impl(Solver &s, mts_info *o) {
   o->dim = s.dim;
   o->precision = s.precision;
   o->dt_bound_pd = s.dt_bound_pd;
-  o->inverse_bytes = (s.sym.kept ? s.sym.n_kept : s.sym.n_tiles) * 64 * 64 * (int64_t)sizeof(double);
+  o->inverse_bytes = ((s.sym.kept ? s.sym.n_kept : s.sym.n_tiles) - s.sym.n_kept32) * 64 * 64 * (int64_t)sizeof(double) +
+                     s.sym.n_kept32 * 64 * 64 * (int64_t)sizeof(float);
   o->slot_bytes = s.sell.pair_slots ? 6.0 : s.precision == MTS_MIXED ? 8.0 : 12.0;
 }
 
