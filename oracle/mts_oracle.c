@@ -179,6 +179,8 @@ struct orc_solver {
    * A = M + beta dt^2 K over all FE dofs (identity on prescribed and inactive dofs) */
   double beta;
   double *LA;
+  double *LP;                 /* implicit PD: Cholesky factor of M + beta dt^2 K_PD (N dim)^2 */
+  double betaP;
   double *febuf;              /* per-element internal forces of orc_fe_force (ne * nen * dim) */
   /* coupling */
   int64_t nc, nl;
@@ -869,6 +871,60 @@ static int build_y(orc_solver *s) {
   return 0;
 }
 
+/* Implicit PD step (Eq. 38 with beta = 1/4 for the PD subdomain, pure-PD
+ * mode): A = M + beta dt^2 K_PD assembled column by column from the linear
+ * bond force of Eq. 2 with the current bond states (K_PD u = -f(u)), and
+ * factored (Cholesky, A = L L^T).  Rebuilt whenever bonds break. */
+static int build_pd_implicit(orc_solver *s) {
+  int dim = s->dim;
+  int64_t n = s->N * dim;
+  double c = s->betaP * s->dtP * s->dtP;
+  if (!s->LP) s->LP = xcalloc((size_t)(n * n), sizeof(double));
+  double *A = s->LP;
+  double *e = xcalloc((size_t)n, sizeof(double));
+  if (!A || !e) { free(e); return -1; }
+  for (int64_t j = 0; j < n; j++) {
+    e[j] = 1.0;
+    for (int64_t i = 0; i < s->N; i++) {
+      double F[3];
+      node_force(s, i, e, s->mu, 0, F); /* column j of -K_PD */
+      for (int d = 0; d < dim; d++) A[(i * dim + d) * n + j] = -c * F[d];
+    }
+    e[j] = 0.0;
+    A[j * n + j] += s->mP[j / dim];
+  }
+  free(e);
+  for (int64_t j = 0; j < n; j++) {
+    double d = A[j * n + j];
+    for (int64_t k = 0; k < j; k++) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0.0)) { set_err("implicit PD matrix not positive definite at row %lld", (long long)j); return -1; }
+    double ljj = sqrt(d);
+    A[j * n + j] = ljj;
+    for (int64_t i = j + 1; i < n; i++) {
+      double t = A[i * n + j];
+      for (int64_t k = 0; k < j; k++) t -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = t / ljj;
+    }
+  }
+  return 0;
+}
+
+/* x = A^-1 b through the implicit PD factor (x and b may alias). */
+static void pd_solve(const orc_solver *s, const double *b, double *x) {
+  int64_t n = s->N * s->dim;
+  const double *L = s->LP;
+  for (int64_t i = 0; i < n; i++) {
+    double t = b[i];
+    for (int64_t k = 0; k < i; k++) t -= L[i * n + k] * x[k];
+    x[i] = t / L[i * n + i];
+  }
+  for (int64_t i = n - 1; i >= 0; i--) {
+    double t = x[i];
+    for (int64_t k = i + 1; k < n; k++) t -= L[k * n + i] * x[k];
+    x[i] = t / L[i * n + i];
+  }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Create                                                                    */
 /* ------------------------------------------------------------------------- */
@@ -881,6 +937,10 @@ orc_solver *orc_create(const orc_problem *p) {
     return NULL;
   }
   if (p->clamp_x0 && p->vel_bc != 0.0) { set_err("clamp_x0 needs vel_bc = 0"); return NULL; }
+  if (p->pd_beta != 0.0 && (p->pd_beta != 0.25 || p->mode != ORC_PURE_PD)) {
+    set_err("pd_beta must be 0, or 1/4 in pure-PD mode");
+    return NULL;
+  }
   if (p->m < 1) { set_err("m must be >= 1"); return NULL; }
   if (!(p->dx > 0.0) || !(p->horizon_factor >= 1.0)) { set_err("bad dx / horizon"); return NULL; }
   if (!(p->dt_pd > 0.0)) { set_err("dt_pd must be > 0"); return NULL; }
@@ -1025,6 +1085,8 @@ orc_solver *orc_create(const orc_problem *p) {
       if (build_y(s)) { orc_destroy(s); return NULL; }
     }
   }
+  s->betaP = p->pd_beta;
+  if (s->betaP > 0.0 && build_pd_implicit(s)) { orc_destroy(s); return NULL; }
   /* initial accelerations a0 = M^-1 (P - K u0) with u0 = 0 (reading R15) */
   for (int64_t i = 0; i < N; i++)
     for (int d = 0; d < dim; d++) s->aP[i * dim + d] = s->PP[i * dim + d] / s->mP[i];
@@ -1041,6 +1103,7 @@ void orc_destroy(orc_solver *s) {
   free(s->cn); free(s->cidx); free(s->cel); free(s->cw); free(s->H); free(s->L); free(s->lam0);
   free(s->region);
   free(s->LA);
+  free(s->LP);
   free(s->febuf);
   free(s);
 }
@@ -1064,7 +1127,7 @@ static int macro_step(orc_solver *s) {
   double *tF = xcalloc((size_t)nF, sizeof(double));
   double *r = xcalloc((size_t)(coupled ? s->nl : 1), sizeof(double));
   double *lam = xcalloc((size_t)(coupled ? s->nl : 1), sizeof(double));
-  double *W = xcalloc((size_t)(coupled ? N * dim * 3 : 1), sizeof(double));
+  double *W = xcalloc((size_t)(coupled ? N * dim * 3 : (s->betaP > 0.0 ? N * dim : 1)), sizeof(double));
   int rc = -1;
   if (!fP || !ut || !vt || !at || !fF || !tF || !r || !lam || !W) goto out;
 
@@ -1125,6 +1188,38 @@ static int macro_step(orc_solver *s) {
   /* PD free problem (Eq. 48a): m substeps at dt_PD, bond states updated on the
    * free problem only (Sec. 2.5, note on broken bonds) */
   for (int j = 1; j <= m; j++) {
+    if (s->betaP > 0.0) {
+      /* implicit PD step (Eq. 38, beta = 1/4, pure-PD mode): predictor, then
+       * (M + beta dt^2 K) a = P + f(u*) with the current bond states; the
+       * critical-stretch test runs on the solved displacement and its breaks
+       * take effect from the next step (reading R36) */
+      double b2 = (0.5 - s->betaP) * s->dtP * s->dtP, c = s->betaP * s->dtP * s->dtP;
+      double *us = W; /* N dim scratch (the link buffers are unused in pure-PD mode) */
+      for (int64_t t = 0; t < N * dim; t++) us[t] = (s->uP[t] + s->dtP * s->vP[t]) + b2 * s->aP[t];
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < N; i++) {
+        double F[3];
+        node_force(s, i, us, s->mu, 0, F);
+        for (int d = 0; d < dim; d++) fP[i * dim + d] = F[d] + s->PP[i * dim + d];
+      }
+      pd_solve(s, fP, fP);
+      for (int64_t t = 0; t < N * dim; t++) {
+        double an = fP[t];
+        s->uP[t] = us[t] + c * an;
+        s->vP[t] = s->vP[t] + s->hdtP * (s->aP[t] + an);
+        s->aP[t] = an;
+      }
+      int64_t broke_j = 0;
+#pragma omp parallel for schedule(static) reduction(+ : broke_j)
+      for (int64_t i = 0; i < N; i++) {
+        double F[3];
+        broke_j += node_force(s, i, s->uP, s->mu, s->p.breaking, F);
+      }
+      s->nbroken += broke_j;
+      if (broke_j && build_pd_implicit(s)) goto out;
+      s->pd_steps++;
+      continue;
+    }
     double sfac = 1.0 - (double)j / (double)m; /* S_j = (1 - j/m) lambda_0 (reading R14) */
     /* The loops over nodes below are independent per node (each node sums its
      * own family and owns its row of bond states), so an OpenMP build gives

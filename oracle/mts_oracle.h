@@ -42,6 +42,8 @@ typedef struct {
                                  load of the beam of Sec. 3.2 */
   int32_t clamp_x0;           /* 1: every component of the FE nodes on x = dom_lo held at
                                  zero (the beam's fixed end); needs vel_bc = 0 */
+  double pd_beta;             /* Newmark beta of the PD step (pure-PD mode): 0 explicit
+                                 (velocity Verlet), 1/4 average acceleration (implicit) */
 } orc_problem;
 
 typedef struct {

@@ -373,6 +373,56 @@ def test_two_node_verlet_closed_form():
         assert q == pytest.approx(q0 * math.cos(n * th), rel=1e-9, abs=1e-12 * q0)
 
 
+def test_two_node_implicit_closed_form():
+    """Implicit PD step (Newmark gamma 1/2, beta 1/4, Eq. 38): on one bond the
+    relative coordinate q obeys q'' + w^2 q = 0, and the average-acceleration
+    step gives exactly q_n = q0 cos(n th) with cos th = (1 - W^2/4)/(1 + W^2/4),
+    W = w dt, started from rest at q0 with a0 = -w^2 q0; here W = 3, beyond the
+    explicit bound W = 2."""
+    L = 1e-3
+    pos = np.array([[0.0, 0.0], [L, 0.0]])
+    base = dict(dim=2, mode="pure_pd", pos=pos, dx=1e-3, horizon_factor=1.2,
+                pd_lo=(-5e-4, -5e-4), pd_hi=(1.5e-3, 5e-4), dom_lo=(-5e-4, -5e-4),
+                dom_hi=(1.5e-3, 5e-4), cracks=[], m=1, dt_pd=1e-7, E=72e9, rho=2440.0,
+                G0=3.8, thickness=1.0, traction=0.0, breaking=False)
+    info = Oracle(base, setup_only=True).info()
+    V, c0 = info["volume"], info["c0"]
+    k = c0 / L ** 3 * L * L * V * V
+    mnode = base["rho"] * V
+    w = math.sqrt(2 * k / mnode)
+    dt = 3.0 / w
+    o = Oracle(dict(base, dt_pd=dt, pd_beta=0.25))
+    q0 = 1e-7
+    u = np.array([[-q0 / 2, 0.0], [q0 / 2, 0.0]])
+    o.set(O.PD_U, u)
+    o.set(O.PD_A, o.pd_force(u) / mnode)
+    W2 = (w * dt) ** 2
+    th = math.acos((1 - W2 / 4) / (1 + W2 / 4))
+    for n in range(1, 41):
+        o.advance(1)
+        q = np.diff(o.get(O.PD_U)[:, 0])[0]
+        assert q == pytest.approx(q0 * math.cos(n * th), rel=1e-9, abs=1e-12 * q0)
+
+
+def test_implicit_pd_conserves_energy_beyond_explicit_bound():
+    """The average-acceleration step conserves kinetic + deformation energy
+    minus the work of the constant load exactly for the linear bond force (no
+    breaking), here at five times the explicit PD stability bound."""
+    inst = mi.plate2d(30, 1, 10, 1e-8, mode="pure_pd", breaking=False, name="p30 implicit")
+    inst["cracks"] = []
+    inst["dt_pd"] = 5 * Oracle(inst, setup_only=True).dt_bound(0)
+    inst["pd_beta"] = 0.25
+    o = Oracle(inst)
+    E = []
+    for _ in range(100):
+        o.advance(1)
+        i = o.info()
+        E.append(i["e_kin"] + i["e_pd"] - i["w_ext"])
+    i = o.info()
+    assert np.abs(np.array(E)).max() <= 1e-10 * (i["e_kin"] + i["e_pd"])
+    assert i["e_kin"] > 0 and i["e_pd"] > 0
+
+
 def _energy_drift(dt, steps):
     inst = mi.plate2d(20, 1, steps, dt, mode="pure_pd", breaking=False)
     o = Oracle(inst)
