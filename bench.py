@@ -345,21 +345,24 @@ def branching_run(mts, torch, log):
     return out
 
 
-# the paper's Table 2 cases that run explicit PD (cases 1 and 2 are implicit PD)
-TABLE2_CASES = [(3, 5e-4, 0.2, 2), (4, 5e-4, 0.1, 2), (5, 5e-4, 0.1, 5), (6, 2.5e-4, 1.0, 1), (7, 2.5e-4, 0.1, 10)]
-TABLE2_PAPER_MS = {3: (95.9, 44.7), 4: (86.9, 41.0), 5: (208.7, 39.2), 6: (253.0, 253.0), 7: (552.9, 50.6)}
+# the paper's Table 2 cases: (case, dx, PD area, m, PD Newmark beta); case 2
+# (MTS with the implicit PD step) is not run
+TABLE2_CASES = [(1, 5e-4, 1.0, 1, 0.25), (3, 5e-4, 0.2, 2, 0.0), (4, 5e-4, 0.1, 2, 0.0), (5, 5e-4, 0.1, 5, 0.0),
+                (6, 2.5e-4, 1.0, 1, 0.0), (7, 2.5e-4, 0.1, 10, 0.0)]
+TABLE2_PAPER_MS = {1: (69.8, 69.8), 3: (95.9, 44.7), 4: (86.9, 41.0), 5: (208.7, 39.2), 6: (253.0, 253.0),
+                   7: (552.9, 50.6)}
 
 
 def table2_run(mts, torch, log, pd_steps=400):
-    """The efficiency study's mode-I plate (Table 2) in the cases that run the
-    PD step explicitly: per FE step and per PD step, wall time of pd_steps PD
+    """The efficiency study's mode-I plate (Table 2) in its cases except the
+    MTS model with the implicit PD step (case 2): per FE step and per PD step, wall time of pd_steps PD
     steps from a resident state, and the split into PD substeps (the paper's
     t^U), FE step (t^K) and multipliers with the final update (t^lambda) from
     a second, event-timed pass."""
     import mts_inputs as mi
     out = []
-    for case, dx, frac, m in TABLE2_CASES:
-        inst = mi.efficiency2d(dx, pd_frac=frac, m=m, n_macro=pd_steps // m)
+    for case, dx, frac, m, pd_beta in TABLE2_CASES:
+        inst = mi.efficiency2d(dx, pd_frac=frac, m=m, pd_beta=pd_beta, n_macro=pd_steps // m)
         s = mts.Solver(inst)
         s.advance(max(2, 20 // m))
         s.sync()
@@ -381,7 +384,7 @@ def table2_run(mts, torch, log, pd_steps=400):
         info = s.query()
         paper = TABLE2_PAPER_MS[case]
         rec = {"case": case, "workload": inst["name"], "dx_mm": dx * 1e3, "pd_area": frac, "m": m,
-               "pd_nodes": info["n_pd"], "bonds": info["nnz"], "fe_beta": inst["fe_beta"],
+               "pd_nodes": info["n_pd"], "bonds": info["nnz"], "fe_beta": inst["fe_beta"], "pd_beta": pd_beta,
                "ms_per_fe_step": wall, "ms_per_pd_step": wall / m,
                "phases_ms_per_fe_step": {"t_U_pd_substeps": ph["pd_substeps"], "t_K_fe": ph["fe"],
                                          "t_lambda_multipliers_and_update": ph["lambda"] + ph["link"]},

@@ -90,6 +90,12 @@ typedef struct mts_problem {
   int32_t clamp_x0;     /* 1: every displacement component of the FE nodes on the face
                            x = dom_lo[0] is held at zero (the fixed end of that beam); needs
                            vel_bc = 0 (coupled mode, one solver, not the pool) */
+  double pd_beta;       /* Newmark beta of the PD step (gamma = 1/2): 0 explicit (velocity Verlet),
+                           1/4 average acceleration, implicit: each step solves
+                           (M + beta dt^2 K) a = P + f(u*) by conjugate gradients with the current
+                           bond states, and the critical-stretch test runs on the solved
+                           displacement (Eq. 38; pure-PD mode, FP64, one solver, not the pool;
+                           dt_pd may exceed the explicit bound) */
 } mts_problem;
 
 typedef struct mts_info {

@@ -204,7 +204,7 @@ def branching2d(nx: int = 400, mode: str = "coupled", *, m: int = 10, t_end: flo
 
 
 def efficiency2d(dx: float = 5e-4, *, pd_frac: float = 0.1, m: int = 2, fe_beta: float = 0.25,
-                 n_macro: int = 100, precision: str = "fp64", perturb: float = 0.0,
+                 pd_beta: float = 0.0, n_macro: int = 100, precision: str = "fp64", perturb: float = 0.0,
                  seed: int = SEED_BASE + 6, name: Optional[str] = None) -> Dict:
     """The mode-I plate of the paper's efficiency study (Sec. 3.3, Table 2),
     turned by 90 degrees so that the notch is horizontal: a 40 x 100 mm plate
@@ -214,7 +214,8 @@ def efficiency2d(dx: float = 5e-4, *, pd_frac: float = 0.1, m: int = 2, fe_beta:
     0.1 (a 20 x 20 mm PD box at the notch), 0.2 (a 40 x 20 mm strip across the
     plate) or 1.0 (pure PD over the plate, the traction as a body force within
     delta of the loaded faces).  Q4 elements of 4 dx, implicit FE step by
-    default (the paper's choice for this study)."""
+    default (the paper's choice for this study); pd_beta = 1/4 makes the PD
+    step implicit (pure PD only, the study's case 1)."""
     W, H = 0.04, 0.1
     pure = pd_frac >= 1.0
     if pure:
@@ -228,7 +229,7 @@ def efficiency2d(dx: float = 5e-4, *, pd_frac: float = 0.1, m: int = 2, fe_beta:
     n = (int(round((pd_hi[0] - pd_lo[0]) / dx)), int(round((pd_hi[1] - pd_lo[1]) / dx)))
     fe_h = 4.0 * dx
     inst = dict(
-        name=name or (f"efficiency plate {n[0]}x{n[1]} pure PD {precision}" if pure else
+        name=name or (f"efficiency plate {n[0]}x{n[1]} pure PD{' implicit' if pd_beta else ''} {precision}" if pure else
                       f"efficiency plate PD {int(round(100 * pd_frac))}% m={m} {precision}"),
         dim=2, mode="pure_pd" if pure else "coupled", precision=precision, breaking=True,
         pd_n=(n[0], n[1], 1), pd_lo=pd_lo, pd_hi=pd_hi, dx=dx, horizon_factor=3.015,
@@ -236,7 +237,8 @@ def efficiency2d(dx: float = 5e-4, *, pd_frac: float = 0.1, m: int = 2, fe_beta:
         fe_n=(0, 0, 0) if pure else (int(round(W / fe_h)), int(round(H / fe_h)), 1), fe_h=fe_h,
         overlap=3.0 * dx, weight="cubic", cracks=[(0.05, 0.0, 0.01)],
         thickness=1.0, kernel="exp", l_over_delta=0.1, traction=16e6, vel_bc=0.0,
-        fe_beta=0.0 if pure else fe_beta, m=1 if pure else m, dt_pd=5e-9, n_macro=n_macro,
+        fe_beta=0.0 if pure else fe_beta, pd_beta=pd_beta if pure else 0.0, m=1 if pure else m, dt_pd=5e-9,
+        n_macro=n_macro,
         E=72e9, rho=2235.0, G0=204.0,
     )
     inst["pos"] = lattice_positions(n, pd_lo, dx, perturb, seed)

@@ -42,6 +42,7 @@ class Problem(C.Structure):
         ("fe_beta", C.c_double),
         ("traction_x", C.c_double),
         ("clamp_x0", C.c_int32),
+        ("pd_beta", C.c_double),
     ]
 
 
@@ -173,6 +174,7 @@ def make_problem(inst: dict):
     p.s_crit = float(inst.get("s_crit", 0.0))
     p.traction_x = float(inst.get("traction_x", 0.0))
     p.clamp_x0 = 1 if inst.get("clamp_x0", False) else 0
+    p.pd_beta = float(inst.get("pd_beta", 0.0))
     return p, pos
 
 

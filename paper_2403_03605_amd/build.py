@@ -11,8 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmtspd.so")
-SOURCES = ["neighbors.hip", "layout.hip", "pd.hip", "fe.hip", "fe_implicit.hip", "coupling.hip", "dense.hip",
-           "solver.hip", "pool.hip", "energy.hip"]
+SOURCES = ["neighbors.hip", "layout.hip", "pd.hip", "pd_implicit.hip", "fe.hip", "fe_implicit.hip", "coupling.hip",
+           "dense.hip", "solver.hip", "pool.hip", "energy.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

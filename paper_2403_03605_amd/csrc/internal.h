@@ -211,6 +211,9 @@ struct Solver {
   double *fe_inv_diag = nullptr;  // Jacobi preconditioner of M + beta dt^2 K
   double *fe_HF = nullptr;        // nl x nl FE block (dt/2) G_F A^-1 G_F^T of H
   struct FeImplicit *fe_impl = nullptr;  // conjugate-gradient buffers (host struct)
+  // implicit PD step (pd_beta > 0, pure-PD mode, FP64)
+  double pd_beta = 0.0;
+  struct PdImplicit *pd_impl = nullptr;
   void *fe_tab = nullptr;        // element tables (shape functions, derivatives, Hooke), device
   std::vector<int32_t> h_conn;
   std::vector<uint8_t> h_bc;
@@ -352,6 +355,10 @@ void fe_implicit_free_step(Solver &s);
 void fe_implicit_correct(Solver &s);  // after lambda_m
 void fe_implicit_hf(Solver &s);       // the FE block of H, once
 void fe_implicit_free(Solver &s);     // host buffers
+// implicit PD step (pd_implicit.hip)
+void pd_implicit_setup(Solver &s);
+void pd_implicit_step(Solver &s);     // one PD step, then the break test on its displacement
+void pd_implicit_free(Solver &s);
 // coupling (coupling.hip)
 void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);

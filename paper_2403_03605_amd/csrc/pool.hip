@@ -54,6 +54,7 @@ void destroy_solver(Solver *s) {
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->nf_event) (void)hipEventDestroy(s->nf_event);
   fe_implicit_free(*s);
+  pd_implicit_free(*s);
   if (s->pinned_flag) (void)hipHostFree(s->pinned_flag);
   s->arena.free_all();
   delete s;
@@ -391,6 +392,7 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
   if (p->dim != P->dim || p->precision != P->precision)
     return (set_error("request dim/precision differ from the pool's"), MTS_EINVAL);
   if (p->fe_beta != 0.0) return (set_error("the pool runs the explicit FE step only (fe_beta = 0)"), MTS_EINVAL);
+  if (p->pd_beta != 0.0) return (set_error("the pool runs the explicit PD step only (pd_beta = 0)"), MTS_EINVAL);
   if (p->traction_x != 0.0 || p->clamp_x0)
     return (set_error("the pool serves y-face tractions and the x-velocity load only"), MTS_EINVAL);
   mts_plan_info plan{};

@@ -153,6 +153,9 @@ void validate(const mts_problem *p) {
   if (p->mode != MTS_COUPLED && (p->traction_x != 0.0 || p->clamp_x0))
     throw ArgError{"traction_x and clamp_x0 act on the FE mesh (coupled mode)"};
   if (p->clamp_x0 && p->vel_bc != 0.0) throw ArgError{"clamp_x0 needs vel_bc = 0"};
+  if (!(p->pd_beta == 0.0 || p->pd_beta == 0.25)) throw ArgError{"pd_beta must be 0 (explicit) or 1/4"};
+  if (p->pd_beta != 0.0 && (p->mode != MTS_PURE_PD || p->precision != MTS_FP64))
+    throw ArgError{"the implicit PD step runs in pure-PD mode and FP64"};
   for (int64_t i = 0; i < p->n_pd * p->dim; i++)
     if (!std::isfinite(p->host_pd_pos[i])) throw ArgError{"non-finite node position"};
 }
@@ -249,6 +252,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   s->breaking = pin->breaking != 0;
   s->m = pin->m;
   s->fe_beta = pin->mode == MTS_COUPLED ? pin->fe_beta : 0.0;
+  s->pd_beta = pin->pd_beta;
   derive_params(*s);
   DeviceArena &ar = s->arena;
   hipStream_t st = s->stream;
@@ -286,6 +290,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   build_neighbors(*s);
   vlog(*s, "neighbours: %lld nodes, %lld bonds, %d lanes per row", (long long)N, (long long)s->nnz, s->sell.L);
   pd_setup(*s);
+  pd_implicit_setup(*s);
   if (pin->mode == MTS_COUPLED) {
     fe_setup(*s);
     vlog(*s, "fe: %lld nodes, %lld elements", (long long)s->nfe, (long long)s->ne);
@@ -434,8 +439,11 @@ void advance_impl(Solver &s, int64_t n) {
       // the m substep launches run back to back; one event pair brackets them
       hipEvent_t e0 = nullptr;
       s.prof_begin(MTS_KT_PD_SUBSTEP, &e0);
-      if (!pd_subcycle(s))
+      if (s.pd_beta > 0.0) {
+        for (int j = 1; j <= s.m; j++) pd_implicit_step(s);
+      } else if (!pd_subcycle(s)) {
         for (int j = 1; j <= s.m; j++) pd_substep(s, j);
+      }
       s.prof_end(MTS_KT_PD_SUBSTEP, e0, s.m);
     }
     int slot = -1;
@@ -599,6 +607,7 @@ mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_by
       if (h->s.pinned_flag) (void)hipHostFree(h->s.pinned_flag);
       if (h->s.nf_event) (void)hipEventDestroy(h->s.nf_event);
       fe_implicit_free(h->s);
+      pd_implicit_free(h->s);
       h->s.arena.free_all();
       delete h;
     }
@@ -929,6 +938,7 @@ void mts_destroy(mts_solver *h) {
   if (s.nf_event) (void)hipEventDestroy(s.nf_event);
   if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
   fe_implicit_free(s);
+  pd_implicit_free(s);
   s.arena.free_all();
   delete h;
 }
