@@ -91,6 +91,9 @@ def _create_status(inst):
     dict(fe_beta=0.5),                               # only explicit or average acceleration
     dict(clamp_x0=True, vel_bc=1.0),                 # a clamped face moves with no velocity
     dict(mode="pure_pd", traction_x=1e6),            # end traction acts on the FE mesh
+    dict(pd_beta=0.25),                              # the implicit PD step runs in pure-PD mode only
+    dict(mode="pure_pd", pd_beta=0.25, precision="mixed"),  # ... and in FP64
+    dict(mode="pure_pd", pd_beta=0.5),               # only explicit or average acceleration
 ])
 def test_create_rejects_bad_descriptions_before_device_use(bad):
     """Degenerate or inconsistent descriptions are rejected with MTS_EINVAL by
