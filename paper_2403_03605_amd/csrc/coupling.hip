@@ -616,11 +616,14 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   int32_t *dnodes = nullptr;
   const int32_t *load_color = s.ccolor;
   const uint8_t *csel = nullptr;
+  // host sources of the copies below stay alive until the stream is synchronised
+  std::vector<int32_t> sub;
+  std::vector<uint8_t> cs;
   if (all) {
     MTS_HIP(hipMemsetAsync(s.H, 0, sizeof(double) * nl * nl, st));
   } else {
-    std::vector<int32_t> sub((size_t)s.nc, -1);
-    std::vector<uint8_t> cs((size_t)s.nc, 0);
+    sub.assign((size_t)s.nc, -1);
+    cs.assign((size_t)s.nc, 0);
     for (int32_t q : sel) {
       sub[q] = s.h_ccolor[q];
       cs[q] = 1;
