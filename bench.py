@@ -18,11 +18,13 @@ setup timed separately).  The same JSON line carries:
 - the bond pass's roofline (HBM bound) on two byte models and the counter
   traffic;
 - the crack-branching plate of the paper's Sec. 4.1, MTS against pure PD;
-- the per-step times of the efficiency study's plate (Table 2, the cases that
-  run the PD step explicitly), split as the paper splits them;
+- the per-step times of the efficiency study's plate (Table 2, every case but
+  the MTS model with the implicit PD step), split as the paper splits them;
 - the oracle's rate on the host's cores (one thread and all threads).
 
-Prints one JSON line.
+Prints one JSON line.  --serve, --branching and --glass-block (the 3D impact
+block in glass run to the end, with its rebuilds timed) each print a line of
+their own instead.
 """
 from __future__ import annotations
 
@@ -345,6 +347,51 @@ def branching_run(mts, torch, log):
     return out
 
 
+def glass_block_run(mts, torch, log, precision="mixed", n_macro=None):
+    """The 100 x 100 x 20 impact block in glass: the whole run (2000 PD
+    steps, m = 8; or its first n_macro macro steps) from a resident state,
+    with the rebuilds of the unit-load responses, H and its inverse that its
+    breaks trigger, timed by the library's rebuild event pairs."""
+    import mts_inputs as mi
+    inst = mi.config(3, precision=precision, material="glass",
+                     name=f"block 100x100x20 m=8 {precision} glass")
+    t0 = time.perf_counter()
+    s = mts.Solver(inst)
+    s.sync()
+    setup = time.perf_counter() - t0
+    n_macro = min(n_macro or inst["n_macro"], inst["n_macro"])
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, chunk = 0, 25
+    while done < n_macro:
+        k = min(chunk, n_macro - done)
+        s.advance(k)
+        s.sync()
+        done += k
+        log(f"glass block: {done}/{n_macro} macro steps, {time.perf_counter() - t0:.1f} s, "
+            f"{s.query()['n_rebuilds']} rebuilds")
+    run = time.perf_counter() - t0
+    info = s.query()
+    e = s.energy()
+    ph = {}
+    for name, kt in (("pd_substeps", mts.KT_PD_SUBSTEP), ("fe", mts.KT_FE), ("lambda", mts.KT_LAMBDA),
+                     ("link", mts.KT_LINK), ("rebuild", mts.KT_REBUILD)):
+        ph[name] = s.kernel_time(kt)[1]
+    s.profile(False)
+    s.close()
+    nr = info["n_rebuilds"]
+    rec = {"workload": inst["name"], "run_s": run, "setup_s": setup, "macro_steps": info["macro_steps"],
+           "pd_steps": info["pd_steps"], "pd_nodes": info["n_pd"], "bonds": info["nnz"], "broken": e["n_broken"],
+           "constraints": info["n_constraints"], "rebuilds": nr,
+           "rebuild_ms_total": ph["rebuild"], "ms_per_rebuild": ph["rebuild"] / nr if nr else None,
+           "rebuild_columns_fraction": (info["n_rebuild_columns"] / (nr * info["n_constraints"])) if nr else None,
+           "phases_ms_total": ph, "bond_updates_per_s": info["pd_steps"] * info["nnz"] / run}
+    log(f"glass block: {run:.1f} s, {nr} rebuilds at {rec['ms_per_rebuild'] or 0:.1f} ms, "
+        f"{e['n_broken']} of {info['nnz']} bonds broken")
+    return rec
+
+
 # the paper's Table 2 cases: (case, dx, PD area, m, PD Newmark beta); case 2
 # (MTS with the implicit PD step) is not run
 TABLE2_CASES = [(1, 5e-4, 1.0, 1, 0.25), (3, 5e-4, 0.2, 2, 0.0), (4, 5e-4, 0.1, 2, 0.0), (5, 5e-4, 0.1, 5, 0.0),
@@ -421,6 +468,8 @@ def main():
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     ap.add_argument("--serve", action="store_true", help="only run the serving stream (its own JSON line)")
     ap.add_argument("--branching", action="store_true", help="only run the crack-branching comparison (its own line)")
+    ap.add_argument("--glass-block", action="store_true",
+                    help="only run the 100x100x20 block in glass to the end, with its rebuilds (its own line)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
     ap.add_argument("--serve-budget-gib", type=float, default=0.0, help="pool budget (0: 90%% of free HBM)")
@@ -463,6 +512,15 @@ def main():
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "crack-branching plate 100 x 40 mm, dx 0.25 mm, 6e-5 s"},
             "branching": br}), flush=True)
+        return
+    if args.glass_block:
+        gb = glass_block_run(mts, torch, log, args.precision or "mixed", args.steps)
+        print(json.dumps({
+            "metric": "3D impact block in glass: run time to the end (s), rebuilds included",
+            "value": gb["run_s"], "unit": "s", "n_gpus": 1, "steps": gb["macro_steps"], "warmup": 0,
+            "ms_per_step": gb["run_s"] * 1e3 / gb["macro_steps"], "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if gb["workload"].endswith("fp64 glass") else "f32 bond math / f64 integration",
+            "data": "synthetic", "config": {"workload": gb["workload"]}, "glass_block": gb}), flush=True)
         return
     default_prec = "mixed" if args.config == 3 else "fp64"
     prec = args.precision or default_prec

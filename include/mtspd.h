@@ -147,7 +147,13 @@ enum {
 };
 
 /* Kernels that mts_kernel_time reports. */
-enum { MTS_KT_PD_SUBSTEP = 0, MTS_KT_LINK = 1, MTS_KT_FE = 2, MTS_KT_LAMBDA = 3, MTS_KT_COUNT = 4 };
+enum {
+  MTS_KT_PD_SUBSTEP = 0, MTS_KT_LINK = 1, MTS_KT_FE = 2, MTS_KT_LAMBDA = 3,
+  MTS_KT_REBUILD = 4, /* rebuilds of the unit-load responses, H and its inverse (Algorithm 1,
+                         update of Y): stream time from the rebuild's first to its last
+                         work, host waits inside it included */
+  MTS_KT_COUNT = 5
+};
 
 typedef struct mts_solver mts_solver;
 
@@ -234,7 +240,8 @@ mts_status mts_energy_noalloc(mts_solver *s, double *dev_out);
 /* HIP-event timing on the solver's stream while enabled.  MTS_KT_PD_SUBSTEP:
  * one event pair brackets the m back-to-back substep launches of a macro step
  * and *launches counts the substeps; the other groups count one launch group
- * (FE free step, multiplier solve, link re-run) per macro step. */
+ * (FE free step, multiplier solve, link re-run) per macro step, or one per
+ * rebuild (MTS_KT_REBUILD). */
 mts_status mts_profile(mts_solver *s, int32_t enable);
 mts_status mts_kernel_time(mts_solver *s, int32_t kernel, int64_t *launches, double *total_ms);
 

@@ -8,6 +8,6 @@ it has not been built.
 from ._lib import (  # noqa: F401
     COUPLED, PURE_PD, FP64, MIXED,
     PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, DAMAGE, LAMBDA, PD_ALPHA, PD_MASS, FE_MASS, FE_X,
-    CONSTRAINT_NODES, H, KT_PD_SUBSTEP, KT_LINK, KT_FE, KT_LAMBDA,
+    CONSTRAINT_NODES, H, KT_PD_SUBSTEP, KT_LINK, KT_FE, KT_LAMBDA, KT_REBUILD,
     REQ_ACTIVE, REQ_DONE, MtsError, Solver, Pool, load, plan, LIB_PATH, EXPORTS,
 )

@@ -15,7 +15,7 @@ COUPLED, PURE_PD = 0, 1
 FP64, MIXED = 0, 1
 PD_U, PD_V, PD_A, FE_U, FE_V, FE_A, DAMAGE, LAMBDA, PD_ALPHA, PD_MASS, FE_MASS, FE_X, \
     CONSTRAINT_NODES, H = range(14)
-KT_PD_SUBSTEP, KT_LINK, KT_FE, KT_LAMBDA = range(4)
+KT_PD_SUBSTEP, KT_LINK, KT_FE, KT_LAMBDA, KT_REBUILD = range(5)
 REQ_ACTIVE, REQ_DONE = 1, 2
 WEIGHT = {"cubic": 0, "linear": 1, "constant": 2}
 KERNEL = {"pmb": 0, "exp": 1}

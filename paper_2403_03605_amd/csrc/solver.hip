@@ -407,7 +407,10 @@ void resolve_pending(Solver &s) {
   }
   if (s.pinned_flag[slot]) {
     s.pinned_flag[slot] = 0;
+    hipEvent_t e0;
+    s.prof_begin(MTS_KT_REBUILD, &e0);
     coupling_rebuild(s, s.mask_snap[slot]);
+    s.prof_end(MTS_KT_REBUILD, e0);
     s.n_rebuilds++;
   }
 }
