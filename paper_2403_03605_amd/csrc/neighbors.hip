@@ -233,8 +233,9 @@ void build_neighbors(Solver &s) {
                   (void *)items, (void *)rowlen, (void *)rp64})
     ar.release(q);
 
-  // Rows of the bond layout in spatial tile order (32 x 8 nodes in 2D,
-  // 8 x 4 x 4 or 4 x 4 x 4 in 3D, ascending id inside a tile): a workgroup's
+  // Rows of the bond layout in spatial tile order (32 x 8 nodes in 2D, 32 x 16
+  // with eight-wavefront workgroups; 8 x 4 x 4 or 4 x 4 x 4 in 3D; ascending id
+  // inside a tile): a workgroup's
   // rows and their neighbours then form a compact patch, which keeps the
   // neighbour gathers of consecutive workgroups in the same L2 and the staged
   // neighbour lists short.
@@ -248,7 +249,7 @@ void build_neighbors(Solver &s) {
       for (int64_t i = 0; i < N; i++) lo[a] = std::min(lo[a], s.pos[(size_t)i * dim + a]);
     }
     // 3D tiles of 16 x halo_waves nodes: one workgroup at 4 lanes per row
-    const double ext2[3] = {32.0, 8.0, 1.0}, ext3[3] = {s.halo_waves == 8 ? 8.0 : 4.0, 4.0, 4.0};
+    const double ext2[3] = {32.0, s.halo_waves == 8 ? 16.0 : 8.0, 1.0}, ext3[3] = {s.halo_waves == 8 ? 8.0 : 4.0, 4.0, 4.0};
     const double *ext = dim == 2 ? ext2 : ext3;
     std::vector<int64_t> key(N);
     int64_t nt[3] = {1, 1, 1};

@@ -175,3 +175,26 @@ def test_nonfinite_state_detected_at_macro_step_end(mts):
         s.advance(1)             # surfaces here, without a sync
     assert e.value.status == 4
     s.close()
+
+
+def test_rebuild_timer_counts_every_rebuild(mts):
+    """mts_kernel_time(MTS_KT_REBUILD): one event pair per rebuild of the
+    unit-load responses and the inverse, none for the setup build, and the
+    per-step groups keep counting one per macro step."""
+    inst = mi.config(0)  # 50 x 20 plate, m = 4: the crack reaches the overlap within 50 macro steps
+    print("case", inst["name"], flush=True)
+    s = mts.Solver(inst)
+    s.profile(True)
+    s.advance(50)
+    s.sync()
+    n, ms = s.kernel_time(mts.KT_REBUILD)
+    q = s.query()
+    assert q["n_rebuilds"] > 0
+    assert n == q["n_rebuilds"] and ms > 0.0
+    n_l, _ = s.kernel_time(mts.KT_LAMBDA)
+    assert n_l == 50
+    s.profile(False)
+    assert s.kernel_time(mts.KT_REBUILD) == (0, 0.0)
+    with pytest.raises(mts.MtsError):
+        s.kernel_time(5)
+    s.close()
