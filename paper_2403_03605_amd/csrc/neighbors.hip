@@ -235,10 +235,9 @@ void build_neighbors(Solver &s) {
 
   // Rows of the bond layout in spatial tile order (32 x 8 nodes in 2D, 32 x 16
   // with eight-wavefront workgroups; 8 x 4 x 4 or 4 x 4 x 4 in 3D; ascending id
-  // inside a tile): a workgroup's
-  // rows and their neighbours then form a compact patch, which keeps the
-  // neighbour gathers of consecutive workgroups in the same L2 and the staged
-  // neighbour lists short.
+  // inside a tile): a workgroup's rows and their neighbours then form a compact
+  // patch, which keeps the neighbour gathers of consecutive workgroups in the
+  // same L2 and the staged neighbour lists short.
   if (s.halo_waves == 0) s.halo_waves = (dim == 3 && s.precision == MTS_MIXED) ? 8 : 4;
   std::vector<int32_t> rows(N);
   for (int64_t i = 0; i < N; i++) rows[i] = (int32_t)i;

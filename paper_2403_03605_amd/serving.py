@@ -39,6 +39,8 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
     lock = threading.Lock()
     errors = []
     work = [0.0] * n  # bond-updates of each request (directed slots x PD substeps)
+    rebuilds = [0] * n
+    submit_s = [0.0]  # builder time inside mts_pool_submit (all builders)
     t0 = time.perf_counter()
 
     next_k = [0]
@@ -58,7 +60,10 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
                 if delay > 0:
                     time.sleep(delay)
                 while True:
+                    ts = time.perf_counter()
                     rid = pool.submit(r["inst"], r["inst"]["n_macro"])
+                    with lock:
+                        submit_s[0] += time.perf_counter() - ts
                     if rid is not None:
                         break
                     freed.wait(0.005)
@@ -76,10 +81,13 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
         th.start()
     finished = 0
     steps = 0
+    step_s = 0.0  # host time inside mts_pool_step (it runs the rebuilds that the last step flagged)
     while finished < n:
         if errors:
             raise errors[0]
+        ts = time.perf_counter()
         na, done = pool.step()
+        step_s += time.perf_counter() - ts
         steps += 1
         for rid in done:
             while True:  # the admission thread registers the id right after submit returns
@@ -91,6 +99,7 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
             inst = requests[k]["inst"]
             npd = inst["pos"].shape[0]
             phi = pool.read(rid, _lib.DAMAGE, npd)
+            rebuilds[k] = pool.poll(rid)[2]["n_rebuilds"]
             t_done[k] = time.perf_counter() - t0
             if keep_results:
                 results[k] = {"damage": phi, "u": pool.read(rid, _lib.PD_U, npd * 2)}
@@ -116,6 +125,8 @@ def serve(requests: List[Dict], budget_bytes: int, *, max_slots: int = 64, use_g
         "admission_wait_p50_s": float(np.percentile(wait, 50)), "admission_wait_p99_s": float(np.percentile(wait, 99)),
         "bond_updates": total, "span_s": span, "bond_updates_per_s": total / span,
         "pool_steps": steps, "graph_captures": info["graph_captures"], "graph_replays": info["graph_replays"],
+        "rebuilds": int(sum(rebuilds)), "requests_with_rebuilds": int(sum(1 for x in rebuilds if x)),
+        "host_s_in_pool_step": step_s, "host_s_in_pool_submit": submit_s[0],
         "latencies_s": lat.tolist(),
     }
     if keep_results:
