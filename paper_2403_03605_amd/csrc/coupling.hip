@@ -240,14 +240,18 @@ __global__ __launch_bounds__(WAVE) void k_dirty_nodes(const int64_t *word_off, i
 
 // r = G_F v~_F - G_P V_m  (right-hand side of Eq. 49, from Eq. 41)
 __global__ void k_rhs(int64_t nc, int dim, int nen, const int32_t *cn, const int32_t *cel, const int32_t *conn,
-                      const double *cw, const double *vt, const double *vP, int64_t N, double *r) {
+                      const double *cw, const double *vt, const double *vP, int64_t N, double *r,
+                      const int32_t *rpos, double *r_blk) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
   int64_t e = cel[q];
   for (int d = 0; d < dim; d++) {
     double g = 0.0;
     for (int a = 0; a < nen; a++) g += cw[q * nen + a] * vt[(int64_t)conn[e * nen + a] * dim + d];
-    r[q * dim + d] = g - vP[d * N + cn[q]];
+    const double v = g - vP[d * N + cn[q]];
+    r[q * dim + d] = v;
+    const int32_t p = rpos[q * dim + d];  // the same entry in the multiplier solve's block order
+    if (p >= 0) r_blk[p] = v;
   }
 }
 
@@ -693,9 +697,10 @@ void coupling_lambda(Solver &s) {
   hipStream_t st = s.stream;
   hipEvent_t e0 = nullptr;
   s.prof_begin(MTS_KT_LAMBDA, &e0);
-  k_rhs<<<nb(s.nc), 256, 0, st>>>(s.nc, s.dim, s.nen, s.cn, s.cel, s.conn, s.cw, s.vt, s.v, s.N, s.rhs);
+  k_rhs<<<nb(s.nc), 256, 0, st>>>(s.nc, s.dim, s.nen, s.cn, s.cel, s.conn, s.cw, s.vt, s.v, s.N, s.rhs, s.sym.rpos,
+                                  s.sym.rperm);
   MTS_LAUNCH_CHECK();
-  sym_blocks_apply(s, s.rhs, s.lam, s.lam0);  // lambda_0 <- lambda_m for the next macro step too
+  sym_blocks_apply(s, s.rhs, s.sym.rperm, s.lam, s.lam0);  // lambda_0 <- lambda_m for the next macro step too
   s.prof_end(MTS_KT_LAMBDA, e0);
 }
 

@@ -444,10 +444,100 @@ __device__ __forceinline__ void load_pairs(const double *tile, bool f32, int q0,
   }
 }
 
-__global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, const int32_t *tile_meta,
-                                                   const int64_t *off, const int32_t *idx, const double *r,
-                                                   const int32_t *kept, const uint8_t *kept_f32,
-                                                   const int64_t *n_kept, double *rowpart, double *colpart) {
+// Row sums of quarter qt of a tile (rows 16 qt .. 16 qt + 15): p[q] holds
+// this lane's two-entry products of row 2 (8 qt + q) + h; recursive halving
+// over the 32 lanes of the half-wavefront, then one lane in four writes.
+__device__ __forceinline__ void sym_quarter_rows(const double p[8], int lane, int qt, double *row_tile) {
+  const int h = lane >> 5;
+  const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  double p4[4], p2[2];
+#pragma unroll
+  for (int kk = 0; kk < 4; kk++) p4[kk] = pick(b4, p[kk], p[4 + kk]) + __shfl_xor(pick(b4, p[4 + kk], p[kk]), 16, WAVE);
+#pragma unroll
+  for (int kk = 0; kk < 2; kk++) p2[kk] = pick(b3, p4[kk], p4[2 + kk]) + __shfl_xor(pick(b3, p4[2 + kk], p4[kk]), 8, WAVE);
+  double p1 = pick(b2, p2[0], p2[1]) + __shfl_xor(pick(b2, p2[1], p2[0]), 4, WAVE);
+  p1 += __shfl_xor(p1, 2, WAVE);
+  p1 += __shfl_xor(p1, 1, WAVE);
+  // the four lanes 4k .. 4k + 3 of the half hold row 2 (8 qt + k) + h, k = (lane % 32) / 4
+  if ((lane & 3) == 0) row_tile[2 * (8 * qt + ((lane & 31) >> 2)) + h] = p1;
+}
+
+// A kept tile's header, made wave-uniform, and this lane's x_I and x_J
+// entries (r in component-block order, zero-padded), staged in LDS.
+struct SymTile {
+  int64_t tile;
+  bool f32, offd;
+};
+
+__device__ __forceinline__ SymTile sym_tile_begin(const int4 &H, const double *r, int lane, double (*xs)[TS]) {
+  SymTile t;
+  t.tile = __builtin_amdgcn_readfirstlane(H.x);
+  const int rI = __builtin_amdgcn_readfirstlane(H.y), rJ = __builtin_amdgcn_readfirstlane(H.z);
+  const int flags = __builtin_amdgcn_readfirstlane(H.w);
+  t.f32 = (flags & 1) != 0;
+  t.offd = (flags & 2) != 0;
+  const double xi = r[rI + lane], xj = r[rJ + lane];
+  // the previous tile's reads of xs are done before it is rewritten
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  xs[0][lane] = xi;
+  xs[1][lane] = xj;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return t;
+}
+
+// Row partial A_IJ x_J and, off the diagonal, column partial A_IJ^T x_I of
+// every kept tile, one wavefront per tile.  Two forms with the same sums,
+// term by term: k_sym_tiles_all issues every load of a tile at once (two
+// wavefronts per SIMD), for solves with few tiles per wavefront, where a
+// tile's load latency is the cost; k_sym_tiles_stream takes quarters of 8
+// loads, the next requested while the current one is summed (four
+// wavefronts per SIMD; the tile is found through the kept list and the tile
+// table, and x is gathered in dof order), for solves that stream many tiles
+// per wavefront.
+__global__ __launch_bounds__(256, 2) void k_sym_tiles_all(const double *__restrict__ packed,
+                                                       const int4 *__restrict__ hdr, const double *__restrict__ r,
+                                                       const int64_t *__restrict__ n_kept,
+                                                       double *__restrict__ rowpart, double *__restrict__ colpart) {
+  const int64_t n_tiles = *n_kept;
+  __shared__ double xs[4][2][TS];  // per wavefront: x_I, x_J
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  const int h = lane >> 5, c0 = 2 * (lane & 31);
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t k = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + w)); k < n_tiles; k += stride) {
+    const int4 H = hdr[k];
+    const double *tp = packed + (int64_t)__builtin_amdgcn_readfirstlane(H.x) * TS * TS;
+    const bool f32 = (__builtin_amdgcn_readfirstlane(H.w) & 1) != 0;
+    double2 e[32];
+#pragma unroll
+    for (int qt = 0; qt < 4; qt++) load_pairs(tp, f32, 8 * qt, lane, &e[8 * qt]);
+    const SymTile t = sym_tile_begin(H, r, lane, xs[w]);
+    const double xj0 = xs[w][1][c0], xj1 = xs[w][1][c0 + 1];
+    double cs0 = 0.0, cs1 = 0.0;
+#pragma unroll
+    for (int qt = 0; qt < 4; qt++) {
+      double p[8];
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const double xr = xs[w][0][2 * (8 * qt + q) + h];
+        cs0 += e[8 * qt + q].x * xr;
+        cs1 += e[8 * qt + q].y * xr;
+        p[q] = e[8 * qt + q].x * xj0 + e[8 * qt + q].y * xj1;
+      }
+      sym_quarter_rows(p, lane, qt, rowpart + t.tile * TS);
+    }
+    cs0 += __shfl_xor(cs0, 32, WAVE);
+    cs1 += __shfl_xor(cs1, 32, WAVE);
+    if (t.offd && h == 0) *reinterpret_cast<double2 *>(colpart + t.tile * TS + c0) = double2{cs0, cs1};
+  }
+}
+
+__global__ __launch_bounds__(256, 4) void k_sym_tiles_stream(const double *packed, const int32_t *tile_meta,
+                                                          const int64_t *off, const int32_t *idx, const double *r,
+                                                          const int32_t *kept, const uint8_t *kept_f32,
+                                                          const int64_t *n_kept, double *rowpart, double *colpart) {
   const int64_t n_tiles = *n_kept;
   __shared__ double xs[4][2][TS];  // per wavefront: x_I, x_J
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
@@ -491,9 +581,11 @@ __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, cons
       // recursive halving over the 32 lanes of the half-wavefront
       double p4[4], p2[2];
 #pragma unroll
-      for (int k = 0; k < 4; k++) p4[k] = pick(b4, p[k], p[4 + k]) + __shfl_xor(pick(b4, p[4 + k], p[k]), 16, WAVE);
+      for (int kk = 0; kk < 4; kk++)
+        p4[kk] = pick(b4, p[kk], p[4 + kk]) + __shfl_xor(pick(b4, p[4 + kk], p[kk]), 16, WAVE);
 #pragma unroll
-      for (int k = 0; k < 2; k++) p2[k] = pick(b3, p4[k], p4[2 + k]) + __shfl_xor(pick(b3, p4[2 + k], p4[k]), 8, WAVE);
+      for (int kk = 0; kk < 2; kk++)
+        p2[kk] = pick(b3, p4[kk], p4[2 + kk]) + __shfl_xor(pick(b3, p4[2 + kk], p4[kk]), 8, WAVE);
       double p1 = pick(b2, p2[0], p2[1]) + __shfl_xor(pick(b2, p2[1], p2[0]), 4, WAVE);
       p1 += __shfl_xor(p1, 2, WAVE);
       p1 += __shfl_xor(p1, 1, WAVE);
@@ -506,11 +598,45 @@ __global__ __launch_bounds__(256, 4) void k_sym_tiles(const double *packed, cons
   }
 }
 
-// y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I).  One
-// workgroup per block row; wave w takes every kRedWaves-th contribution and the
-// wave sums are added in a fixed order.
+// y[idx[i]] = sum_{J <= I} rowpart(I, J) + sum_{J > I} colpart(J, I) over the
+// kept tiles of block row I.  One workgroup per block row; wave w takes the
+// terms with J = w mod kRedWaves, listed for it in ascending J, and the wave
+// sums are added in a fixed order.  (The skipped tiles' partial sums
+// are zero, and none of these sums is ever -0, so leaving them out changes no
+// bit.)
 constexpr int kRedWaves = 16;  // wavefronts per block row in the reduction
 
+__global__ __launch_bounds__(kRedWaves * 64) void k_sym_reduce_list(const int64_t *off, const int32_t *row_comp,
+                                                              const int32_t *row_block, const int32_t *idx,
+                                                              const int32_t *red_off, const int2 *red,
+                                                              const double *rowpart, const double *colpart,
+                                                              double *y, double *y2) {
+  __shared__ double part[kRedWaves][TS];
+  const int64_t c = row_comp[blockIdx.x], I = row_block[blockIdx.x];
+  const int64_t n = off[c + 1] - off[c];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x >> 6;
+  double s = 0.0;
+  const int e1 = red_off[blockIdx.x * kRedWaves + w + 1];
+  for (int e = red_off[blockIdx.x * kRedWaves + w]; e < e1; e++) {
+    const int2 E = red[e];
+    s += ((E.x & 1) ? colpart : rowpart)[(int64_t)(E.x >> 1) * TS + lane];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0) {
+    const int64_t i = I * TS + lane;
+    double tot = part[0][lane];
+    for (int q = 1; q < kRedWaves; q++) tot += part[q][lane];  // fixed order
+    if (i < n) {
+      y[idx[off[c] + i]] = tot;
+      if (y2) y2[idx[off[c] + i]] = tot;
+    }
+  }
+}
+
+// The same sums for the streaming solve, whose block rows keep most of
+// their tiles: wave w walks J = w, w + kRedWaves, .. directly (a skipped
+// tile's partial sum is zero).
 __global__ __launch_bounds__(kRedWaves * 64) void k_sym_reduce(const int64_t *off, const int64_t *tile_base,
                                                               const int32_t *row_comp, const int32_t *row_block,
                                                               const int32_t *idx, const double *rowpart,
@@ -588,6 +714,26 @@ void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps)
   B.n_rows = (int64_t)rc.size();
   B.row_comp = ar.alloc<int32_t>(rc.size());
   B.row_block = ar.alloc<int32_t>(rb.size());
+  // right-hand side in component-block order: dof h_idx[h_off[c] + p] sits at
+  // pbase[c] + p, component c padded with zeros to whole tiles
+  int64_t nr = 0, ndof = 0;
+  std::vector<int64_t> pbase(B.n_comp + 1, 0);
+  for (int64_t c = 0; c < B.n_comp; c++) {
+    pbase[c + 1] = pbase[c] + (B.h_off[c + 1] - B.h_off[c] + TS - 1) / TS * TS;
+    for (int64_t q = B.h_off[c]; q < B.h_off[c + 1]; q++) ndof = std::max<int64_t>(ndof, B.h_idx[q] + 1);
+  }
+  nr = pbase[B.n_comp];
+  std::vector<int32_t> rpos((size_t)std::max<int64_t>(ndof, s.nl), -1);
+  for (int64_t c = 0; c < B.n_comp; c++)
+    for (int64_t q = B.h_off[c]; q < B.h_off[c + 1]; q++) rpos[B.h_idx[q]] = (int32_t)(pbase[c] + q - B.h_off[c]);
+  B.rperm = ar.alloc<double>((size_t)std::max<int64_t>(nr, 1));
+  B.rpos = ar.alloc<int32_t>(rpos.size());
+  B.hdr = ar.alloc<int4>((size_t)std::max<int64_t>(B.n_tiles, 1));
+  B.red_off = ar.alloc<int32_t>((size_t)B.n_rows * kRedWaves + 1);
+  B.red = ar.alloc<int2>((size_t)std::max<int64_t>(2 * B.n_tiles, 1));
+  B.h_pbase = pbase;
+  MTS_HIP(hipMemsetAsync(B.rperm, 0, sizeof(double) * (size_t)std::max<int64_t>(nr, 1), st));
+  MTS_HIP(hipMemcpyAsync(B.rpos, rpos.data(), sizeof(int32_t) * rpos.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.row_comp, rc.data(), sizeof(int32_t) * rc.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.row_block, rb.data(), sizeof(int32_t) * rb.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.idx, B.h_idx.data(), sizeof(int32_t) * B.h_idx.size(), hipMemcpyHostToDevice, st));
@@ -684,6 +830,35 @@ void sym_blocks_prune(Solver &s) {
   }
   B.n_kept = (int64_t)kept.size();
   B.n_kept32 = (int64_t)to32.size();
+  {
+    // kept-tile headers, and per block row its kept partial sums in
+    // ascending block column (the zero partials of skipped tiles add nothing)
+    std::vector<int64_t> rowbase(B.n_comp + 1, 0);
+    for (int64_t c = 0; c < B.n_comp; c++)
+      rowbase[c + 1] = rowbase[c] + (B.h_off[c + 1] - B.h_off[c] + TS - 1) / TS;
+    std::vector<int4> hdr(kept.size());
+    // one list per block row and reduction wavefront (block column mod kRedWaves)
+    std::vector<std::vector<int2>> per_row((size_t)B.n_rows * kRedWaves);
+    for (size_t q = 0; q < kept.size(); q++) {
+      const int32_t t = kept[q];
+      const int32_t c = meta[(size_t)t * 3], I = meta[(size_t)t * 3 + 1], J = meta[(size_t)t * 3 + 2];
+      hdr[q] = int4{t, (int32_t)(B.h_pbase[c] + (int64_t)I * TS), (int32_t)(B.h_pbase[c] + (int64_t)J * TS),
+                    (f32[q] ? 1 : 0) | (I != J ? 2 : 0)};
+      per_row[(size_t)(rowbase[c] + I) * kRedWaves + J % kRedWaves].push_back(int2{t * 2, J});
+      if (I != J) per_row[(size_t)(rowbase[c] + J) * kRedWaves + I % kRedWaves].push_back(int2{t * 2 + 1, I});
+    }
+    std::vector<int32_t> roff(1, 0);
+    std::vector<int2> red;
+    for (auto &v : per_row) {
+      std::sort(v.begin(), v.end(), [](const int2 &a, const int2 &b) { return a.y < b.y; });
+      red.insert(red.end(), v.begin(), v.end());
+      roff.push_back((int32_t)red.size());
+    }
+    MTS_HIP(hipMemcpyAsync(B.hdr, hdr.data(), sizeof(int4) * hdr.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemcpyAsync(B.red_off, roff.data(), sizeof(int32_t) * roff.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipMemcpyAsync(B.red, red.data(), sizeof(int2) * red.size(), hipMemcpyHostToDevice, st));
+    MTS_HIP(hipStreamSynchronize(st));  // before the host vectors go away
+  }
   if (!B.kept_f32) B.kept_f32 = s.arena.alloc<uint8_t>((size_t)B.n_tiles);
   MTS_HIP(hipMemcpyAsync(B.kept, kept.data(), sizeof(int32_t) * kept.size(), hipMemcpyHostToDevice, st));
   MTS_HIP(hipMemcpyAsync(B.kept_f32, f32.data(), f32.size(), hipMemcpyHostToDevice, st));
@@ -704,17 +879,32 @@ void sym_blocks_prune(Solver &s) {
        (long long)B.n_tiles, (long long)B.n_kept32);
 }
 
-void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2) {
+// Kept tiles up to which a solve issues every load of a tile at once and
+// reduces over lists of its kept tiles (about two tiles per resident
+// wavefront: 2048 at two per SIMD on 256 CUs); above it the solve streams
+// quarters of tiles and reduces over every tile of a block row.  Both forms
+// give the same bits for any count, so a solve captured in a graph stays
+// valid when a rebuild moves the count across this bound.
+constexpr int64_t kSymFullTiles = 4096;
+
+void sym_blocks_apply(Solver &s, const double *r_dof, const double *r_blk, double *y, double *y2) {
   auto &B = s.sym;
   if (!B.n_tiles) return;
   // four tiles per workgroup at a time; up to eight resident workgroups per CU
   // the grid covers every tile; the count of kept tiles is read on the device
   const unsigned g = (unsigned)std::min<int64_t>((B.n_tiles + 3) / 4, 256 * 8);
-  k_sym_tiles<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r, B.kept, B.kept_f32, B.n_kept_dev,
-                                       B.rowpart, B.colpart);
-  MTS_LAUNCH_CHECK();
-  k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block, B.idx,
-                                                        B.rowpart, B.colpart, y, y2);
+  if (B.n_kept <= kSymFullTiles) {
+    k_sym_tiles_all<<<g, 256, 0, s.stream>>>(B.packed, B.hdr, r_blk, B.n_kept_dev, B.rowpart, B.colpart);
+    MTS_LAUNCH_CHECK();
+    k_sym_reduce_list<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(
+        B.off, B.row_comp, B.row_block, B.idx, B.red_off, B.red, B.rowpart, B.colpart, y, y2);
+  } else {
+    k_sym_tiles_stream<<<g, 256, 0, s.stream>>>(B.packed, B.tile_meta, B.off, B.idx, r_dof, B.kept, B.kept_f32,
+                                                B.n_kept_dev, B.rowpart, B.colpart);
+    MTS_LAUNCH_CHECK();
+    k_sym_reduce<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(B.off, B.tile_base, B.row_comp, B.row_block,
+                                                                      B.idx, B.rowpart, B.colpart, y, y2);
+  }
   MTS_LAUNCH_CHECK();
 }
 

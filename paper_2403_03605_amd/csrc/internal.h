@@ -258,6 +258,17 @@ struct Solver {
     uint8_t *kept_f32 = nullptr;    // per kept entry: 1 if stored in FP32
     int64_t n_kept32 = 0;
     bool prune = true;
+    // the multiplier solve's right-hand side in component-block order (each
+    // component padded with zeros to whole tiles), every dof's position in it,
+    // a header per kept tile, and per block row the partial sums of its kept
+    // tiles (ascending block column); sized for every tile at setup, so a
+    // rebuild rewrites them in place
+    double *rperm = nullptr;
+    int32_t *rpos = nullptr;
+    int4 *hdr = nullptr;        // per kept tile: {tile, rI, rJ, flags (1: FP32, 2: off the diagonal)}
+    int32_t *red_off = nullptr; // per block row and reduction wavefront: first entry of red
+    int2 *red = nullptr;        // {tile << 1 | (1: column partial), block column}
+    std::vector<int64_t> h_pbase;  // per component: first entry in rperm (n_comp + 1)
   } sym;
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;
@@ -374,7 +385,9 @@ enum { kSideNone = 0, kSideRing = 1, kSideElem = 2, kSideGather = 3, kSideSnap =
 // dense linear algebra (dense.hip)
 void sym_blocks_setup(Solver &s, const std::vector<std::vector<int32_t>> &comps);
 void sym_blocks_build(Solver &s);
-void sym_blocks_apply(Solver &s, const double *r, double *y, double *y2 = nullptr);
+// y (and y2) <- H^-1 r, r given in dof order and in component-block order
+// (sym.rperm's layout); each form of the solve reads the layout it needs
+void sym_blocks_apply(Solver &s, const double *r_dof, const double *r_blk, double *y, double *y2 = nullptr);
 void sym_blocks_prune(Solver &s);  // the tiles the solve reads
 // solver construction and helpers shared with the serving pool (solver.hip)
 void create_impl(const mts_problem *pin, void *stream, Solver *s);

@@ -565,7 +565,8 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
     if (p->mode == MTS_COUPLED) {
       const int64_t T = (nl + 63) / 64, tiles = T * (T + 1) / 2;
       bytes += nl * nl * 8 * (nl <= 4096 ? 2 : 1);   // H (and its copy, when kept)
-      bytes += tiles * (64 * 64 * 8 + 2 * 64 * 8);    // packed inverse, GEMV partial sums
+      bytes += tiles * (64 * 64 * 8 + 2 * 64 * 8 + 32);  // packed inverse, GEMV partial sums, tile lists
+      bytes += T * 64 * 8 + nl * 12 + T * 64;         // right-hand side in both orders, the map, reduction lists
       bytes += 2 * T * 64 * 256 * 8 + 256 * 256 * 8 + 64 * 64 * 8;  // sweep panels and pivot blocks
       bytes += 4 * rhs * d * p->n_pd * 8 + 2 * 2 * d * p->n_pd * 8;  // link responses, final-update records
       bytes += slots * 40;                            // link region layout (at most every slot)
