@@ -893,7 +893,7 @@ void sym_blocks_apply(Solver &s, const double *r_dof, const double *r_blk, doubl
   // four tiles per workgroup at a time; up to eight resident workgroups per CU
   // the grid covers every tile; the count of kept tiles is read on the device
   const unsigned g = (unsigned)std::min<int64_t>((B.n_tiles + 3) / 4, 256 * 8);
-  if (B.n_kept <= kSymFullTiles) {
+  if (B.form == 1 || (B.form == 0 && B.n_kept <= kSymFullTiles)) {
     k_sym_tiles_all<<<g, 256, 0, s.stream>>>(B.packed, B.hdr, r_blk, B.n_kept_dev, B.rowpart, B.colpart);
     MTS_LAUNCH_CHECK();
     k_sym_reduce_list<<<(unsigned)B.n_rows, kRedWaves * 64, 0, s.stream>>>(

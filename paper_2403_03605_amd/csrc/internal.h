@@ -269,6 +269,7 @@ struct Solver {
     int32_t *red_off = nullptr; // per block row and reduction wavefront: first entry of red
     int2 *red = nullptr;        // {tile << 1 | (1: column partial), block column}
     std::vector<int64_t> h_pbase;  // per component: first entry in rperm (n_comp + 1)
+    int form = 0;                  // solve form: 0 by the kept-tile count, 1 all loads at once, 2 streaming
   } sym;
   std::vector<int32_t> h_cn;
   int64_t n_region = 0;

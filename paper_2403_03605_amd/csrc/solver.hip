@@ -235,6 +235,7 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   if (const char *t = std::getenv("MTS_SUBCYCLE")) s->subcycle = std::atoi(t) != 0;  // one launch per macro step
   if (const char *t = std::getenv("MTS_INV_DROP")) s->sym.prune = std::atoi(t) != 0;  // tests: read every tile
   if (const char *t = std::getenv("MTS_FULL_REBUILD")) s->incremental = std::atoi(t) == 0;  // tests: every column
+  if (const char *t = std::getenv("MTS_SYM_FORM")) s->sym.form = std::min(std::max(std::atoi(t), 0), 2);  // tests
   if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass

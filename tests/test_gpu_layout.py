@@ -23,7 +23,8 @@ def mts():
     return m
 
 
-KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT", "MTS_SUBCYCLE", "MTS_SPIN_LIMIT")
+KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT", "MTS_SUBCYCLE", "MTS_SPIN_LIMIT",
+         "MTS_SYM_FORM")
 
 
 def _run(mts, inst, n_macro, env):
@@ -224,4 +225,17 @@ def test_incremental_rebuild_bit_identical(mts, inst):
     print(f"  rebuilds {na}, columns recomputed {ca} of {nb * nc}", flush=True)
     assert na == nb and na > 0
     assert cb == nb * nc and 0 < ca <= cb
+    _same(a, b)
+
+
+@pytest.mark.parametrize("inst", _rebuild_cases(), ids=lambda i: i["name"])
+def test_multiplier_solve_forms_bit_identical(mts, inst):
+    """The multiplier solve's two forms (every load of a tile at once with
+    per-wavefront lists of kept partial sums, MTS_SYM_FORM=1; quarters of a
+    tile streamed with a reduction over every tile, MTS_SYM_FORM=2) give the
+    same bits, through rebuilds of the unit-load responses and the inverse."""
+    print("case", inst["name"], flush=True)
+    a, nb = _run(mts, inst, inst["n_macro"], {"MTS_SYM_FORM": "1"})
+    b, _ = _run(mts, inst, inst["n_macro"], {"MTS_SYM_FORM": "2"})
+    assert nb > 0
     _same(a, b)
