@@ -461,7 +461,24 @@ void coupling_setup(Solver &s) {
   s.Wu[1] = ar.alloc<double>(wsz);
   s.Wv = ar.alloc<double>(wsz);
   s.Wa = ar.alloc<double>(wsz);
+  // responses stay exact zeros outside the link region (rows there are read
+  // as neighbours and never written)
   for (double *q : {s.Wu[0], s.Wu[1], s.Wv, s.Wa}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
+  for (auto &B : s.bset) {
+    B.u[0] = ar.alloc<double>(wsz);
+    B.u[1] = ar.alloc<double>(wsz);
+    B.v = ar.alloc<double>(wsz);
+    B.a = ar.alloc<double>(wsz);
+    B.layer = ar.alloc<int32_t>(std::max<int64_t>(s.rsell.n_slices, 1));
+    for (double *q : {B.u[0], B.u[1], B.v, B.a}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
+  }
+  if (!s.bfork) {
+    MTS_HIP(hipEventCreateWithFlags(&s.bfork, hipEventDisableTiming));
+    for (int q = 0; q < Solver::kBuildStreams - 1; q++) {
+      MTS_HIP(hipStreamCreateWithFlags(&s.bstream[q], hipStreamNonBlocking));  // default priority
+      MTS_HIP(hipEventCreateWithFlags(&s.bjoin[q], hipEventDisableTiming));
+    }
+  }
   for (int k = 0; k < 2; k++) s.Wxu[k] = ar.alloc<double>((size_t)2 * dim * N);
   link_records_init(s);
   s.lam = ar.alloc<double>(s.nl);
@@ -642,25 +659,52 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     k_zero_cols<<<nb(nl * nl), 256, 0, st>>>(nl, dim, csel, s.H);
     MTS_LAUNCH_CHECK();
   }
+  // the batches are independent: each has its own right-hand sides, writes
+  // only its own constraints' columns of H, and runs on stream bt mod
+  // kBuildStreams with that stream's buffers (forked from and joined into st)
+  const int nst = (int)std::min<int64_t>(s.build_streams, std::max<int64_t>(nbatch, 1));
+  if (nst > 1) {
+    MTS_HIP(hipEventRecord(s.bfork, st));
+    for (int q = 0; q < nst - 1; q++) MTS_HIP(hipStreamWaitEvent(s.bstream[q], s.bfork, 0));
+  }
+  struct StreamBack {  // s.stream is the launch stream of link_substep
+    Solver &s;
+    hipStream_t st;
+    ~StreamBack() { s.stream = st; }
+  } back{s, st};
   for (int64_t bt = 0; bt < nbatch; bt++) {
+    const int q = (int)(bt % nst);
+    hipStream_t sq = q ? s.bstream[q - 1] : st;
+    double *const u0 = q ? s.bset[q - 1].u[0] : s.Wu[0], *const u1 = q ? s.bset[q - 1].u[1] : s.Wu[1];
+    double *const wv = q ? s.bset[q - 1].v : s.Wv, *const wa = q ? s.bset[q - 1].a : s.Wa;
+    int32_t *const layer = q ? s.bset[q - 1].layer : s.batch_layer;
     const int32_t *rc = &rcd[bt * 32], *rd = &rcd[bt * 32 + 16];
     if (s.rsell.n_slices) {
       const int32_t *bn = all ? s.batch_nodes + s.h_batch_off[bt] : dnodes + boff[bt];
       const int32_t nbn = all ? s.h_batch_off[bt + 1] - s.h_batch_off[bt] : boff[bt + 1] - boff[bt];
-      k_batch_layer<<<(unsigned)s.rsell.n_slices, WAVE, 0, st>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
+      k_batch_layer<<<(unsigned)s.rsell.n_slices, WAVE, 0, sq>>>(s.x, s.N, dim, s.rsell.rows, s.rsell.n_rows,
                                                                  s.rsell.n_slices, s.rsell.L, bn, nbn, s.prm.delta,
-                                                                 s.m, s.batch_layer);
+                                                                 s.m, layer);
       MTS_LAUNCH_CHECK();
     }
+    s.stream = sq;
     int k = 0;  // substep 1 starts every response from rest, so no clearing is needed
+    const double *uk[2] = {u0, u1};
+    double *uw[2] = {u0, u1};
     for (int j = 1; j <= s.m; j++) {
-      link_substep(s, j, s.Wu[k], s.Wu[k ^ 1], s.Wv, s.Wa, load_color, rc, rd, s.nrhs, s.batch_layer);
+      link_substep(s, j, uk[k], uw[k ^ 1], wv, wa, load_color, rc, rd, s.nrhs, layer);
       k ^= 1;
     }
-    k_extract<<<nb(s.nc), 256, 0, st>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drcd + bt * 32, drcd + bt * 32 + 16,
-                                        s.Wv, csel, s.H);
+    s.stream = st;
+    k_extract<<<nb(s.nc), 256, 0, sq>>>(s.nc, dim, nl, s.nrhs, s.cn, s.owner, drcd + bt * 32, drcd + bt * 32 + 16,
+                                        wv, csel, s.H);
     MTS_LAUNCH_CHECK();
   }
+  if (nst > 1)
+    for (int q = 0; q < nst - 1; q++) {
+      MTS_HIP(hipEventRecord(s.bjoin[q], s.bstream[q]));
+      MTS_HIP(hipStreamWaitEvent(st, s.bjoin[q], 0));
+    }
   if (s.fe_beta > 0.0) {
     k_add_dense<<<nb(nl * nl), 256, 0, st>>>(nl * nl, nl, dim, csel, s.fe_HF, s.H);
   } else {
@@ -685,6 +729,20 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
   sym_blocks_build(s);
   MTS_HIP(hipStreamSynchronize(st));
   vlog(s, "coupling: H inverted");
+}
+
+void coupling_free(Solver &s) {
+  for (int q = 0; q < Solver::kBuildStreams - 1; q++) {
+    if (s.bstream[q]) {
+      (void)hipStreamSynchronize(s.bstream[q]);
+      (void)hipStreamDestroy(s.bstream[q]);
+    }
+    if (s.bjoin[q]) (void)hipEventDestroy(s.bjoin[q]);
+    s.bstream[q] = nullptr;
+    s.bjoin[q] = nullptr;
+  }
+  if (s.bfork) (void)hipEventDestroy(s.bfork);
+  s.bfork = nullptr;
 }
 
 bool coupling_solve_and_correct(Solver &s, bool fuse_next_fe, int snap_slot) {

@@ -283,6 +283,17 @@ struct Solver {
   std::vector<int32_t> h_batch_off;  // per batch of unit loads: range of batch_nodes
   int32_t *batch_nodes = nullptr;    // PD node ids of the constraints loaded by each batch
   int32_t *batch_layer = nullptr;    // per link-region slice: layer w.r.t. the current batch's loads
+  // further response buffers and streams of a build: its colour batches run
+  // on kBuildStreams streams at once (batch b on stream b mod kBuildStreams,
+  // with buffer set b mod kBuildStreams; set 0 is Wu, Wv, Wa, batch_layer)
+  static constexpr int kBuildStreams = 4;
+  struct BuildSet {
+    double *u[2] = {nullptr, nullptr}, *v = nullptr, *a = nullptr;
+    int32_t *layer = nullptr;
+  } bset[kBuildStreams - 1];
+  hipStream_t bstream[kBuildStreams - 1] = {};
+  hipEvent_t bfork = nullptr, bjoin[kBuildStreams - 1] = {};
+  int build_streams = kBuildStreams;
   // rebuilds recompute only the columns whose response support holds a node
   // with a bond changed since the last build (the rest are unchanged bit for bit)
   bool incremental = true;
@@ -374,6 +385,7 @@ void pd_implicit_free(Solver &s);
 // coupling (coupling.hip)
 void coupling_setup(Solver &s);
 void coupling_rebuild(Solver &s, const uint64_t *full_mask);
+void coupling_free(Solver &s);  // the build streams and events (memory is the arena's)
 // fuse_next_fe: the next macro step's FE free step rides in the link
 // launches (its kernels are independent of them); returns whether it did
 // snap_slot >= 0: also save this macro step's bond states into that slot and

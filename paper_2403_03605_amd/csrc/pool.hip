@@ -53,6 +53,7 @@ void destroy_solver(Solver *s) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->nf_event) (void)hipEventDestroy(s->nf_event);
+  coupling_free(*s);
   fe_implicit_free(*s);
   pd_implicit_free(*s);
   if (s->pinned_flag) (void)hipHostFree(s->pinned_flag);

@@ -236,6 +236,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   if (const char *t = std::getenv("MTS_INV_DROP")) s->sym.prune = std::atoi(t) != 0;  // tests: read every tile
   if (const char *t = std::getenv("MTS_FULL_REBUILD")) s->incremental = std::atoi(t) == 0;  // tests: every column
   if (const char *t = std::getenv("MTS_SYM_FORM")) s->sym.form = std::min(std::max(std::atoi(t), 0), 2);  // tests
+  if (const char *t = std::getenv("MTS_BUILD_STREAMS"))  // tests: streams of a build's colour batches
+    s->build_streams = std::min(std::max(std::atoi(t), 1), Solver::kBuildStreams);
   if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
@@ -569,7 +571,8 @@ mts_status mts_plan(const mts_problem *p, mts_plan_info *out) {
       bytes += tiles * (64 * 64 * 8 + 2 * 64 * 8 + 32);  // packed inverse, GEMV partial sums, tile lists
       bytes += T * 64 * 8 + nl * 12 + T * 64;         // right-hand side in both orders, the map, reduction lists
       bytes += 2 * T * 64 * 256 * 8 + 256 * 256 * 8 + 64 * 64 * 8;  // sweep panels and pivot blocks
-      bytes += 4 * rhs * d * p->n_pd * 8 + 2 * 2 * d * p->n_pd * 8;  // link responses, final-update records
+      // link responses (one set per build stream), final-update records
+      bytes += Solver::kBuildStreams * (4 * rhs * d * p->n_pd * 8 + p->n_pd * 4) + 2 * 2 * d * p->n_pd * 8;
       bytes += slots * 40;                            // link region layout (at most every slot)
       bytes += ne * 8 * 8 * 8 + nfe * 8 * 24 + nc * 64 * 8;  // FE mesh and state, coupling tables
       bytes += slots / 8 + p->n_pd + nc * 8;          // last build's bond states, changed-node and column flags
@@ -611,6 +614,7 @@ mts_status mts_create_in(const mts_problem *p, void *dev_arena, int64_t arena_by
       (void)hipGetLastError();
       if (h->s.pinned_flag) (void)hipHostFree(h->s.pinned_flag);
       if (h->s.nf_event) (void)hipEventDestroy(h->s.nf_event);
+      coupling_free(h->s);
       fe_implicit_free(h->s);
       pd_implicit_free(h->s);
       h->s.arena.free_all();
@@ -942,6 +946,7 @@ void mts_destroy(mts_solver *h) {
     if (e) (void)hipEventDestroy(e);
   if (s.nf_event) (void)hipEventDestroy(s.nf_event);
   if (s.pinned_flag) (void)hipHostFree(s.pinned_flag);
+  coupling_free(s);
   fe_implicit_free(s);
   pd_implicit_free(s);
   s.arena.free_all();

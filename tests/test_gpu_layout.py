@@ -24,7 +24,7 @@ def mts():
 
 
 KNOBS = ("MTS_LANES", "MTS_HALO", "MTS_HALO_WAVES", "MTS_TILE", "MTS_PD_VARIANT", "MTS_SUBCYCLE", "MTS_SPIN_LIMIT",
-         "MTS_SYM_FORM")
+         "MTS_SYM_FORM", "MTS_BUILD_STREAMS")
 
 
 def _run(mts, inst, n_macro, env):
@@ -237,5 +237,17 @@ def test_multiplier_solve_forms_bit_identical(mts, inst):
     print("case", inst["name"], flush=True)
     a, nb = _run(mts, inst, inst["n_macro"], {"MTS_SYM_FORM": "1"})
     b, _ = _run(mts, inst, inst["n_macro"], {"MTS_SYM_FORM": "2"})
+    assert nb > 0
+    _same(a, b)
+
+
+@pytest.mark.parametrize("inst", _rebuild_cases(), ids=lambda i: i["name"])
+def test_build_streams_bit_identical(mts, inst):
+    """The colour batches of a build (setup and every rebuild) run on four
+    streams at once, each batch with its own response buffers and its own
+    columns of H; one stream (MTS_BUILD_STREAMS=1) gives the same bits."""
+    print("case", inst["name"], flush=True)
+    a, nb = _run(mts, inst, inst["n_macro"], {"MTS_BUILD_STREAMS": "1"})
+    b, _ = _run(mts, inst, inst["n_macro"], {"MTS_BUILD_STREAMS": "4"})
     assert nb > 0
     _same(a, b)
