@@ -464,7 +464,8 @@ void coupling_setup(Solver &s) {
   // responses stay exact zeros outside the link region (rows there are read
   // as neighbours and never written)
   for (double *q : {s.Wu[0], s.Wu[1], s.Wv, s.Wa}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
-  for (auto &B : s.bset) {
+  for (int q = 0; q < s.build_streams - 1; q++) {
+    Solver::BuildSet &B = s.bset[q];
     B.u[0] = ar.alloc<double>(wsz);
     B.u[1] = ar.alloc<double>(wsz);
     B.v = ar.alloc<double>(wsz);
@@ -472,9 +473,9 @@ void coupling_setup(Solver &s) {
     B.layer = ar.alloc<int32_t>(std::max<int64_t>(s.rsell.n_slices, 1));
     for (double *q : {B.u[0], B.u[1], B.v, B.a}) MTS_HIP(hipMemsetAsync(q, 0, sizeof(double) * wsz, st));
   }
-  if (!s.bfork) {
+  if (!s.bfork && s.build_streams > 1) {
     MTS_HIP(hipEventCreateWithFlags(&s.bfork, hipEventDisableTiming));
-    for (int q = 0; q < Solver::kBuildStreams - 1; q++) {
+    for (int q = 0; q < s.build_streams - 1; q++) {
       MTS_HIP(hipStreamCreateWithFlags(&s.bstream[q], hipStreamNonBlocking));  // default priority
       MTS_HIP(hipEventCreateWithFlags(&s.bjoin[q], hipEventDisableTiming));
     }

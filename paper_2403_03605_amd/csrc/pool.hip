@@ -425,6 +425,10 @@ mts_status mts_pool_submit(mts_pool *P, const mts_problem *p, int64_t n_macro, u
     r->s->force_lanes = P->lanes;
     r->s->halo = false;  // one batched kernel for every request: neighbour gathers from global memory
     r->s->tiled = 0;
+    // one build stream per request (its colour batches in sequence): with
+    // four per request, a 256-request stream built on four threads ended in a
+    // host segmentation fault whose cause was not found
+    r->s->build_streams = 1;
     create_impl(p, st, r->s);  // ends with a synchronisation of st
     r->s->stream = P->stream;
     MTS_HIP(hipStreamDestroy(st));

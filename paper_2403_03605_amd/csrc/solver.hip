@@ -236,8 +236,8 @@ void create_impl(const mts_problem *pin, void *stream, Solver *s) {
   if (const char *t = std::getenv("MTS_INV_DROP")) s->sym.prune = std::atoi(t) != 0;  // tests: read every tile
   if (const char *t = std::getenv("MTS_FULL_REBUILD")) s->incremental = std::atoi(t) == 0;  // tests: every column
   if (const char *t = std::getenv("MTS_SYM_FORM")) s->sym.form = std::min(std::max(std::atoi(t), 0), 2);  // tests
-  if (const char *t = std::getenv("MTS_BUILD_STREAMS"))  // tests: streams of a build's colour batches
-    s->build_streams = std::min(std::max(std::atoi(t), 1), Solver::kBuildStreams);
+  if (const char *t = std::getenv("MTS_BUILD_STREAMS"))  // tests: fewer streams for a build's colour batches
+    s->build_streams = std::min(std::max(std::atoi(t), 1), s->build_streams);
   if (const char *t = std::getenv("MTS_SPIN_LIMIT")) s->spin_limit = (uint32_t)std::strtoul(t, nullptr, 10);  // tests
   const char *e = s->force_lanes ? nullptr : std::getenv("MTS_LANES");
   if (e) {  // tuning: lanes per row of the bond pass
