@@ -661,8 +661,9 @@ void coupling_rebuild(Solver &s, const uint64_t *full_mask) {
     MTS_LAUNCH_CHECK();
   }
   // the batches are independent: each has its own right-hand sides, writes
-  // only its own constraints' columns of H, and runs on stream bt mod
-  // kBuildStreams with that stream's buffers (forked from and joined into st)
+  // only its own constraints' columns of H, and runs on stream bt mod nst
+  // (the solver's build streams) with that stream's buffers, forked from and
+  // joined into st
   const int nst = (int)std::min<int64_t>(s.build_streams, std::max<int64_t>(nbatch, 1));
   if (nst > 1) {
     MTS_HIP(hipEventRecord(s.bfork, st));
